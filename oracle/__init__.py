@@ -1,0 +1,148 @@
+"""CPU FP64 oracle for the deconvolution solve -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The GPU library never calls it and
+shares no code with it.
+
+``gd_oracle.c`` holds the filter and the four solvers (Algorithms 1-4 of the
+paper) as plain scalar loops; this module loads it with ctypes and marshals
+numpy arrays.  ``cnn.py`` holds the FP64 reference for the warm-start network.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+SOLVERS = {"vc": 0, "cg": 1, "bicgstab": 2, "sd": 3}
+INITS = {"ubar": 0, "zero": 1, "given": 2}
+NORM_REFS = {"r0ubar": 0, "ubar": 1}
+STATUS = {0: "CONVERGED", 1: "MAXITER", 2: "BREAKDOWN_RHO", 3: "BREAKDOWN_OMEGA", 4: "NONFINITE", 5: "ZERO_REF"}
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                               "-std=c11", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("r_ref", ctypes.c_double),
+                ("r0", ctypes.c_double), ("r_final", ctypes.c_double), ("r_true", ctypes.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.or_filter.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp, dp]
+        lib.or_filter.restype = None
+        lib.or_dot.argtypes = [dp, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_int]
+        lib.or_dot.restype = ctypes.c_double
+        lib.or_solve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_double, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, dp, ctypes.POINTER(_Info)]
+        lib.or_solve.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _grid(shape, ndim):
+    g = tuple(shape[-ndim:])
+    if ndim == 2:
+        ny, nx = g
+        return nx, ny, 1
+    nz, ny, nx = g
+    return nx, ny, nz
+
+
+def spacing_weight(shape, ndim, h=None):
+    """h^d for the inner product; h_d = 2*pi/n_d by default (domain [0,2pi]^d)."""
+    nx, ny, nz = _grid(shape, ndim)
+    if h is None:
+        hs = [2 * math.pi / nx, 2 * math.pi / ny] + ([2 * math.pi / nz] if ndim == 3 else [])
+    else:
+        hs = list(h)[:ndim]
+    w = 1.0
+    for v in hs:
+        w *= v
+    return w
+
+
+def filter(x: np.ndarray, ndim: int) -> np.ndarray:
+    """y = G x for every field in the leading (batch) dimensions of x."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    nx, ny, nz = _grid(x.shape, ndim)
+    npts = nx * ny * nz
+    flat = x.reshape(-1, npts)
+    out = np.empty_like(flat)
+    for b in range(flat.shape[0]):
+        xb = np.ascontiguousarray(flat[b])
+        yb = np.empty_like(xb)
+        lib.or_filter(ndim, nx, ny, nz, _ptr(xb), _ptr(yb))
+        out[b] = yb
+    return out.reshape(x.shape)
+
+
+def dot(a: np.ndarray, b: np.ndarray, hw: float, sum_mode: int = 0) -> float:
+    lib = _load()
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
+    return float(lib.or_dot(_ptr(a), _ptr(b), a.size, hw, sum_mode))
+
+
+def solve(solver: str, ubar: np.ndarray, ndim: int, max_iter: int, tol: float = 0.0, init: str = "ubar",
+          u0: np.ndarray | None = None, norm_ref: str = "r0ubar", h=None, sum_mode: int = 0):
+    """Run one of Algorithms 1-4 on every field of ``ubar`` (leading dims = batch).
+
+    Returns (u, infos, hist): u like ubar; infos a list of dicts; hist an array
+    (batch, max_iter+1) of ||r_k|| with NaN past the last pass.
+    """
+    lib = _load()
+    ubar = np.ascontiguousarray(ubar, dtype=np.float64)
+    nx, ny, nz = _grid(ubar.shape, ndim)
+    npts = nx * ny * nz
+    hw = spacing_weight(ubar.shape, ndim, h)
+    flat = ubar.reshape(-1, npts)
+    B = flat.shape[0]
+    u = np.zeros_like(flat)
+    if init == "given":
+        if u0 is None:
+            raise ValueError("init='given' needs u0")
+        u[:] = np.asarray(u0, dtype=np.float64).reshape(B, npts)
+    hist = np.full((B, max_iter + 1), np.nan)
+    infos = []
+    for b in range(B):
+        ub = np.ascontiguousarray(flat[b])
+        uo = np.ascontiguousarray(u[b])
+        hb = np.full(max_iter + 1, np.nan)
+        info = _Info()
+        rc = lib.or_solve(SOLVERS[solver], ndim, nx, ny, nz, hw, _ptr(ub), _ptr(uo), int(max_iter), float(tol),
+                          INITS[init], NORM_REFS[norm_ref], int(sum_mode), _ptr(hb), ctypes.byref(info))
+        if rc != 0:
+            raise ValueError("oracle rejected the arguments")
+        u[b] = uo
+        hist[b] = hb
+        infos.append({"iters": info.iters, "status": info.status, "status_name": STATUS[info.status],
+                      "r_ref": info.r_ref, "r0": info.r0, "r_final": info.r_final, "r_true": info.r_true})
+    return u.reshape(ubar.shape), infos, hist
