@@ -1,0 +1,170 @@
+/*
+ * gdecon.h -- C ABI of the MI355X deconvolution library (libgdecon.so).
+ *
+ * The library solves the approximate-deconvolution problem G u = ubar of
+ * San & Vedula (Sec. 3, Eq. tau3) on periodic 2D and 3D grids.  G is the
+ * separable 3-point trapezoidal low-pass filter with weights (1/4, 1/2, 1/4)
+ * along every axis, applied matrix-free as a stencil; its Fourier transfer
+ * function is prod_d cos^2(pi k_d / n_d).  The paper leaves G free (opening of
+ * Sec. 4); it runs its own study with a spectral differential filter.
+ *
+ * Solvers: Van Cittert / Richardson (Algorithm 1), steepest descent
+ * (Algorithm 2), conjugate gradient (Algorithm 3) and BiCGSTAB (Algorithm 4).
+ *
+ * Conventions for every entry point
+ *   - Field pointers are DEVICE pointers.  Fields are C-contiguous with x
+ *     fastest: 2D index i + nx*j, 3D index i + nx*(j + ny*k); field b of a
+ *     batch starts at element b * nx*ny*nz.
+ *   - The caller allocates and owns every buffer (inputs, outputs, workspace,
+ *     info).  The library allocates no device memory and keeps no per-call
+ *     state; its only global state is cached device properties and tuning
+ *     choices, guarded by a mutex.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Every
+ *     call is stream-ordered and returns without waiting for the GPU; results
+ *     and `info` are valid once the stream has been synchronised.  A call
+ *     launches only kernels (no memset or copy nodes), so it can be captured
+ *     into a HIP graph.
+ *   - Return value 0 = launched.  Negative values are argument or runtime
+ *     errors detected BEFORE anything is launched (nothing is written then);
+ *     gd_status_string() names them.  Convergence outcomes are not errors:
+ *     they are reported per field in gd_info.status.
+ *   - Inputs must not alias outputs (ubar vs u, x vs y).
+ */
+#ifndef GDECON_H
+#define GDECON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* storage / arithmetic type of the fields */
+enum { GD_F64 = 0, GD_F32 = 1 };
+
+/* solvers: Algorithms 1-4 of the paper */
+enum { GD_VANCITTERT = 0, GD_CG = 1, GD_BICGSTAB = 2, GD_STEEPEST_DESCENT = 3 };
+
+/* initial guess: the paper's u0 = ubar (Algorithms 1-4), zero, or the value
+ * already in u (a warm start) */
+enum { GD_INIT_UBAR = 0, GD_INIT_ZERO = 1, GD_INIT_GIVEN = 2 };
+
+/* reference norm for the relative residual: ||ubar - G ubar|| (the paper's
+ * initial residual, default) or ||ubar|| */
+enum { GD_REF_R0UBAR = 0, GD_REF_UBAR = 1 };
+
+/* return codes (negative) */
+enum {
+    GD_OK = 0,
+    GD_EINVAL = -1,      /* bad ndim/dtype/size/enum, NULL pointer, aliasing */
+    GD_EWORKSPACE = -2,  /* work == NULL or work_bytes too small */
+    GD_EHIP = -3,        /* a HIP runtime call failed */
+    GD_EALIGN = -4       /* workspace not 256-byte aligned */
+};
+
+/* per-field outcome, gd_info.status */
+enum {
+    GD_CONVERGED = 0,        /* ||r_n|| <= tol * r_ref, or r_n == 0 */
+    GD_MAXITER = 1,          /* max_iter passes done (always the case for tol <= 0) */
+    GD_BREAKDOWN_RHO = 2,    /* a zero denominator of alpha: (p,Gp), (f0,q), (r,Gr) or rho */
+    GD_BREAKDOWN_OMEGA = 3,  /* BiCGSTAB: (t,t) == 0 with s != 0 */
+    GD_NONFINITE = 4,        /* a NaN/Inf scalar (e.g. NaN in ubar) */
+    GD_ZERO_REF = 5,         /* reference norm is zero: u = u0, no pass done */
+    GD_TIMEOUT = 6           /* the device-side grid barrier exceeded its wait bound */
+};
+
+typedef struct gd_grid {
+    int32_t ndim;   /* 2 or 3 */
+    int32_t dtype;  /* GD_F64 or GD_F32 */
+    int64_t n[3];   /* nx, ny, nz; each >= 1 (nz ignored when ndim == 2) */
+    double h[3];    /* grid spacings for the inner product h^d sum a_i b_i
+                       (the integral of Eq. inner); a value <= 0 means 2*pi/n */
+    int64_t batch;  /* number of independent fields, >= 1, each with its own
+                       scalars, iteration count and status */
+} gd_grid;
+
+typedef struct gd_opts {
+    int32_t max_iter;   /* N: loop passes of Algorithms 1-4, >= 0 */
+    int32_t init;       /* GD_INIT_* */
+    int32_t norm_ref;   /* GD_REF_* */
+    int32_t reserved;   /* set to 0 */
+    double tol;         /* > 0: stop after the first pass with
+                           ||r_n|| <= tol * r_ref; <= 0: run exactly max_iter
+                           passes (unless a guard stops earlier) */
+    double *history;    /* NULL, or device [batch][max_iter + 1] doubles:
+                           history[b][n] = ||r_n|| (recursive residual,
+                           h-weighted) for n <= iters; later entries untouched */
+    int64_t wait_limit_us; /* bound on one grid-barrier wait; 0 = default
+                              (10 s).  Exceeding it ends the kernel with
+                              GD_TIMEOUT in every info. */
+} gd_opts;
+
+/* one per field, written by the device at the end of a solve */
+typedef struct gd_info {
+    int32_t iters;   /* passes completed */
+    int32_t status;  /* GD_CONVERGED ... */
+    double r_ref;    /* reference norm */
+    double r0;       /* ||r_0|| */
+    double r_final;  /* ||r_iters|| (recursive residual) */
+    double r_true;   /* ||ubar - G u|| recomputed at exit, FP64 arithmetic */
+} gd_info;
+
+/*
+ * y = G x for every field of the batch (the filter of Eq. tau3, applied as a
+ * periodic stencil).  x, y: device, grid->batch fields of grid->dtype.
+ * Errors: GD_EINVAL (bad grid, NULL, x == y).
+ */
+int filter_apply(const gd_grid *grid, const void *x, void *y, void *stream);
+
+/*
+ * Bytes of device workspace the solver needs for this grid (0 on a bad
+ * grid/solver).  The workspace must be 256-byte aligned; its contents on entry
+ * do not matter and are clobbered.
+ */
+size_t deconvolve_workspace_bytes(const gd_grid *grid, int32_t solver);
+
+/*
+ * Solve G u = ubar for every field of the batch.
+ *   ubar  device, input, grid->batch fields (not modified)
+ *   u     device, output; read on entry only when opts->init == GD_INIT_GIVEN
+ *   opts  host pointer; see gd_opts
+ *   work  device workspace of at least deconvolve_workspace_bytes() bytes
+ *   info  device, grid->batch gd_info records (output)
+ * Inner products, norms and the scalars alpha, beta, omega, rho are FP64 on the
+ * device for both dtypes; with GD_F32 the stencil and the vector updates run in
+ * FP32 (the precision mode).  The whole iteration loop, convergence test
+ * included, runs on the device in one persistent launch.
+ *
+ * Van Cittert, Algorithm 1: u_{n+1} = u_n + r_n, r_{n+1} = r_n - G r_n.
+ */
+int deconvolve_vancittert(const gd_grid *grid, const void *ubar, void *u, const gd_opts *opts,
+                          void *work, size_t work_bytes, gd_info *info, void *stream);
+
+/* Conjugate gradient, Algorithm 3 (Eqs. cg1 - cg-b): alpha = rho/(p, Gp),
+ * beta = rho_{n+1}/rho_n.  Same arguments as deconvolve_vancittert. */
+int deconvolve_cg(const gd_grid *grid, const void *ubar, void *u, const gd_opts *opts,
+                  void *work, size_t work_bytes, gd_info *info, void *stream);
+
+/* BiCGSTAB, Algorithm 4, with the frozen shadow residual f0 = r0.  Same
+ * arguments as deconvolve_vancittert.  If ||s|| <= tol * r_ref (or s == 0)
+ * after the alpha half step, the solver takes u += alpha p, r = s and stops
+ * with GD_CONVERGED. */
+int deconvolve_bicgstab(const gd_grid *grid, const void *ubar, void *u, const gd_opts *opts,
+                        void *work, size_t work_bytes, gd_info *info, void *stream);
+
+/* Steepest descent, Algorithm 2 (Eq. sd-a): alpha = (r, r)/(r, Gr).  Same
+ * arguments as deconvolve_vancittert. */
+int deconvolve_steepest_descent(const gd_grid *grid, const void *ubar, void *u, const gd_opts *opts,
+                                void *work, size_t work_bytes, gd_info *info, void *stream);
+
+/* Human-readable name of a return code (< 0) or of a gd_info status (>= 0). */
+const char *gd_status_string(int32_t code);
+
+/* Text of the last error a call on this host thread returned (or ""). */
+const char *gd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GDECON_H */

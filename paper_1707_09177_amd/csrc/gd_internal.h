@@ -1,0 +1,118 @@
+// gd_internal.h -- structures shared by the solver kernels and the host driver.
+#pragma once
+
+#include <stdint.h>
+
+#include "gd_device.h"
+#include "gdecon.h"
+
+namespace gd {
+
+// Tile variants: a kernel is compiled for one (ndim, vw, R) shape, coded as
+// ndim*100 + vw*10 + R, or for VAR_ALL (shape chosen per instance).
+constexpr int VAR_ALL = 0;
+__host__ __device__ constexpr int var_code(int ndim, int vw, int R) { return ndim * 100 + vw * 10 + R; }
+__host__ __device__ constexpr int var_ndim(int c) { return c / 100; }
+__host__ __device__ constexpr int var_vw(int c) { return (c / 10) % 10; }
+__host__ __device__ constexpr int var_r(int c) { return c % 10; }
+
+// solver vectors kept in the workspace (u and ubar are the caller's)
+enum { V_R0 = 0, V_R1 = 1, V_P0 = 2, V_P1 = 3, V_Q0 = 4, V_Q1 = 5, V_F0 = 6, NVEC = 7 };
+
+// sweeps of the persistent kernel
+enum Phase : int {
+    PH_RREF_UBAR = 0,  // ||ubar||^2
+    PH_RREF_RES,       // ||ubar - G ubar||^2
+    PH_INIT_UBAR,      // u0 = ubar
+    PH_INIT_ZERO,      // u0 = 0
+    PH_INIT_GIVEN,     // u0 from the caller
+    PH_VC,             // Algorithm 1 pass
+    PH_CG1,            // Algorithm 3: p, G p, (p, G p)
+    PH_CG2,            // Algorithm 3: u, r, (r, r)
+    PH_BIA,            // Algorithm 4: p, q = G p, (f0, q)
+    PH_BIB,            // Algorithm 4: s, t = G s, (s,t) (t,t) (s,s)
+    PH_BIC,            // Algorithm 4: u, r, (f0, r) (r, r)
+    PH_SD1,            // Algorithm 2: (r, G r)
+    PH_SD2,            // Algorithm 2: u, r, (r, r)
+    PH_TRUE            // ||ubar - G u||^2 in FP64, writes gd_info
+};
+
+// Device descriptor of one field (instance) of a solve.
+struct Inst {
+    const void *ubar;
+    void *u;
+    void *vec[NVEC];
+    double *hist;
+    gd_info *info;
+    Geo geo;
+    int64_t tile0, ntiles;  // global tile range of this instance
+    double hw;              // h^d of the inner product
+    int32_t ndim, vw, R, pad;
+};
+
+// FP64 scalars of one instance; written only by the barrier's last arriver.
+struct State {
+    double alpha, beta, omega, rho, rr, r_ref, r0, pad;
+    int32_t iters, status, done, half;
+};
+
+struct Sync {
+    uint32_t count;  // arrivals at the current barrier
+    uint32_t gen;    // completed barriers
+    uint32_t abort;  // set when a wait exceeded its bound
+    int32_t active;  // instances still iterating
+};
+
+struct Params {
+    Inst tmpl;            // uniform batch: instance 0 (others offset by stride)
+    const Inst *table;    // uneven batch: one Inst per instance (device)
+    State *st;
+    Sync *sync;
+    double *part;         // [tile][NACC] partial sums
+    int64_t stride_bytes; // uniform batch: bytes between consecutive fields
+    int64_t tiles_per_inst;
+    int64_t total_tiles;
+    int64_t wait_ticks;   // bound on one barrier wait, wall-clock ticks
+    double tol;
+    int32_t ninst, init, norm_ref, max_iter;
+    int32_t hist_stride;
+    int32_t pad;
+};
+
+// Tile shape of a field: lanes hold vw consecutive x values, a 3D tile spans
+// R rows, and a tile marches L planes.
+struct TileShape {
+    int vw;
+    int R;
+    int64_t L;
+    int blocks_per_cu;  // 0 = as many as fit
+};
+
+constexpr int64_t kMinL = 8;
+
+TileShape choose_tiles(int ndim, int64_t nx, int64_t ny, int64_t nz, int64_t batch, int tsize, bool aligned,
+                       int solver, bool mixed);
+// Tile shapes compiled into the single-shape kernels: 2D lanes of 16 bytes or
+// of one element; 3D lanes of 16 bytes with 1 or 2 rows per tile, or of one
+// element with 4 or 1 rows (fewer registers per row).
+__host__ __device__ constexpr bool variant_ok(int tsize, int ndim, int vw, int R) {
+    const int vm = 16 / tsize;
+    if (ndim == 2) return R == 1 && (vw == vm || vw == 1);
+    if (vw == vm) return R == 1 || R == 2;
+    return vw == 1 && (R == 4 || R == 1);
+}
+// Shapes the VAR_ALL kernel (uneven batches) can run.
+__host__ __device__ constexpr bool mixed_variant_ok(int tsize, int ndim, int vw, int R) {
+    const int vm = 16 / tsize;
+    if (ndim == 2) return R == 1 && (vw == vm || vw == 1);
+    if (vw == vm) return R == 1 || R == 2;
+    return vw == 1 && R == 1;
+}
+
+// kernel entry points, one instantiation unit per dtype and solver
+const void *solve_kernel_ptr(int dtype, int solver, int variant);
+const void *filter_kernel_ptr(int dtype, int variant);
+Geo make_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int vw, int R, int64_t L);
+int64_t geo_tiles(const Geo &g);
+
+}  // namespace gd

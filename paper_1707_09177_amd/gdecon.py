@@ -1,0 +1,244 @@
+"""ctypes binding of libgdecon.so (the HIP deconvolution library).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch provides device memory and the stream.  If the shared
+library is missing the import fails; there is no CPU fallback.
+
+Fields are torch tensors on a ROCm device, C-contiguous with x fastest:
+shape (..., ny, nx) for ndim=2 or (..., nz, ny, nx) for ndim=3; the leading
+dimensions form the batch of independent fields.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgdecon.so")
+
+F64, F32 = 0, 1
+SOLVERS = {"vc": 0, "cg": 1, "bicgstab": 2, "sd": 3}
+INITS = {"ubar": 0, "zero": 1, "given": 2}
+NORM_REFS = {"r0ubar": 0, "ubar": 1}
+STATUS = {0: "CONVERGED", 1: "MAXITER", 2: "BREAKDOWN_RHO", 3: "BREAKDOWN_OMEGA", 4: "NONFINITE", 5: "ZERO_REF",
+          6: "TIMEOUT"}
+ERRORS = {-1: "GD_EINVAL", -2: "GD_EWORKSPACE", -3: "GD_EHIP", -4: "GD_EALIGN"}
+
+
+class GdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+                ("h", ctypes.c_double * 3), ("batch", ctypes.c_int64)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("init", ctypes.c_int32), ("norm_ref", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tol", ctypes.c_double), ("history", ctypes.c_void_p),
+                ("wait_limit_us", ctypes.c_int64)]
+
+
+INFO_BYTES = 40  # gd_info: int32 iters, int32 status, 4 doubles
+
+EXPORTS = ["filter_apply", "deconvolve_workspace_bytes", "deconvolve_vancittert", "deconvolve_cg",
+           "deconvolve_bicgstab", "deconvolve_steepest_descent", "gd_status_string", "gd_last_error"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libgdecon.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(paper_1707_09177_amd/csrc/build.py); there is no fallback")
+    lib = ctypes.CDLL(path)
+    vp, gp, op = ctypes.c_void_p, ctypes.POINTER(Grid), ctypes.POINTER(Opts)
+    lib.filter_apply.argtypes = [gp, vp, vp, vp]
+    lib.filter_apply.restype = ctypes.c_int
+    lib.deconvolve_workspace_bytes.argtypes = [gp, ctypes.c_int32]
+    lib.deconvolve_workspace_bytes.restype = ctypes.c_size_t
+    for name in ("deconvolve_vancittert", "deconvolve_cg", "deconvolve_bicgstab", "deconvolve_steepest_descent"):
+        f = getattr(lib, name)
+        f.argtypes = [gp, vp, vp, op, vp, ctypes.c_size_t, vp, vp]
+        f.restype = ctypes.c_int
+    lib.gd_status_string.argtypes = [ctypes.c_int32]
+    lib.gd_status_string.restype = ctypes.c_char_p
+    lib.gd_last_error.argtypes = []
+    lib.gd_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise GdError(rc, load().gd_last_error().decode())
+
+
+def _stream_handle(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def make_grid(field_shape, ndim: int, dtype: torch.dtype, h=None) -> Grid:
+    if ndim not in (2, 3):
+        raise ValueError("ndim must be 2 or 3")
+    if len(field_shape) < ndim:
+        raise ValueError(f"a {ndim}D field needs at least {ndim} dimensions")
+    g = Grid()
+    g.ndim = ndim
+    g.dtype = F32 if dtype == torch.float32 else F64 if dtype == torch.float64 else -1
+    if g.dtype < 0:
+        raise ValueError("fields must be float32 or float64")
+    sp = tuple(field_shape[-ndim:])[::-1]  # (nx, ny[, nz])
+    for d in range(3):
+        g.n[d] = sp[d] if d < ndim else 1
+        g.h[d] = (h[d] if h is not None else 0.0) if d < ndim else 0.0
+    g.batch = int(math.prod(field_shape[:-ndim])) if len(field_shape) > ndim else 1
+    return g
+
+
+def _dev_ptr(t: torch.Tensor) -> int:
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return t.data_ptr()
+
+
+def filter_apply(x: torch.Tensor, ndim: int = 2, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """y = G x with the periodic trapezoidal stencil (per field of the batch)."""
+    lib = load()
+    g = make_grid(x.shape, ndim, x.dtype)
+    y = torch.empty_like(x) if out is None else out
+    _check(lib.filter_apply(ctypes.byref(g), _dev_ptr(x), _dev_ptr(y), _stream_handle(stream)))
+    return y
+
+
+def workspace_bytes(field_shape, ndim: int, dtype: torch.dtype, solver: str) -> int:
+    g = make_grid(field_shape, ndim, dtype)
+    n = load().deconvolve_workspace_bytes(ctypes.byref(g), SOLVERS[solver])
+    if n == 0:
+        raise GdError(-1, "bad grid or solver")
+    return int(n)
+
+
+def decode_info(raw: np.ndarray) -> list[dict]:
+    """raw: uint8 array of batch*40 bytes copied from the device info buffer."""
+    out = []
+    b = raw.reshape(-1, INFO_BYTES)
+    for row in b:
+        i32 = row[:8].view(np.int32)
+        f64 = row[8:].view(np.float64)
+        out.append({"iters": int(i32[0]), "status": int(i32[1]), "status_name": STATUS.get(int(i32[1]), "?"),
+                    "r_ref": float(f64[0]), "r0": float(f64[1]), "r_final": float(f64[2]),
+                    "r_true": float(f64[3])})
+    return out
+
+
+@dataclass
+class SolveResult:
+    u: torch.Tensor
+    info_dev: torch.Tensor
+    history: torch.Tensor | None
+
+    def info(self) -> list[dict]:
+        """Per-field outcome (synchronises with the device)."""
+        return decode_info(self.info_dev.cpu().numpy())
+
+
+class Deconvolver:
+    """A solver bound to one field shape, with its workspace allocated once.
+
+    ``solve`` only launches kernels on the stream (no allocation when ``out``
+    and ``info`` buffers are reused), so it can be timed or graph-captured.
+    """
+
+    def __init__(self, field_shape, ndim: int, dtype: torch.dtype, solver: str, device=None, h=None):
+        self.lib = load()
+        self.shape = tuple(field_shape)
+        self.ndim = ndim
+        self.dtype = dtype
+        self.solver = solver
+        self.grid = make_grid(self.shape, ndim, dtype, h)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        n = self.lib.deconvolve_workspace_bytes(ctypes.byref(self.grid), SOLVERS[solver])
+        if n == 0:
+            raise GdError(-1, "bad grid or solver")
+        self.work = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        self.batch = int(self.grid.batch)
+        self.info_dev = torch.zeros(self.batch * INFO_BYTES, dtype=torch.uint8, device=self.device)
+        self._fn = getattr(self.lib, {"vc": "deconvolve_vancittert", "cg": "deconvolve_cg",
+                                      "bicgstab": "deconvolve_bicgstab",
+                                      "sd": "deconvolve_steepest_descent"}[solver])
+
+    def solve(self, ubar: torch.Tensor, max_iter: int, tol: float = 0.0, init: str = "ubar",
+              out: torch.Tensor | None = None, norm_ref: str = "r0ubar", history: torch.Tensor | None = None,
+              wait_limit_us: int = 0, stream=None) -> SolveResult:
+        if tuple(ubar.shape) != self.shape or ubar.dtype != self.dtype:
+            raise ValueError(f"ubar must have shape {self.shape} and dtype {self.dtype}")
+        if init == "given" and out is None:
+            raise ValueError("init='given' reads the initial guess from `out`")
+        u = torch.empty_like(ubar) if out is None else out
+        o = Opts()
+        o.max_iter = int(max_iter)
+        o.init = INITS[init]
+        o.norm_ref = NORM_REFS[norm_ref]
+        o.tol = float(tol)
+        o.history = _dev_ptr(history) if history is not None else None
+        o.wait_limit_us = int(wait_limit_us)
+        if history is not None and (history.dtype != torch.float64 or history.numel() < self.batch * (max_iter + 1)):
+            raise ValueError("history must be float64 with batch*(max_iter+1) entries")
+        rc = self._fn(ctypes.byref(self.grid), _dev_ptr(ubar), _dev_ptr(u), ctypes.byref(o),
+                      self.work.data_ptr(), self.work.numel(), self.info_dev.data_ptr(), _stream_handle(stream))
+        _check(rc)
+        return SolveResult(u, self.info_dev, history)
+
+
+def deconvolve(solver: str, ubar: torch.Tensor, max_iter: int, tol: float = 0.0, ndim: int = 2, init: str = "ubar",
+               u0: torch.Tensor | None = None, norm_ref: str = "r0ubar", history: bool = False, h=None,
+               wait_limit_us: int = 0, stream=None):
+    """One-shot solve of G u = ubar.  Returns (u, infos, history or None).
+
+    Synchronises the stream to read the per-field info records.
+    """
+    d = Deconvolver(ubar.shape, ndim, ubar.dtype, solver, device=ubar.device, h=h)
+    out = None
+    if init == "given":
+        if u0 is None:
+            raise ValueError("init='given' needs u0")
+        out = u0.clone()
+    hist = None
+    if history:
+        hist = torch.full((d.batch, max_iter + 1), float("nan"), dtype=torch.float64, device=ubar.device)
+    res = d.solve(ubar, max_iter, tol, init=init, out=out, norm_ref=norm_ref, history=hist,
+                  wait_limit_us=wait_limit_us, stream=stream)
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return res.u, res.info(), hist
+
+
+def deconvolve_vancittert(ubar, max_iter, **kw):
+    return deconvolve("vc", ubar, max_iter, **kw)
+
+
+def deconvolve_cg(ubar, max_iter, **kw):
+    return deconvolve("cg", ubar, max_iter, **kw)
+
+
+def deconvolve_bicgstab(ubar, max_iter, **kw):
+    return deconvolve("bicgstab", ubar, max_iter, **kw)
+
+
+def deconvolve_steepest_descent(ubar, max_iter, **kw):
+    return deconvolve("sd", ubar, max_iter, **kw)
