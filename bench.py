@@ -1,0 +1,180 @@
+"""Throughput of the deconvolution solve on one MI355X.
+
+One step = one solve of G u = ubar to relative residual 1e-6 (recursive
+residual normalised by ||ubar - G ubar||) over the whole batch of the
+workload, inputs resident in HBM, through the C ABI.  Default workload: 16
+independent 2048^2 vorticity fields with a k^-3 spectrum (4 <= k <= 512),
+FP32 storage and stencil/vector arithmetic, FP64 inner products and scalars,
+BiCGSTAB.  CG and Van Cittert are timed on the same batch for the
+"vs Van Cittert" ratio.
+
+Prints one JSON line.  `value` = grid points of the batch / mean time per
+solve (points/s).  `roofline` prices the persistent solve kernel's
+algorithmic HBM bytes against 8 TB/s.  `cpu_baseline` times the CPU FP64
+oracle on a bounded sample of the same workload (rank 0, N=1).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "deconvolved grid points/s to rel. residual 1e-6; % HBM roofline; vs Van Cittert"
+
+# Algorithmic field accesses per grid point (one access = one full-field read
+# or write): init + passes + exit true residual.  Halo re-reads are not counted.
+#   VC:        init 3 (read ubar, write u, r) + 4 per pass + exit 2
+#   CG:        init 3 + 3 (first pass, p0 = r0 not re-read) + 8 per later pass + exit 2
+#   BiCGSTAB:  init 4 (read ubar, write u, r, f0) + 13 (first pass: p0 = q0 = 0 not read)
+#              + 15 per later pass + exit 2
+def accesses(solver: str, iters: int) -> int:
+    if iters <= 0:
+        return 5 if solver != "bicgstab" else 6
+    if solver == "vc":
+        return 3 + 4 * iters + 2
+    if solver == "cg":
+        return 3 + 7 + 8 * (iters - 1) + 2
+    if solver == "bicgstab":
+        return 4 + 13 + 15 * (iters - 1) + 2
+    if solver == "sd":
+        return 3 + 5 * iters + 2
+    raise ValueError(solver)
+
+
+WORKLOADS = {
+    "c2": dict(desc="2D periodic 2048^2 x 16 fields, E(k)~k^-3 on 4<=k<=512, trapezoidal filter, "
+                    "BiCGSTAB to rel. residual 1e-6 (FP32 storage/stencil/updates, FP64 dots/scalars)",
+               cfg=2, ndim=2, n=2048, count=16),
+    "c3": dict(desc="3D periodic 256^3 x 3 velocity components, E(k)~k^-5/3 on 2<=k<=80, divergence-free, "
+                    "BiCGSTAB per component to rel. residual 1e-6 (FP32 storage, FP64 dots/scalars)",
+               cfg=3, ndim=3, n=256, count=3),
+}
+
+
+def make_inputs(w, torch, gd, dev):
+    from paper_1707_09177_amd import synth
+    u = synth.config_fields(w["cfg"], n=w["n"], count=w["count"], dtype=np.float32)
+    ut = torch.from_numpy(u).to(dev)
+    ubar = gd.filter_apply(ut, ndim=w["ndim"])   # ubar = G u on the GPU
+    torch.cuda.synchronize()
+    return u, ubar
+
+
+def time_solver(gd, torch, ubar, w, solver, steps, warmup, tol=1e-6, max_iter=500):
+    d = gd.Deconvolver(ubar.shape, w["ndim"], ubar.dtype, solver)
+    out = torch.empty_like(ubar)
+    for _ in range(warmup):
+        d.solve(ubar, max_iter, tol, out=out)
+    torch.cuda.synchronize()
+    info = d.solve(ubar, max_iter, tol, out=out).info()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        d.solve(ubar, max_iter, tol, out=out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ms = [a.elapsed_time(b) for a, b in evs]
+    return dict(info=info, ms_events=float(np.mean(ms)), ms_min=float(np.min(ms)), wall_ms=wall * 1e3, u=out)
+
+
+def cpu_baseline(w, u32, tol=1e-6, sample_fields=4):
+    import oracle
+    fields = u32[:sample_fields].astype(np.float64)
+    ub = oracle.filter(fields, w["ndim"]).astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    _, infos, _ = oracle.solve("bicgstab", ub, w["ndim"], 500, tol=tol)
+    dt = time.perf_counter() - t0
+    pts = fields.size
+    return dict(value=pts / dt, unit="points/s", cores=1, kind="oracle",
+                sample=f"{len(fields)} of {w['count']} fields ({'x'.join(str(s) for s in fields.shape[1:])}), "
+                       f"FP64 oracle BiCGSTAB to 1e-6, single thread, {dt:.1f} s, "
+                       f"iters {[i['iters'] for i in infos]}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--solvers", default="bicgstab,cg,vc")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(fields shard across GPUs with no communication; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1707_09177_amd import gdecon as gd
+    gd.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = WORKLOADS[args.workload]
+    u32, ubar = make_inputs(w, torch, gd, dev)
+    npts = int(ubar.numel())
+    itemsize = ubar.element_size()
+
+    results = {}
+    for s in args.solvers.split(","):
+        r = time_solver(gd, torch, ubar, w, s, args.steps if s == "bicgstab" else max(3, args.steps // 2),
+                        args.warmup)
+        iters = [i["iters"] for i in r["info"]]
+        st = {i["status_name"] for i in r["info"]}
+        worst_true = max(i["r_true"] / i["r_ref"] for i in r["info"])
+        acc = accesses(s, max(iters))
+        gbs = npts * itemsize * acc / (r["ms_events"] * 1e-3) / 1e9
+        results[s] = dict(ms=r["ms_events"], ms_min=r["ms_min"], wall_ms=r["wall_ms"], iters=iters,
+                          status=sorted(st), worst_true_rel_residual=worst_true,
+                          points_per_s=npts / (r["ms_events"] * 1e-3), accesses_per_point=acc,
+                          algorithmic_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS)
+        del r
+    main_s = "bicgstab" if "bicgstab" in results else list(results)[0]
+    m = results[main_s]
+    if "CONVERGED" not in m["status"] or len(m["status"]) != 1:
+        print(f"warning: {main_s} did not converge on every field: {m['status']}", file=sys.stderr)
+
+    out = {
+        "metric": METRIC,
+        "value": m["points_per_s"],
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "fields": w["count"], "grid": [w["n"]] * w["ndim"],
+                   "points": npts, "solver": main_s, "tol": 1e-6},
+        "roofline": {"bound": "hbm", "achieved": m["algorithmic_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": m["hbm_frac"], "traffic": None,
+                     "kernel": f"solve_kernel<float,{main_s}> (one persistent launch per solve)",
+                     "bytes_per_launch": npts * itemsize * m["accesses_per_point"]},
+        "iterations": m["iters"][0] if len(set(m["iters"])) == 1 else m["iters"],
+        "solvers": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
+    }
+    if "vc" in results and main_s != "vc":
+        out["vs_vancittert"] = results["vc"]["ms"] / m["ms"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, u32)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -164,6 +164,26 @@ const char *gd_status_string(int32_t code);
 /* Text of the last error a call on this host thread returned (or ""). */
 const char *gd_last_error(void);
 
+/* Launch shape of the last solve launched from this host thread: tile lane
+ * width (vw elements), rows per tile (R, 3D), planes per tile along the march
+ * axis (L), tile count, and the persistent grid (workgroups, waves).  For
+ * tests and performance reports. */
+typedef struct gd_launch_info {
+    int32_t variant, vw, R, reserved;
+    int64_t L, tiles, blocks, waves;
+} gd_launch_info;
+int gd_last_launch(gd_launch_info *out);
+
+/* Diagnostics: while set, every solve records, for its k-th grid barrier,
+ * buf[4k] = first arrival, buf[4k+1] = last arrival, buf[4k+2] = release and
+ * buf[4k+3] = latest per-field reduction, in device wall-clock ticks
+ * (hipDeviceAttributeWallClockRate kHz), for k < 64; from buf[256] on, one
+ * counter per (sweep s, tile t) at buf[256 + s * tiles + t] counts how often
+ * the tile was claimed in that sweep.  The caller initialises buf (first
+ * arrival to UINT64_MAX, the others to 0) before each solve.  buf: device
+ * memory of `capacity` uint64 entries; NULL switches recording off. */
+int gd_set_trace(uint64_t *buf, int64_t capacity);
+
 #ifdef __cplusplus
 }
 #endif

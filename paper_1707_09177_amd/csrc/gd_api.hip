@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -53,10 +54,16 @@ const void *solve_kernel_ptr(int dtype, int solver, int variant) {
 __global__ void prep_kernel(Params P) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
-        P.sync->count = 0;
-        P.sync->gen = 0;
+        P.sync->top = 0;
         P.sync->abort = 0;
         P.sync->active = P.ninst;
+    }
+    if (i < 2) P.sync->snap[i].v = 0;
+    if (i < NGRP) {
+        P.sync->cnt[i].v = 0;
+        P.sync->gen[i].v = 0;
+        P.sync->pool[0][i].v = 0;
+        P.sync->pool[1][i].v = 0;
     }
     if (i < P.ninst) {
         State s;
@@ -67,6 +74,7 @@ __global__ void prep_kernel(Params P) {
         s.status = GD_MAXITER;
         s.done = 0;
         s.half = 0;
+        s.cnt = 0;
         P.st[i] = s;
     }
 }
@@ -151,6 +159,10 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 const char *last_error() { return g_err.c_str(); }
 
+thread_local gd_launch_info g_last_launch;
+unsigned long long *g_trace = nullptr;
+int64_t g_trace_cap = 0;
+
 int validate_grid(const gd_grid *g) {
     if (!g) return fail(GD_EINVAL, "grid is NULL");
     if (g->ndim != 2 && g->ndim != 3) return fail(GD_EINVAL, "ndim must be 2 or 3 (got %d)", g->ndim);
@@ -215,7 +227,8 @@ size_t workspace_layout(const gd_grid *g, int solver, int64_t ninst, int64_t til
     return off;
 }
 
-int launch_solve(Params &P, int dtype, int solver, int variant, int blocks_per_cu, hipStream_t stream) {
+// Resident waves of the solve kernel for this variant (its persistent grid).
+int solve_grid(int dtype, int solver, int variant, int blocks_per_cu, const void **kernel, int64_t *blocks_cap) {
     DevProps dp;
     int rc = dev_props(&dp);
     if (rc) return rc;
@@ -223,17 +236,28 @@ int launch_solve(Params &P, int dtype, int solver, int variant, int blocks_per_c
     if (!k) return fail(GD_EINVAL, "no kernel for solver %d variant %d", solver, variant);
     int occ = occupancy(k);
     if (blocks_per_cu > 0 && blocks_per_cu < occ) occ = blocks_per_cu;
+    *kernel = k;
+    *blocks_cap = (int64_t)occ * dp.ncu;
+    return GD_OK;
+}
+
+int launch_solve(Params &P, const void *k, int64_t blocks_cap, hipStream_t stream) {
+    DevProps dp;
+    int rc = dev_props(&dp);
+    if (rc) return rc;
     const int64_t want = (P.total_tiles + WPB - 1) / WPB;
-    const int64_t cap = (int64_t)occ * dp.ncu;
-    const int64_t blocks = std::max<int64_t>(1, std::min(want, cap));
+    const int64_t blocks = std::max<int64_t>(1, std::min(want, blocks_cap));
     if (P.wait_ticks <= 0) P.wait_ticks = (int64_t)10 * 1000 * dp.wall_khz;  // 10 s
-    const int prep_blocks = (int)((P.ninst + 255) / 256);
+    const int prep_blocks = (int)((std::max<int64_t>(P.ninst, NGRP) + 255) / 256);
     hipLaunchKernelGGL(prep_kernel, dim3(prep_blocks), dim3(256), 0, stream, P);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(GD_EHIP, "prep launch: %s", hipGetErrorString(e));
     void *args[] = {&P};
     e = hipLaunchKernel(k, dim3((unsigned)blocks), dim3(BLOCK), args, 0, stream);
     if (e != hipSuccess) return fail(GD_EHIP, "solve launch: %s", hipGetErrorString(e));
+    g_last_launch.blocks = blocks;
+    g_last_launch.waves = blocks * WPB;
+    g_last_launch.tiles = P.total_tiles;
     return GD_OK;
 }
 
@@ -280,7 +304,15 @@ int solve_common(int solver, const gd_grid *g, const void *ubar, void *u, const 
     if (ranges_overlap(ubar, field_bytes, work, need)) return fail(GD_EINVAL, "ubar overlaps the workspace");
     if (ranges_overlap(u, field_bytes, work, need)) return fail(GD_EINVAL, "u overlaps the workspace");
     const bool aligned = ((uintptr_t)ubar % 16 == 0) && ((uintptr_t)u % 16 == 0);
-    const TileShape ts = choose_tiles(g->ndim, nx, ny, nz, g->batch, (int)tsize, aligned, solver, false);
+    TileShape ts = choose_tiles(g->ndim, nx, ny, nz, g->batch, (int)tsize, aligned, solver, false);
+    const int variant = var_code(g->ndim, ts.vw, ts.R);
+    const void *kern = nullptr;
+    int64_t blocks_cap = 0;
+    rc = solve_grid(g->dtype, solver, variant, ts.blocks_per_cu, &kern, &blocks_cap);
+    if (rc) return rc;
+    // march length balanced over the waves the persistent grid will hold
+    ts.L = balanced_L(g->ndim == 2 ? ny : nz, g->batch * tiles_per_plane(g->ndim, nx, ny, ts.vw, ts.R),
+                      blocks_cap * WPB * kTilesPerWave);
 
     Params P;
     std::memset(&P, 0, sizeof P);
@@ -316,7 +348,18 @@ int solve_common(int solver, const gd_grid *g, const void *ubar, void *u, const 
     P.norm_ref = o->norm_ref;
     P.max_iter = o->max_iter;
     P.hist_stride = o->max_iter + 1;
-    return launch_solve(P, g->dtype, solver, var_code(g->ndim, ts.vw, ts.R), ts.blocks_per_cu, (hipStream_t)stream);
+    P.steal = kSteal;
+    if (const char *e = getenv("GD_STEAL")) P.steal = std::max(0, atoi(e));
+    P.trace = g_trace;
+    P.trace_cap = g_trace_cap;
+    rc = launch_solve(P, kern, blocks_cap, (hipStream_t)stream);
+    if (rc == GD_OK) {
+        g_last_launch.variant = variant;
+        g_last_launch.vw = ts.vw;
+        g_last_launch.R = ts.R;
+        g_last_launch.L = ts.L;
+    }
+    return rc;
 }
 
 }  // namespace gd
@@ -403,5 +446,17 @@ const char *gd_status_string(int32_t code) {
 }
 
 const char *gd_last_error(void) { return gd::last_error(); }
+
+int gd_set_trace(uint64_t *buf, int64_t capacity) {
+    gd::g_trace = reinterpret_cast<unsigned long long *>(buf);
+    gd::g_trace_cap = buf ? capacity : 0;
+    return GD_OK;
+}
+
+int gd_last_launch(gd_launch_info *out) {
+    if (!out) return GD_EINVAL;
+    *out = gd::g_last_launch;
+    return GD_OK;
+}
 
 }  // extern "C"

@@ -3,6 +3,9 @@
 
 #include <stdint.h>
 
+#include <algorithm>
+#include <climits>
+
 #include "gd_device.h"
 #include "gdecon.h"
 
@@ -51,17 +54,49 @@ struct Inst {
 };
 
 // FP64 scalars of one instance; written only by the barrier's last arriver.
-struct State {
+// FP64 scalars of one instance, written by the wave that completes the
+// instance's last tile of a sweep.  `cnt` counts the tiles of the current
+// sweep that have published their partial sums.
+struct alignas(128) State {
     double alpha, beta, omega, rho, rr, r_ref, r0, pad;
     int32_t iters, status, done, half;
+    uint32_t cnt;
 };
 
+// Grid-barrier state.  Workgroups arrive in NGRP groups (workgroup b is in
+// group b % NGRP), each with its own counter and its own release flag on a
+// separate 128-byte line, so that arrivals and polling spread over many
+// memory channels instead of serialising on one address.
+constexpr int NGRP = 32;
+struct alignas(128) SyncLine {
+    uint32_t v;
+    uint32_t pad[31];
+};
 struct Sync {
-    uint32_t count;  // arrivals at the current barrier
-    uint32_t gen;    // completed barriers
+    uint32_t top;    // groups complete at the current barrier
     uint32_t abort;  // set when a wait exceeded its bound
     int32_t active;  // instances still iterating
+    uint32_t pad[29];
+    SyncLine cnt[NGRP];  // arrivals per group at the current barrier
+    SyncLine gen[NGRP];  // completed barriers, one copy per group
+    // tile pools of a sweep: the tiles are split into ng contiguous pools and
+    // pool[par][p] counts the tiles of pool p taken so far in a sweep of
+    // parity par (sweeps alternate between the two sets)
+    SyncLine pool[2][NGRP];
+    // instances still active after barrier k, in slot k & 1: every workgroup
+    // takes its loop decision from this snapshot, never from `active` itself
+    // (which the next sweep's reductions already decrement)
+    SyncLine snap[2];
 };
+
+// A wave drains its own group's pool, then helps with the next kSteal - 1.
+constexpr int kSteal = 4;
+// Target tiles per resident wave: the dynamic pools need several per wave to
+// even out the per-wave speed differences at the end of a sweep.
+constexpr int kTilesPerWave = 3;
+// diagnostics buffer layout: 4 entries per barrier for the first 64 barriers,
+// then one claim counter per (sweep, tile)
+constexpr int64_t kTraceClaims = 256;
 
 struct Params {
     Inst tmpl;            // uniform batch: instance 0 (others offset by stride)
@@ -77,6 +112,12 @@ struct Params {
     int32_t ninst, init, norm_ref, max_iter;
     int32_t hist_stride;
     int32_t pad;
+    // optional diagnostics: per barrier k, trace[4k..4k+3] = first arrival,
+    // last arrival, release, latest instance completion (wall-clock ticks)
+    unsigned long long *trace;
+    int64_t trace_cap;
+    int32_t steal;  // pools a wave visits (its own first)
+    int32_t pad2;
 };
 
 // Tile shape of a field: lanes hold vw consecutive x values, a 3D tile spans
@@ -89,6 +130,10 @@ struct TileShape {
 };
 
 constexpr int64_t kMinL = 8;
+constexpr int64_t kMaxL = 512;
+
+int64_t tiles_per_plane(int ndim, int64_t nx, int64_t ny, int vw, int R);
+int64_t balanced_L(int64_t nmarch, int64_t cols, int64_t waves);
 
 TileShape choose_tiles(int ndim, int64_t nx, int64_t ny, int64_t nz, int64_t batch, int tsize, bool aligned,
                        int solver, bool mixed);

@@ -3,12 +3,14 @@
 // One launch runs a whole solve for a batch of fields ("instances").  The grid
 // holds at most as many workgroups as can be resident at once, every wave
 // loops over tiles, and the sweeps of Algorithms 1-4 are separated by a grid
-// barrier.  The last workgroup to reach a barrier sums the per-tile FP64
-// partial inner products of every instance in a fixed order (so results are
-// bitwise reproducible and independent of which wave ran which tile),
-// updates that instance's scalars (alpha, beta, omega, rho, convergence test,
-// guards, residual history) and releases the others.  The iteration loop,
-// including the stopping test, therefore never returns to the host.
+// barrier.  Each tile publishes its FP64 partial inner products and counts
+// itself done for its instance; the wave that completes an instance's last
+// tile sums that instance's partials in tile order (so results are bitwise
+// reproducible and independent of which wave ran which tile) and updates its
+// scalars (alpha, beta, omega, rho, convergence test, guards, residual
+// history).  Instances therefore finish their reductions in parallel, and the
+// grid barrier itself only orders the sweeps.  The iteration loop, including
+// the stopping test, never returns to the host.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -20,6 +22,11 @@
 namespace gd {
 
 // ------------------------------------------------------------ device state
+// s_waitcnt vmcnt(0): block until every vector-memory operation this wave
+// has issued (stores and cache invalidations included) has completed.  GFX9 encoding:
+// vmcnt = 0, expcnt = 7 and lgkmcnt = 15 (the latter two: no wait).
+__device__ __forceinline__ void wait_vm_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 __device__ __forceinline__ int ld_i32(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -27,8 +34,9 @@ __device__ __forceinline__ double ld_f64(const double *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+template <bool TABLE>
 static __device__ __forceinline__ Inst get_inst(const Params &P, int i) {
-    if (P.table) return P.table[i];
+    if constexpr (TABLE) return P.table[i];
     Inst I = P.tmpl;
     const int64_t off = (int64_t)i * P.stride_bytes;
     I.ubar = (const char *)I.ubar + off;
@@ -42,8 +50,9 @@ static __device__ __forceinline__ Inst get_inst(const Params &P, int i) {
     return I;
 }
 
+template <bool TABLE>
 static __device__ __forceinline__ int inst_of(const Params &P, int64_t t) {
-    if (!P.table) return (int)(t / P.tiles_per_inst);
+    if constexpr (!TABLE) return (int)(t / P.tiles_per_inst);
     int lo = 0, hi = P.ninst - 1;
     while (lo < hi) {  // last instance with tile0 <= t
         const int mid = (lo + hi + 1) >> 1;
@@ -89,96 +98,93 @@ __device__ __forceinline__ void tile_body(const Inst &I, const State *S, int it,
     const T beta = T(ld_f64(&S->beta));
     const T omega = T(ld_f64(&S->omega));
     const bool odd = (it & 1) != 0;
-    T *const *V = reinterpret_cast<T *const *>(I.vec);
+    T *const V[NVEC] = {static_cast<T *>(I.vec[0]), static_cast<T *>(I.vec[1]), static_cast<T *>(I.vec[2]),
+                        static_cast<T *>(I.vec[3]), static_cast<T *>(I.vec[4]), static_cast<T *>(I.vec[5]),
+                        static_cast<T *>(I.vec[6])};
     // ping-pong buffers: X(base) is the current one, Y(base) the next one
-    auto X = [&](int base) -> T * { return odd ? V[base + 1] : V[base]; };
-    auto Y = [&](int base) -> T * { return odd ? V[base] : V[base + 1]; };
+    // (a bitwise blend, so that the pair is never indexed through memory)
+    const uintptr_t sel = odd ? ~uintptr_t(0) : uintptr_t(0);
+    auto blend = [&](T *a, T *b) -> T * {
+        return reinterpret_cast<T *>((reinterpret_cast<uintptr_t>(a) & ~sel) | (reinterpret_cast<uintptr_t>(b) & sel));
+    };
+    auto X = [&](int base) -> T * { return blend(V[base], V[base + 1]); };
+    auto Y = [&](int base) -> T * { return blend(V[base + 1], V[base]); };
     const T *ub = static_cast<const T *>(I.ubar);
     T *u = static_cast<T *>(I.u);
     with_variant<T, VS>(I, [&]<int NDIM, int VW, int R>() {
+        const Geo &g = I.geo;
         if constexpr (PH == PH_RREF_UBAR) {
-            OpNormUbar<T, T, VW> op{ub};
-            point_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            OpNormUbar<T, T, VW> op{{nullptr}, {ub}};
+            point_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_RREF_RES) {
-            OpResNorm<T, T, VW> op{ub, ub};
-            march_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            OpResNorm<T, T, VW> op{{ub}, {ub}};
+            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_TRUE) {
-            OpResNorm<T, double, VW> op{u, ub};
-            march_tile<NDIM, VW, R, double>(I.geo, lt, op, acc, lane);
+            OpResNorm<T, double, VW> op{{u}, {ub}};
+            march_tile<NDIM, VW, R, T, double>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_INIT_UBAR) {
-            OpInitUbar<T, T, VW> op{ub, u, V[V_R0], V[V_F0]};
-            march_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            OpInitUbar<T, T, VW> op{{ub}, {nullptr}, u, V[V_R0], V[V_F0]};
+            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_INIT_ZERO) {
-            OpInitZero<T, T, VW> op{ub, u, V[V_R0], V[V_F0]};
-            point_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            OpInitZero<T, T, VW> op{{nullptr}, {ub}, u, V[V_R0], V[V_F0]};
+            point_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_INIT_GIVEN) {
-            OpInitGiven<T, T, VW> op{u, ub, V[V_R0], V[V_F0]};
-            march_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            OpInitGiven<T, T, VW> op{{u}, {ub}, V[V_R0], V[V_F0]};
+            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_VC) {
-            OpVC<T, T, VW> op{X(V_R0), Y(V_R0), u};
-            march_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            OpVC<T, T, VW> op{{X(V_R0)}, {u}, Y(V_R0), u};
+            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_CG1) {
-            OpCG1<T, T, VW> op{V[V_R0], X(V_P0), Y(V_P0), beta, it == 0};
-            march_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            if (it == 0) {
+                OpCG1First<T, T, VW> op{{V[V_R0]}, {nullptr}, Y(V_P0)};
+                march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            } else {
+                OpCG1<T, T, VW> op{{V[V_R0], X(V_P0)}, {nullptr}, Y(V_P0), beta};
+                march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            }
         } else if constexpr (PH == PH_CG2) {
-            OpCG2<T, T, VW> op{Y(V_P0), V[V_R0], u, alpha};
-            march_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            OpCG2<T, T, VW> op{{Y(V_P0)}, {u, V[V_R0]}, u, V[V_R0], alpha};
+            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_BIA) {
-            OpBiA<T, T, VW> op{X(V_R0), X(V_P0), X(V_Q0), V[V_F0],
-                               Y(V_P0), Y(V_Q0), beta, omega, it == 0};
-            march_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            if (it == 0) {
+                OpBiAFirst<T, T, VW> op{{X(V_R0)}, {V[V_F0]}, Y(V_P0), Y(V_Q0)};
+                march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            } else {
+                OpBiA<T, T, VW> op{{X(V_R0), X(V_P0), X(V_Q0)}, {V[V_F0]}, Y(V_P0), Y(V_Q0), beta, omega};
+                march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            }
         } else if constexpr (PH == PH_BIB) {
-            OpBiB<T, T, VW> op{X(V_R0), Y(V_Q0), alpha};
-            march_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            OpBiB<T, T, VW> op{{X(V_R0), Y(V_Q0)}, {nullptr}, alpha};
+            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_BIC) {
-            OpBiC<T, T, VW> op{X(V_R0), Y(V_Q0), Y(V_P0), V[V_F0], u, Y(V_R0), alpha, omega};
-            march_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            OpBiC<T, T, VW> op{{X(V_R0), Y(V_Q0)}, {u, Y(V_P0), V[V_F0]}, u, Y(V_R0), alpha, omega};
+            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_SD1) {
-            OpSD1<T, T, VW> op{X(V_R0)};
-            march_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            OpSD1<T, T, VW> op{{X(V_R0)}, {nullptr}};
+            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_SD2) {
-            OpSD2<T, T, VW> op{X(V_R0), Y(V_R0), u, alpha};
-            march_tile<NDIM, VW, R, T>(I.geo, lt, op, acc, lane);
+            OpSD2<T, T, VW> op{{X(V_R0)}, {u}, Y(V_R0), u, alpha};
+            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         }
     });
 }
 
-template <typename T, int VS, int PH>
-__device__ void run_phase(const Params &P, int it) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t wave_gid = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
-    const int64_t nwaves = (int64_t)gridDim.x * WPB;
-    constexpr int nacc = PhaseNacc<PH>::v;
-    for (int64_t t = wave_gid; t < P.total_tiles; t += nwaves) {
-        const int i = inst_of(P, t);
-        const State *S = &P.st[i];
-        if (PH != PH_TRUE && ld_i32(&S->done)) continue;
-        const Inst I = get_inst(P, i);
-        double acc[NACC] = {0.0, 0.0, 0.0};
-        tile_body<T, VS, PH>(I, S, it, t - I.tile0, acc, lane);
-#pragma unroll
-        for (int k = 0; k < nacc; ++k) {
-            const double v = wave_sum(acc[k]);
-            if (lane == 0) P.part[t * NACC + k] = v;
-        }
-    }
-}
-
 // ------------------------------------------------ scalar recurrences (FP64)
-static __device__ __forceinline__ void finish(State *S, int status) {
+static __device__ __forceinline__ void finish(const Params &P, State *S, int status) {
     S->status = status;
     S->done = 1;
+    __hip_atomic_fetch_add(&P.sync->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Stopping test after `n` completed passes with residual norm rn.
 static __device__ __forceinline__ bool stop_check(const Params &P, State *S, double rn, int n) {
-    if (!isfinite(rn)) { finish(S, GD_NONFINITE); return true; }
-    if (rn == 0.0 || (P.tol > 0.0 && rn <= P.tol * S->r_ref)) { finish(S, GD_CONVERGED); return true; }
-    if (n >= P.max_iter) { finish(S, GD_MAXITER); return true; }
+    if (!isfinite(rn)) { finish(P, S, GD_NONFINITE); return true; }
+    if (rn == 0.0 || (P.tol > 0.0 && rn <= P.tol * S->r_ref)) { finish(P, S, GD_CONVERGED); return true; }
+    if (n >= P.max_iter) { finish(P, S, GD_MAXITER); return true; }
     return false;
 }
 
-static __device__ __forceinline__ void update_scalars(const Params &P, const Inst &I, State *S, int ph, int solver, const double (&sum)[NACC]) {
+static __device__ __forceinline__ void update_scalars(const Params &P, const Inst &I, State *S, int ph, const double (&sum)[NACC]) {
     const double hw = I.hw;
     switch (ph) {
     case PH_RREF_UBAR:
@@ -194,15 +200,15 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
         S->r0 = r0;
         S->rr = rr;
         S->iters = 0;
-        if (I.hist) I.hist[0] = r0;
+        if (I.hist) I.hist[0] = r0;  // index 0 <= max_iter
         // Algorithm 3: rho_0 = (r0, r0).  Algorithm 4: alpha = omega = rho = 1
         // and rho_1 = (f0, r0) = (r0, r0) since f0 = r0.
         S->alpha = 1.0;
         S->omega = 1.0;
         S->beta = 0.0;
         S->rho = rr;
-        if (!isfinite(S->r_ref)) finish(S, GD_NONFINITE);
-        else if (S->r_ref == 0.0) finish(S, GD_ZERO_REF);
+        if (!isfinite(S->r_ref)) finish(P, S, GD_NONFINITE);
+        else if (S->r_ref == 0.0) finish(P, S, GD_ZERO_REF);
         else stop_check(P, S, r0, 0);
         break;
     }
@@ -211,21 +217,21 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
         const double rr = hw * sum[0];
         S->iters += 1;
         S->rr = rr;
-        if (I.hist) I.hist[S->iters] = sqrt(rr);
+        if (I.hist && S->iters <= P.max_iter) I.hist[S->iters] = sqrt(rr);
         stop_check(P, S, sqrt(rr), S->iters);
         break;
     }
     case PH_SD1: {
         const double rd = hw * sum[0];
-        if (!isfinite(rd)) finish(S, GD_NONFINITE);
-        else if (rd == 0.0) finish(S, GD_BREAKDOWN_RHO);
+        if (!isfinite(rd)) finish(P, S, GD_NONFINITE);
+        else if (rd == 0.0) finish(P, S, GD_BREAKDOWN_RHO);
         else S->alpha = S->rr / rd;
         break;
     }
     case PH_CG1: {
         const double pd = hw * sum[0];
-        if (!isfinite(pd)) finish(S, GD_NONFINITE);
-        else if (pd == 0.0) finish(S, GD_BREAKDOWN_RHO);
+        if (!isfinite(pd)) finish(P, S, GD_NONFINITE);
+        else if (pd == 0.0) finish(P, S, GD_BREAKDOWN_RHO);
         else S->alpha = S->rho / pd;
         break;
     }
@@ -233,7 +239,7 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
         const double rho_new = hw * sum[0];
         S->iters += 1;
         S->rr = rho_new;
-        if (I.hist) I.hist[S->iters] = sqrt(rho_new);
+        if (I.hist && S->iters <= P.max_iter) I.hist[S->iters] = sqrt(rho_new);
         if (!stop_check(P, S, sqrt(rho_new), S->iters)) {
             S->beta = rho_new / S->rho;
             S->rho = rho_new;
@@ -242,21 +248,21 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
     }
     case PH_BIA: {
         const double fq = hw * sum[0];
-        if (!isfinite(fq)) finish(S, GD_NONFINITE);
-        else if (fq == 0.0) finish(S, GD_BREAKDOWN_RHO);
+        if (!isfinite(fq)) finish(P, S, GD_NONFINITE);
+        else if (fq == 0.0) finish(P, S, GD_BREAKDOWN_RHO);
         else S->alpha = S->rho / fq;  // rho holds rho_{n+1} = (f0, r_n)
         break;
     }
     case PH_BIB: {
         const double st = hw * sum[0], tt = hw * sum[1], ss = hw * sum[2];
         if (!isfinite(st) || !isfinite(tt) || !isfinite(ss)) {
-            finish(S, GD_NONFINITE);
+            finish(P, S, GD_NONFINITE);
             break;
         }
         const double thr = P.tol > 0.0 ? P.tol * S->r_ref : 0.0;
         const int half = (ss == 0.0) || (sqrt(ss) <= thr);
         if (!half && tt == 0.0) {
-            finish(S, GD_BREAKDOWN_OMEGA);
+            finish(P, S, GD_BREAKDOWN_OMEGA);
             break;
         }
         S->half = half;
@@ -267,14 +273,14 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
         const double fr = hw * sum[0], rr = hw * sum[1];
         S->iters += 1;
         S->rr = rr;
-        if (I.hist) I.hist[S->iters] = sqrt(rr);
+        if (I.hist && S->iters <= P.max_iter) I.hist[S->iters] = sqrt(rr);
         if (S->half) {
-            finish(S, isfinite(rr) ? GD_CONVERGED : GD_NONFINITE);
+            finish(P, S, isfinite(rr) ? GD_CONVERGED : GD_NONFINITE);
             break;
         }
         if (stop_check(P, S, sqrt(rr), S->iters)) break;
-        if (!isfinite(fr)) finish(S, GD_NONFINITE);
-        else if (fr == 0.0) finish(S, GD_BREAKDOWN_RHO);
+        if (!isfinite(fr)) finish(P, S, GD_NONFINITE);
+        else if (fr == 0.0) finish(P, S, GD_BREAKDOWN_RHO);
         else {
             S->beta = (S->alpha / S->omega) * (fr / S->rho);
             S->rho = fr;
@@ -295,146 +301,262 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
     default:
         break;
     }
-    (void)solver;
 }
 
-// Executed by the whole last-arriving workgroup.
-static __device__ void reduce_update(const Params &P, int ph, int solver) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & (WAVE - 1);
-    __shared__ int s_act[WPB];
+// Sum instance i's per-tile partials in tile order and advance its scalars.
+// Run by the whole wave that completed the instance's last tile.
+template <bool TABLE>
+static __device__ void complete_instance(const Params &P, const Inst &I, State *S, int ph, int lane,
+                                         uint32_t epoch) {
     const int nacc = phase_nacc(ph);
-    int act = 0;
-    for (int i = wave; i < P.ninst; i += WPB) {
-        State *S = &P.st[i];
-        if (ph != PH_TRUE && ld_i32(&S->done)) continue;
-        const Inst I = get_inst(P, i);
-        double sum[NACC] = {0.0, 0.0, 0.0};
-        for (int64_t t = lane; t < I.ntiles; t += WAVE) {
+    double sum[NACC] = {0.0, 0.0, 0.0};
+    for (int64_t t = lane; t < I.ntiles; t += WAVE) {
 #pragma unroll
-            for (int k = 0; k < NACC; ++k)
-                if (k < nacc) sum[k] += ld_f64(&P.part[(I.tile0 + t) * NACC + k]);
-        }
-#pragma unroll
-        for (int k = 0; k < NACC; ++k) sum[k] = wave_sum(sum[k]);
-        if (lane == 0) {
-            update_scalars(P, I, S, ph, solver, sum);
-            if (ph != PH_TRUE && !S->done) ++act;
-        }
+        for (int k = 0; k < NACC; ++k)
+            if (k < nacc) sum[k] += ld_f64(&P.part[(I.tile0 + t) * NACC + k]);
     }
-    if (lane == 0) s_act[wave] = act;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int a = 0;
-        for (int w = 0; w < WPB; ++w) a += s_act[w];
-        __hip_atomic_store(&P.sync->active, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) sum[k] = wave_sum(sum[k]);
+    if (lane == 0) {
+        update_scalars(P, I, S, ph, sum);
+        __hip_atomic_store(&S->cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (P.trace && 4 * (int64_t)epoch + 3 < P.trace_cap)
+            atomicMax(&P.trace[4 * epoch + 3], (unsigned long long)wall_clock64());
     }
 }
 
+// One tile of a sweep: march it, publish its partials, count it done, and
+// finish the instance's reduction if it was the instance's last tile.
+template <typename T, int VS, int PH>
+__device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch, int64_t t, int lane) {
+    constexpr int nacc = PhaseNacc<PH>::v;
+    const int64_t ntot = P.total_tiles;
+    const int i = inst_of<VS == VAR_ALL>(P, t);
+    State *S = &P.st[i];
+    // finished instances skip their tiles (a wave-uniform decision)
+    if (PH != PH_TRUE && __builtin_amdgcn_readfirstlane(ld_i32(&S->done)) != 0) return;
+    const Inst I = get_inst<VS == VAR_ALL>(P, i);
+    // diagnostics: count the claims of every (sweep, tile) pair
+    const bool trc = P.trace && kTraceClaims + 4 * ((int64_t)epoch * ntot + t) + 3 < P.trace_cap;
+    if (lane == 0 && trc) {
+        unsigned long long *c = &P.trace[kTraceClaims + 4 * ((int64_t)epoch * ntot + t)];
+        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xf;
+        atomicAdd(&c[0], 1ull);
+        c[1] = ((unsigned long long)blockIdx.x << 16) | ((threadIdx.x >> 6) << 8) | xcc;
+        c[2] = wall_clock64();
+    }
+    double acc[NACC] = {0.0, 0.0, 0.0};
+    tile_body<T, VS, PH>(I, S, it, t - I.tile0, acc, lane);
+    if (lane == 0 && trc) P.trace[kTraceClaims + 4 * ((int64_t)epoch * ntot + t) + 3] = wall_clock64();
+    // publish this tile's partials, then count the tile done
+#pragma unroll
+    for (int k2 = 0; k2 < nacc; ++k2) {
+        const double v = wave_sum(acc[k2]);
+        // agent-coherent store (no L2 write-back of unrelated lines needed)
+        if (lane == 0) __hip_atomic_store(&P.part[t * NACC + k2], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // wait until this wave's partial stores have completed, then count the
+    // tile; the completing wave reads the partials with agent-coherent loads
+    // after it has seen the full count
+    wait_vm_stores();
+    uint32_t prev = 0;
+    if (lane == 0) prev = __hip_atomic_fetch_add(&S->cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    prev = (uint32_t)__builtin_amdgcn_readfirstlane(prev);
+    if (prev == (uint32_t)I.ntiles - 1) complete_instance<VS == VAR_ALL>(P, I, S, PH, lane, epoch);
+}
+
+// One sweep.  With P.steal > 0 the workgroup takes tiles from the sweep's
+// pools, one per wave per round: thread 0 claims WPB consecutive tiles with one
+// atomic and hands them out through LDS, so the decision to stop is the same
+// for the whole workgroup.  With P.steal == 0, wave w takes tiles w, w + W,
+// ... (W waves).  A tile's result does not depend on which wave runs it.
+template <typename T, int VS, int PH>
+__device__ void run_phase(const Params &P, int it, uint32_t epoch) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    const int64_t ntot = P.total_tiles;
+    if (P.steal <= 0) {
+        const int64_t wave_gid = (int64_t)blockIdx.x * WPB + wave;
+        const int64_t nwaves = (int64_t)gridDim.x * WPB;
+        for (int64_t t = wave_gid; t < ntot; t += nwaves) run_tile<T, VS, PH>(P, it, epoch, t, lane);
+        return;
+    }
+    __shared__ int64_t s_base;
+    const uint32_t nb = gridDim.x;
+    const uint32_t ng = nb < (uint32_t)NGRP ? nb : (uint32_t)NGRP;
+    const uint32_t grp = blockIdx.x % NGRP;
+    for (uint32_t h = 0; h < (uint32_t)P.steal && h < ng; ++h) {
+        const uint32_t pl = (grp + h) % ng;
+        const int64_t lo = ntot * pl / ng, hi = ntot * (pl + 1) / ng;
+        uint32_t *ctr = &P.sync->pool[epoch & 1][pl].v;
+        for (;;) {
+            __syncthreads();  // every wave has read the previous round's s_base
+            if (threadIdx.x == 0)
+                s_base = lo + (int64_t)__hip_atomic_fetch_add(ctr, (uint32_t)WPB, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const int64_t base = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(s_base - lo)) + lo;
+            if (base >= hi) break;  // same decision in every wave of the workgroup
+            const int64_t t = base + wave;
+            if (t < hi) run_tile<T, VS, PH>(P, it, epoch, t, lane);
+        }
+    }
+}
+
+template <bool TABLE>
 static __device__ void mark_timeout(const Params &P) {
     __hip_atomic_store(&P.sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int i = 0; i < P.ninst; ++i) {
-        const Inst I = get_inst(P, i);
+        const Inst I = get_inst<TABLE>(P, i);
         I.info->status = GD_TIMEOUT;
         I.info->iters = P.st[i].iters;
     }
 }
 
-// Grid barrier that also finishes the sweep's reductions.  Returns false when
-// the run was aborted (a wait exceeded its bound).
-static __device__ bool grid_sync(const Params &P, uint32_t &epoch, int ph, int solver) {
-    __shared__ int s_last, s_abort;
+// Grid barrier between sweeps.  Returns false when the run was aborted (a
+// wait exceeded its bound).
+//
+// Arrival is two-level: a workgroup counts itself in its group; the last of a
+// group counts the group at the top; the last group's last workgroup writes
+// the next generation into every group's release flag, and each workgroup
+// polls only its own group's flag.
+//
+// Memory ordering across the 8 XCDs (each with its own L2): thread 0 of every
+// workgroup issues one agent-scope release fence (L2 write-back) before it
+// arrives, waits with relaxed loads (no cache maintenance while others are
+// still streaming), and issues one agent-scope acquire fence after the wait.
+// The workgroup's other waves share the CU's caches and are ordered behind
+// thread 0 by the workgroup barrier.
+template <bool TABLE>
+static __device__ int grid_sync(const Params &P, uint32_t &epoch) {
+    __shared__ int s_last, s_abort, s_act;
     __syncthreads();
+    const uint32_t nb = gridDim.x;
+    const uint32_t ng = nb < (uint32_t)NGRP ? nb : (uint32_t)NGRP;
+    const uint32_t grp = blockIdx.x % NGRP;
+    Sync *sy = P.sync;
     if (threadIdx.x == 0) {
+        const bool tr = P.trace && 4 * (int64_t)epoch + 3 < P.trace_cap;
+        if (tr) {
+            const unsigned long long now = wall_clock64();
+            atomicMin(&P.trace[4 * epoch + 0], now);
+            atomicMax(&P.trace[4 * epoch + 1], now);
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const uint32_t prev = __hip_atomic_fetch_add(&P.sync->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        const int last = prev == gridDim.x - 1;
+        const uint32_t gsize = (nb - grp + NGRP - 1) / NGRP;
+        const uint32_t c = __hip_atomic_fetch_add(&sy->cnt[grp].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int last = 0;
+        if (c == gsize - 1) {
+            __hip_atomic_store(&sy->cnt[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            const uint32_t t = __hip_atomic_fetch_add(&sy->top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == ng - 1) {
+                __hip_atomic_store(&sy->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last = 1;
+            }
+        }
         int ab = 0;
         if (!last) {
             const int64_t t0 = wall_clock64();
-            while (__hip_atomic_load(&P.sync->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == epoch) {
-                if (__hip_atomic_load(&P.sync->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            int nap = 1;
+            while (__hip_atomic_load(&sy->gen[grp].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) {
+                if (__hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     ab = 1;
                     break;
                 }
                 if (wall_clock64() - t0 > P.wait_ticks) {
-                    mark_timeout(P);
+                    mark_timeout<TABLE>(P);
                     ab = 1;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                // back off up to ~0.5 us between polls
+                if (nap < 16) {
+                    __builtin_amdgcn_s_sleep(1);
+                    ++nap;
+                } else {
+                    __builtin_amdgcn_s_sleep(8);
+                }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // let the cache invalidation complete before the other waves of the
+        // workgroup, released by the barrier below, issue their loads
+        wait_vm_stores();
         s_last = last;
         s_abort = ab;
+        if (!last && !ab)
+            s_act = (int)__hip_atomic_load(&sy->snap[epoch & 1].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (s_abort) return false;
-    if (s_last) {
-        reduce_update(P, ph, solver);
-        __syncthreads();
+    if (s_abort) return -1;
+    if (s_last && threadIdx.x < WAVE) {
+        // every workgroup has arrived: every tile of the sweep and every
+        // instance reduction is done, so `active` is final for this barrier
         if (threadIdx.x == 0) {
-            __hip_atomic_store(&P.sync->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&P.sync->gen, epoch + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const int a = __hip_atomic_load(&sy->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sy->snap[epoch & 1].v, (uint32_t)a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_act = a;
+            if (P.trace && 4 * (int64_t)epoch + 3 < P.trace_cap) P.trace[4 * epoch + 2] = wall_clock64();
         }
-        __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // the sweep just finished is done with its pool set; the sweep after
+        // next uses it again
+        for (uint32_t k = threadIdx.x; k < (uint32_t)NGRP; k += WAVE)
+            __hip_atomic_store(&sy->pool[epoch & 1][k].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        for (uint32_t k = threadIdx.x; k < ng; k += WAVE)
+            __hip_atomic_store(&sy->gen[k].v, epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __syncthreads();  // s_act is set; no wave of this workgroup runs ahead
     ++epoch;
-    return true;
-}
-
-__device__ __forceinline__ int active_count(const Params &P) {
-    return __hip_atomic_load(&P.sync->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return s_act;
 }
 
 template <typename T, int SOLVER, int VS>
 __global__ __launch_bounds__(BLOCK) void solve_kernel(Params P) {
+    constexpr bool TB = VS == VAR_ALL;
     uint32_t epoch = 0;
+    int act;
     // reference norm when it is not the initial residual itself
     if (P.norm_ref == GD_REF_UBAR) {
-        run_phase<T, VS, PH_RREF_UBAR>(P, 0);
-        if (!grid_sync(P, epoch, PH_RREF_UBAR, SOLVER)) return;
+        run_phase<T, VS, PH_RREF_UBAR>(P, 0, epoch);
+        if (grid_sync<TB>(P, epoch) < 0) return;
     } else if (P.init != GD_INIT_UBAR) {
-        run_phase<T, VS, PH_RREF_RES>(P, 0);
-        if (!grid_sync(P, epoch, PH_RREF_RES, SOLVER)) return;
+        run_phase<T, VS, PH_RREF_RES>(P, 0, epoch);
+        if (grid_sync<TB>(P, epoch) < 0) return;
     }
     // initial guess and residual
-    if (P.init == GD_INIT_UBAR) {
-        run_phase<T, VS, PH_INIT_UBAR>(P, 0);
-        if (!grid_sync(P, epoch, PH_INIT_UBAR, SOLVER)) return;
-    } else if (P.init == GD_INIT_ZERO) {
-        run_phase<T, VS, PH_INIT_ZERO>(P, 0);
-        if (!grid_sync(P, epoch, PH_INIT_ZERO, SOLVER)) return;
-    } else {
-        run_phase<T, VS, PH_INIT_GIVEN>(P, 0);
-        if (!grid_sync(P, epoch, PH_INIT_GIVEN, SOLVER)) return;
-    }
-    for (int it = 0; it < P.max_iter && active_count(P) > 0; ++it) {
+    if (P.init == GD_INIT_UBAR) run_phase<T, VS, PH_INIT_UBAR>(P, 0, epoch);
+    else if (P.init == GD_INIT_ZERO) run_phase<T, VS, PH_INIT_ZERO>(P, 0, epoch);
+    else run_phase<T, VS, PH_INIT_GIVEN>(P, 0, epoch);
+    act = grid_sync<TB>(P, epoch);
+    if (act < 0) return;
+    // every workgroup sees the same `act` after each barrier, so all take the
+    // same path through the loop
+    for (int it = 0; it < P.max_iter && act > 0; ++it) {
         if constexpr (SOLVER == GD_VANCITTERT) {
-            run_phase<T, VS, PH_VC>(P, it);
-            if (!grid_sync(P, epoch, PH_VC, SOLVER)) return;
+            run_phase<T, VS, PH_VC>(P, it, epoch);
+            if ((act = grid_sync<TB>(P, epoch)) < 0) return;
         } else if constexpr (SOLVER == GD_CG) {
-            run_phase<T, VS, PH_CG1>(P, it);
-            if (!grid_sync(P, epoch, PH_CG1, SOLVER)) return;
-            run_phase<T, VS, PH_CG2>(P, it);
-            if (!grid_sync(P, epoch, PH_CG2, SOLVER)) return;
+            run_phase<T, VS, PH_CG1>(P, it, epoch);
+            if (grid_sync<TB>(P, epoch) < 0) return;
+            run_phase<T, VS, PH_CG2>(P, it, epoch);
+            if ((act = grid_sync<TB>(P, epoch)) < 0) return;
         } else if constexpr (SOLVER == GD_BICGSTAB) {
-            run_phase<T, VS, PH_BIA>(P, it);
-            if (!grid_sync(P, epoch, PH_BIA, SOLVER)) return;
-            run_phase<T, VS, PH_BIB>(P, it);
-            if (!grid_sync(P, epoch, PH_BIB, SOLVER)) return;
-            run_phase<T, VS, PH_BIC>(P, it);
-            if (!grid_sync(P, epoch, PH_BIC, SOLVER)) return;
+            run_phase<T, VS, PH_BIA>(P, it, epoch);
+            if (grid_sync<TB>(P, epoch) < 0) return;
+            run_phase<T, VS, PH_BIB>(P, it, epoch);
+            if (grid_sync<TB>(P, epoch) < 0) return;
+            run_phase<T, VS, PH_BIC>(P, it, epoch);
+            if ((act = grid_sync<TB>(P, epoch)) < 0) return;
         } else {
-            run_phase<T, VS, PH_SD1>(P, it);
-            if (!grid_sync(P, epoch, PH_SD1, SOLVER)) return;
-            run_phase<T, VS, PH_SD2>(P, it);
-            if (!grid_sync(P, epoch, PH_SD2, SOLVER)) return;
+            run_phase<T, VS, PH_SD1>(P, it, epoch);
+            if (grid_sync<TB>(P, epoch) < 0) return;
+            run_phase<T, VS, PH_SD2>(P, it, epoch);
+            if ((act = grid_sync<TB>(P, epoch)) < 0) return;
         }
     }
-    run_phase<T, VS, PH_TRUE>(P, 0);
-    grid_sync(P, epoch, PH_TRUE, SOLVER);
+    run_phase<T, VS, PH_TRUE>(P, 0, epoch);
+    grid_sync<TB>(P, epoch);
 }
 
 // filter_apply: one wave per tile, no reduction.
@@ -449,10 +571,9 @@ __global__ __launch_bounds__(BLOCK) void filter_kernel(Inst tmpl, int64_t stride
     T *y = static_cast<T *>(tmpl.u) + b * stride_elems;
     double acc[NACC] = {0.0, 0.0, 0.0};
     with_variant<T, VS>(tmpl, [&]<int NDIM, int VW, int R>() {
-        OpFilter<T, T, VW> op{x, y};
-        march_tile<NDIM, VW, R, T>(tmpl.geo, t - b * tiles_per_inst, op, acc, lane);
+        OpFilter<T, T, VW> op{{x}, {nullptr}, y};
+        march_tile<NDIM, VW, R, T, T>(tmpl.geo, t - b * tiles_per_inst, op, acc, lane);
     });
 }
-
 
 }  // namespace gd

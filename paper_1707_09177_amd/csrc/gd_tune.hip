@@ -14,36 +14,55 @@
 namespace gd {
 
 namespace {
-constexpr int64_t kWaveSlots = 256 * 16;  // resident waves we aim to fill
+constexpr int64_t kWaveSlots = 256 * 16;  // resident waves assumed before the kernel is known
 }
 
+// Lane width and rows per tile.
 TileShape choose_tiles(int ndim, int64_t nx, int64_t ny, int64_t nz, int64_t batch, int tsize, bool aligned,
                        int /*solver*/, bool mixed) {
     TileShape t;
     const int vmax = 16 / tsize;
     t.vw = (aligned && nx % vmax == 0 && nx >= vmax) ? vmax : 1;
     t.blocks_per_cu = 0;
-    int64_t nmarch;
-    int64_t per_plane;
-    const int64_t nxs = (nx + 64 * t.vw - 1) / (64 * t.vw);
     if (ndim == 2) {
         t.R = 1;
-        nmarch = ny;
-        per_plane = nxs;
+    } else if (t.vw > 1) {
+        t.R = ny >= 2 ? 2 : 1;
     } else {
-        if (t.vw > 1) t.R = ny >= 2 ? 2 : 1;
-        else t.R = (!mixed && ny >= 4) ? 4 : 1;
-        nmarch = nz;
-        per_plane = nxs * ((ny + t.R - 1) / t.R);
+        t.R = (!mixed && ny >= 4) ? 4 : 1;
     }
-    // planes per tile: as long as possible while still giving >= 2 tiles per
-    // resident wave; never below kMinL, never above 256
-    const int64_t want_tiles = 2 * kWaveSlots;
-    int64_t L = (batch * per_plane * nmarch) / std::max<int64_t>(1, want_tiles);
-    L = std::max<int64_t>(kMinL, std::min<int64_t>(256, L));
-    L = std::min<int64_t>(L, std::max<int64_t>(kMinL, nmarch));
-    t.L = L;
+    t.L = balanced_L(ndim == 2 ? ny : nz, batch * tiles_per_plane(ndim, nx, ny, t.vw, t.R), kWaveSlots);
     return t;
+}
+
+int64_t tiles_per_plane(int ndim, int64_t nx, int64_t ny, int vw, int R) {
+    const int64_t nxs = (nx + 64 * vw - 1) / (64 * vw);
+    return ndim == 2 ? nxs : nxs * ((ny + R - 1) / R);
+}
+
+// Planes per tile for `cols` independent tile columns of `nmarch` planes run
+// by `waves` resident waves (tile t goes to wave t mod waves).  Minimises the
+// planes the busiest wave marches, halo planes included, preferring longer
+// tiles on ties (fewer halo re-reads).
+int64_t balanced_L(int64_t nmarch, int64_t cols, int64_t waves) {
+    waves = std::max<int64_t>(1, waves);
+    cols = std::max<int64_t>(1, cols);
+    int64_t bestL = std::max<int64_t>(1, std::min<int64_t>(nmarch, kMaxL));
+    int64_t bestCost = INT64_MAX;
+    const int64_t nseg_max = std::max<int64_t>(1, (nmarch + kMinL - 1) / kMinL);
+    for (int64_t nseg = 1; nseg <= nseg_max; ++nseg) {
+        const int64_t L = (nmarch + nseg - 1) / nseg;
+        if (L > kMaxL || (L < kMinL && nseg > 1)) continue;
+        const int64_t segs = (nmarch + L - 1) / L;
+        const int64_t tiles = cols * segs;
+        const int64_t per_wave = (tiles + waves - 1) / waves;
+        const int64_t cost = per_wave * (L + 2);
+        if (cost < bestCost || (cost == bestCost && L > bestL)) {
+            bestCost = cost;
+            bestL = L;
+        }
+    }
+    return std::max<int64_t>(kMinL, bestL);
 }
 
 }  // namespace gd

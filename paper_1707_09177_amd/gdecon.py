@@ -47,10 +47,17 @@ class Opts(ctypes.Structure):
                 ("wait_limit_us", ctypes.c_int64)]
 
 
+class LaunchInfo(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("vw", ctypes.c_int32), ("R", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("L", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("blocks", ctypes.c_int64), ("waves", ctypes.c_int64)]
+
+
 INFO_BYTES = 40  # gd_info: int32 iters, int32 status, 4 doubles
 
 EXPORTS = ["filter_apply", "deconvolve_workspace_bytes", "deconvolve_vancittert", "deconvolve_cg",
-           "deconvolve_bicgstab", "deconvolve_steepest_descent", "gd_status_string", "gd_last_error"]
+           "deconvolve_bicgstab", "deconvolve_steepest_descent", "gd_status_string", "gd_last_error",
+           "gd_last_launch", "gd_set_trace"]
 
 _lib = None
 
@@ -77,8 +84,28 @@ def load(path: str = LIB_PATH):
     lib.gd_status_string.restype = ctypes.c_char_p
     lib.gd_last_error.argtypes = []
     lib.gd_last_error.restype = ctypes.c_char_p
+    lib.gd_last_launch.argtypes = [ctypes.POINTER(LaunchInfo)]
+    lib.gd_last_launch.restype = ctypes.c_int
+    lib.gd_set_trace.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    lib.gd_set_trace.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def last_launch() -> dict:
+    """Tile shape and persistent grid of the last solve launched from this thread."""
+    li = LaunchInfo()
+    load().gd_last_launch(ctypes.byref(li))
+    return {k: int(getattr(li, k)) for k, _ in LaunchInfo._fields_ if k != "reserved"}
+
+
+def set_trace(buf: torch.Tensor | None):
+    """Record grid-barrier timestamps of later solves into ``buf`` (int64, on
+    the device; see gd_set_trace).  ``None`` switches recording off."""
+    if buf is None:
+        load().gd_set_trace(None, 0)
+    else:
+        load().gd_set_trace(_dev_ptr(buf), buf.numel())
 
 
 def _check(rc: int):
