@@ -90,7 +90,7 @@ def time_solver(gd, torch, ubar, w, solver, steps, warmup, tol=1e-6, max_iter=50
     return dict(info=info, ms_events=float(np.mean(ms)), ms_min=float(np.min(ms)), wall_ms=wall * 1e3, u=out)
 
 
-def cpu_baseline(w, u32, tol=1e-6, sample_fields=4):
+def cpu_baseline(w, u32, tol=1e-6, sample_fields=12):
     import oracle
     fields = u32[:sample_fields].astype(np.float64)
     ub = oracle.filter(fields, w["ndim"]).astype(np.float32).astype(np.float64)
@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--solvers", default="bicgstab,cg,vc")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only run a plain 1 GiB device copy (x5): the reference kernel that scales "
+                         "FETCH_SIZE / WRITE_SIZE counter readings to bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -119,6 +122,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calib:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_read": src.numel() * 4, "copy_calib_bytes_written": dst.numel() * 4,
+                          "launches": 5}))
+        return
     from paper_1707_09177_amd import gdecon as gd
     gd.load()
     dev = torch.device("cuda:0")

@@ -89,8 +89,8 @@ struct Sync {
     SyncLine snap[2];
 };
 
-// A wave drains its own group's pool, then helps with the next kSteal - 1.
-constexpr int kSteal = 4;
+// A workgroup drains its own group's pool, then helps with the others.
+constexpr int kSteal = NGRP;
 // Target tiles per resident wave: the dynamic pools need several per wave to
 // even out the per-wave speed differences at the end of a sweep.
 constexpr int kTilesPerWave = 3;
