@@ -53,11 +53,45 @@ def accesses(solver: str, iters: int) -> int:
 WORKLOADS = {
     "c2": dict(desc="2D periodic 2048^2 x 16 fields, E(k)~k^-3 on 4<=k<=512, trapezoidal filter, "
                     "BiCGSTAB to rel. residual 1e-6 (FP32 storage/stencil/updates, FP64 dots/scalars)",
-               cfg=2, ndim=2, n=2048, count=16),
+               cfg=2, ndim=2, n=2048, count=16, key="2048sq_x16"),
     "c3": dict(desc="3D periodic 256^3 x 3 velocity components, E(k)~k^-5/3 on 2<=k<=80, divergence-free, "
                     "BiCGSTAB per component to rel. residual 1e-6 (FP32 storage, FP64 dots/scalars)",
-               cfg=3, ndim=3, n=256, count=3),
+               cfg=3, ndim=3, n=256, count=3, key="256cube_x3"),
 }
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_solve_kernel_bicgstab.txt")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the kernel sources, the build script and the C header."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1707_09177_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))
+                   + glob.glob(os.path.join(csrc, "*.inc")) + [os.path.join(csrc, "build.py"),
+                                                               os.path.join(ROOT, "include", "gdecon.h")])
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key: str):
+    """HBM bytes per launch of the BiCGSTAB solve kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources have
+    changed since those counters were taken (or no figure exists)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.split(" = ", 1) for line in fh.read().splitlines() if " = " in line)
+    except OSError:
+        return None
+    if kv.get("kernel_sources_sha256", "").strip() != kernel_source_hash():
+        return None
+    v = kv.get(f"traffic_bytes[{key}]")
+    return float(v) if v is not None else None
 
 
 def make_inputs(w, torch, gd, dev):
@@ -175,7 +209,8 @@ def main():
         "config": {"workload": w["desc"], "fields": w["count"], "grid": [w["n"]] * w["ndim"],
                    "points": npts, "solver": main_s, "tol": 1e-6},
         "roofline": {"bound": "hbm", "achieved": m["algorithmic_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": m["hbm_frac"], "traffic": None,
+                     "frac": m["hbm_frac"],
+                     "traffic": measured_traffic(w["key"]) if main_s == "bicgstab" else None,
                      "kernel": f"solve_kernel<float,{main_s}> (one persistent launch per solve)",
                      "bytes_per_launch": npts * itemsize * m["accesses_per_point"]},
         "iterations": m["iters"][0] if len(set(m["iters"])) == 1 else m["iters"],
