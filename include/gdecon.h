@@ -158,6 +158,74 @@ int deconvolve_bicgstab(const gd_grid *grid, const void *ubar, void *u, const gd
 int deconvolve_steepest_descent(const gd_grid *grid, const void *ubar, void *u, const gd_opts *opts,
                                 void *work, size_t work_bytes, gd_info *info, void *stream);
 
+/*
+ * ---- Uneven batches: many independent fields of different sizes ----------
+ *
+ * One persistent launch solves every instance of the list, each with its own
+ * grid, scalars, iteration count and status; the instances share the solver,
+ * the dtype and the options.  Results equal what the single-grid entry points
+ * compute for each instance up to the summation order of the dot products
+ * (tiles are split differently), and are reproducible call to call.
+ */
+typedef struct gd_instance {
+    int32_t ndim;        /* 2 or 3 */
+    int32_t reserved;    /* set to 0 */
+    int64_t n[3];        /* nx, ny, nz; each >= 1 (nz ignored when ndim == 2) */
+    double h[3];         /* spacings of the inner product; <= 0 means 2*pi/n */
+    const void *ubar;    /* device, input field (not modified) */
+    void *u;             /* device, output field; read on entry only with
+                            GD_INIT_GIVEN */
+    double *history;     /* NULL or device [max_iter + 1] doubles (see gd_opts) */
+} gd_instance;
+
+/* Workspace bytes for a batch (0 on a bad list).  256-byte aligned buffer,
+ * clobbered.  Depends only on the solver, dtype and the instance sizes. */
+size_t deconvolve_batch_workspace_bytes(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count);
+
+/*
+ * Solve G u = ubar for every instance of `list` (host array of `count`
+ * descriptors, read during the call only) with `solver` (GD_VANCITTERT ...)
+ * in one persistent launch on `stream`.  opts->history is ignored; each
+ * instance names its own.  info: device, `count` records.  The instance
+ * table is written into the workspace by kernels (no copy from host memory),
+ * so the call can be captured into a HIP graph; a replay re-solves the same
+ * pointers.  Errors: GD_EINVAL (bad list entry, overlapping fields, count < 1),
+ * GD_EWORKSPACE, GD_EALIGN, GD_EHIP.
+ */
+int deconvolve_batch(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count, const gd_opts *opts,
+                     void *work, size_t work_bytes, gd_info *info, void *stream);
+
+/*
+ * ---- Autotuner -------------------------------------------------------------
+ *
+ * Times the candidate launch configurations of a solve (tile granularity:
+ * target tiles per resident wave; 3D rows per tile where the uniform kernels
+ * offer a choice) with short fixed-length trial solves on the caller's
+ * buffers and remembers the fastest for this (solver, dtype, sizes)
+ * signature.  Later deconvolve_* / deconvolve_batch calls with the same
+ * signature use it.  With the environment variable GD_TUNE_CACHE naming a
+ * file, choices are also appended there and read back by later processes.
+ * Synchronous (waits for the stream); not for use under graph capture.
+ * `u` (every instance's u) is overwritten by the trials; `info` receives the
+ * last trial's records.
+ */
+typedef struct gd_tune_info {
+    int32_t candidates;      /* configurations timed */
+    int32_t best;            /* index of the fastest */
+    int32_t tiles_per_wave;  /* chosen tile granularity */
+    int32_t rows;            /* chosen 3D rows per tile (1 in 2D) */
+    double best_ms;          /* trial time of the chosen configuration */
+    double default_ms;       /* trial time of the untuned default */
+} gd_tune_info;
+
+int deconvolve_autotune(int32_t solver, const gd_grid *grid, const void *ubar, void *u, void *work, size_t work_bytes,
+                        gd_info *info, void *stream, gd_tune_info *out);
+int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count, void *work,
+                              size_t work_bytes, gd_info *info, void *stream, gd_tune_info *out);
+
+/* Forget every tuning choice made or loaded by this process. */
+void gd_tune_reset(void);
+
 /* Human-readable name of a return code (< 0) or of a gd_info status (>= 0). */
 const char *gd_status_string(int32_t code);
 

@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "gd_internal.h"
 #include "gd_kernels.h"
@@ -283,8 +284,88 @@ bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
     return x < y + nb && y < x + na;
 }
 
-int solve_common(int solver, const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work,
-                 size_t work_bytes, gd_info *info, void *stream) {
+// ---- tuning choices ----------------------------------------------------------
+
+// Launch configuration the autotuner chooses between: target tiles per
+// resident wave (tile granularity) and, for 3D fields in the uniform kernels,
+// rows per tile (0 = the default rule).
+struct TuneCfg {
+    int tpw = kTilesPerWave;
+    int rows = 0;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneCfg> g_tune;
+bool g_tune_loaded = false;
+
+const char *tune_file() {
+    const char *f = getenv("GD_TUNE_CACHE");
+    return (f && *f) ? f : nullptr;
+}
+
+// caller holds g_tune_mu
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *f = tune_file();
+    if (!f) return;
+    FILE *fp = fopen(f, "r");
+    if (!fp) return;
+    char line[1024];
+    while (fgets(line, sizeof line, fp)) {
+        char key[900];
+        int tpw = 0, rows = 0;
+        if (sscanf(line, "%899s %d %d", key, &tpw, &rows) == 3 && tpw >= 1 && tpw <= 64 && rows >= 0 && rows <= 4) {
+            TuneCfg c;
+            c.tpw = tpw;
+            c.rows = rows;
+            g_tune[key] = c;
+        }
+    }
+    fclose(fp);
+}
+
+bool tune_lookup(const std::string &key, TuneCfg *out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void tune_store(const std::string &key, const TuneCfg &c) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune[key] = c;
+    if (const char *f = tune_file()) {
+        if (FILE *fp = fopen(f, "a")) {
+            fprintf(fp, "%s %d %d\n", key.c_str(), c.tpw, c.rows);
+            fclose(fp);
+        }
+    }
+}
+
+std::string device_tag() {
+    DevProps dp;
+    if (dev_props(&dp)) return "dev?";
+    char b[64];
+    snprintf(b, sizeof b, "cu%d", dp.ncu);
+    return b;
+}
+
+std::string key_uniform(int solver, const gd_grid *g, bool aligned) {
+    char b[256];
+    snprintf(b, sizeof b, "U:%s:s%d:t%d:d%d:%lldx%lldx%lld:b%lld:a%d", device_tag().c_str(), solver, g->dtype, g->ndim,
+             (long long)g->n[0], (long long)g->n[1], (long long)(g->ndim == 3 ? g->n[2] : 1), (long long)g->batch,
+             aligned ? 1 : 0);
+    return b;
+}
+
+// ---- uniform batches -----------------------------------------------------------
+
+int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work,
+                  size_t work_bytes, gd_info *info, void *stream, const TuneCfg *force) {
     int rc = validate_grid(g);
     if (rc) return rc;
     rc = validate_opts(o);
@@ -304,7 +385,12 @@ int solve_common(int solver, const gd_grid *g, const void *ubar, void *u, const 
     if (ranges_overlap(ubar, field_bytes, work, need)) return fail(GD_EINVAL, "ubar overlaps the workspace");
     if (ranges_overlap(u, field_bytes, work, need)) return fail(GD_EINVAL, "u overlaps the workspace");
     const bool aligned = ((uintptr_t)ubar % 16 == 0) && ((uintptr_t)u % 16 == 0);
+    TuneCfg cfg;
+    if (force) cfg = *force;
+    else tune_lookup(key_uniform(solver, g, aligned), &cfg);
     TileShape ts = choose_tiles(g->ndim, nx, ny, nz, g->batch, (int)tsize, aligned, solver, false);
+    if (g->ndim == 3 && cfg.rows > 0 && variant_ok((int)tsize, 3, ts.vw, cfg.rows) && (cfg.rows == 1 || ny >= cfg.rows))
+        ts.R = cfg.rows;
     const int variant = var_code(g->ndim, ts.vw, ts.R);
     const void *kern = nullptr;
     int64_t blocks_cap = 0;
@@ -312,7 +398,7 @@ int solve_common(int solver, const gd_grid *g, const void *ubar, void *u, const 
     if (rc) return rc;
     // march length balanced over the waves the persistent grid will hold
     ts.L = balanced_L(g->ndim == 2 ? ny : nz, g->batch * tiles_per_plane(g->ndim, nx, ny, ts.vw, ts.R),
-                      blocks_cap * WPB * kTilesPerWave);
+                      blocks_cap * WPB * std::max(1, cfg.tpw));
 
     Params P;
     std::memset(&P, 0, sizeof P);
@@ -362,6 +448,298 @@ int solve_common(int solver, const gd_grid *g, const void *ubar, void *u, const 
     return rc;
 }
 
+// ---- uneven batches ----------------------------------------------------------
+
+// Instance descriptors are written into the workspace by this kernel, whose
+// argument carries up to kTableChunk of them: the values travel with the
+// launch itself, so no host buffer has to outlive the call or a captured graph.
+constexpr int kTableChunk = 16;
+struct TableChunk {
+    Inst inst[kTableChunk];
+    Inst *dst;
+    int32_t n;
+    int32_t pad;
+};
+static_assert(sizeof(Inst) % 8 == 0, "Inst is copied in 8-byte words");
+static_assert(sizeof(TableChunk) <= 3072, "kernel argument too large");
+
+__global__ void table_kernel(TableChunk c) {
+    constexpr int words = (int)(sizeof(Inst) / 8);
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(c.inst);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(c.dst);
+    for (int k = threadIdx.x; k < c.n * words; k += blockDim.x) dst[k] = src[k];
+}
+
+struct BatchLayout {
+    size_t off_st, off_tab, off_part, off_vec, total;
+    int64_t tiles_max;
+};
+
+int64_t inst_points(const gd_instance &d) { return d.n[0] * d.n[1] * (d.ndim == 3 ? d.n[2] : 1); }
+
+int validate_instance(const gd_instance &d, int i) {
+    if (d.ndim != 2 && d.ndim != 3) return fail(GD_EINVAL, "instance %d: ndim must be 2 or 3", i);
+    for (int k = 0; k < d.ndim; ++k)
+        if (d.n[k] < 1) return fail(GD_EINVAL, "instance %d: n[%d] must be >= 1", i, k);
+    const int64_t npts = inst_points(d);
+    if (d.n[0] > (int64_t(1) << 31) || npts > (int64_t(1) << 40))
+        return fail(GD_EINVAL, "instance %d: field too large", i);
+    return GD_OK;
+}
+
+BatchLayout batch_layout(int solver, int dtype, const gd_instance *list, int32_t count) {
+    const size_t tsize = dtype == GD_F32 ? 4 : 8;
+    BatchLayout L;
+    size_t off = align_up(sizeof(Sync), 256);
+    L.off_st = off;
+    off = align_up(off + (size_t)count * sizeof(State), 256);
+    L.off_tab = off;
+    off = align_up(off + (size_t)count * sizeof(Inst), 256);
+    L.tiles_max = 0;
+    for (int i = 0; i < count; ++i) {
+        const gd_instance &d = list[i];
+        L.tiles_max += max_tiles(d.ndim, d.n[0], d.n[1], d.ndim == 3 ? d.n[2] : 1);
+    }
+    L.off_part = off;
+    off = align_up(off + (size_t)L.tiles_max * NACC * sizeof(double), 256);
+    L.off_vec = off;
+    for (int i = 0; i < count; ++i) off += (size_t)nvec_of(solver) * align_up((size_t)inst_points(list[i]) * tsize, 256);
+    L.total = off;
+    return L;
+}
+
+std::string key_batch(int solver, int dtype, const gd_instance *list, int32_t count) {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the sizes and alignments
+    auto mix = [&](uint64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (v >> (8 * b)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    for (int i = 0; i < count; ++i) {
+        const gd_instance &d = list[i];
+        mix((uint64_t)d.ndim);
+        for (int k = 0; k < 3; ++k) mix((uint64_t)(k < d.ndim ? d.n[k] : 1));
+        mix((((uintptr_t)d.ubar | (uintptr_t)d.u) % 16 == 0) ? 1 : 0);
+    }
+    char b[256];
+    snprintf(b, sizeof b, "B:%s:s%d:t%d:c%d:%016llx", device_tag().c_str(), solver, dtype, count, (unsigned long long)h);
+    return b;
+}
+
+// Every u must be disjoint from every other field (inputs may be shared).
+int check_batch_overlaps(int dtype, const gd_instance *list, int32_t count, const void *work, size_t need) {
+    const size_t tsize = dtype == GD_F32 ? 4 : 8;
+    struct Iv {
+        uintptr_t a, b;
+        bool out;
+        int i;
+    };
+    std::vector<Iv> iv;
+    iv.reserve(2 * (size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const size_t bytes = (size_t)inst_points(list[i]) * tsize;
+        iv.push_back({(uintptr_t)list[i].ubar, (uintptr_t)list[i].ubar + bytes, false, i});
+        iv.push_back({(uintptr_t)list[i].u, (uintptr_t)list[i].u + bytes, true, i});
+        if (ranges_overlap(list[i].ubar, bytes, work, need) || ranges_overlap(list[i].u, bytes, work, need))
+            return fail(GD_EINVAL, "instance %d overlaps the workspace", i);
+    }
+    std::sort(iv.begin(), iv.end(), [](const Iv &x, const Iv &y) { return x.a < y.a; });
+    uintptr_t end_any = 0, end_out = 0;
+    for (const Iv &c : iv) {
+        if (c.a < end_out || (c.out && c.a < end_any))
+            return fail(GD_EINVAL, "instance %d: an output field overlaps another field", c.i);
+        end_any = std::max(end_any, c.b);
+        if (c.out) end_out = std::max(end_out, c.b);
+    }
+    return GD_OK;
+}
+
+int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, const gd_opts *o, void *work,
+                size_t work_bytes, gd_info *info, void *stream, const TuneCfg *force) {
+    if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
+    if (dtype != GD_F32 && dtype != GD_F64) return fail(GD_EINVAL, "dtype must be GD_F32 or GD_F64");
+    if (!list || count < 1) return fail(GD_EINVAL, "the instance list is empty");
+    int rc = validate_opts(o);
+    if (rc) return rc;
+    if (!info) return fail(GD_EINVAL, "info must be non-NULL");
+    for (int i = 0; i < count; ++i) {
+        if ((rc = validate_instance(list[i], i))) return rc;
+        if (!list[i].ubar || !list[i].u) return fail(GD_EINVAL, "instance %d: ubar and u must be non-NULL", i);
+    }
+    if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
+    if ((uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be 256-byte aligned");
+    const BatchLayout lay = batch_layout(solver, dtype, list, count);
+    if (work_bytes < lay.total)
+        return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", lay.total, work_bytes);
+    if ((rc = check_batch_overlaps(dtype, list, count, work, lay.total))) return rc;
+
+    const int tsize = dtype == GD_F32 ? 4 : 8;
+    const int vm = 16 / tsize;
+    std::vector<Inst> tab((size_t)count);
+    bool same = true;
+    for (int i = 0; i < count; ++i) {
+        const gd_instance &d = list[i];
+        const bool al = ((uintptr_t)d.ubar % 16 == 0) && ((uintptr_t)d.u % 16 == 0);
+        Inst &I = tab[i];
+        std::memset(&I, 0, sizeof I);
+        I.ndim = d.ndim;
+        I.vw = (al && d.n[0] % vm == 0 && d.n[0] >= vm) ? vm : 1;
+        I.R = 1;
+        if (I.ndim != tab[0].ndim || I.vw != tab[0].vw) same = false;
+    }
+    const int variant = (same && tab[0].vw == vm) ? kTableBit + var_code(tab[0].ndim, vm, 1) : VAR_ALL;
+    const void *kern = nullptr;
+    int64_t blocks_cap = 0;
+    if ((rc = solve_grid(dtype, solver, variant, 0, &kern, &blocks_cap))) return rc;
+    TuneCfg cfg;
+    if (force) cfg = *force;
+    else tune_lookup(key_batch(solver, dtype, list, count), &cfg);
+
+    // Tiles of about equal size across instances: target points per tile from
+    // the total work and the tiles the grid should hold.
+    double ptot = 0;
+    for (int i = 0; i < count; ++i) ptot += (double)inst_points(list[i]);
+    const double target_tiles = (double)blocks_cap * WPB * std::max(1, cfg.tpw);
+    const double pts_per_tile = std::max(1.0, ptot / target_tiles);
+    char *w = (char *)work;
+    size_t voff = lay.off_vec;
+    int64_t tile0 = 0;
+    for (int i = 0; i < count; ++i) {
+        const gd_instance &d = list[i];
+        Inst &I = tab[i];
+        const int64_t nx = d.n[0], ny = d.n[1], nz = d.ndim == 3 ? d.n[2] : 1;
+        const int64_t nmarch = d.ndim == 2 ? ny : nz;
+        const double row_pts = (double)WAVE * I.vw * I.R;
+        int64_t L = (int64_t)std::llround(pts_per_tile / row_pts);
+        L = std::min<int64_t>(std::max<int64_t>(L, kMinL), kMaxL);
+        const int64_t nseg = std::max<int64_t>(1, (nmarch + L - 1) / L);
+        L = std::max<int64_t>(kMinL, (nmarch + nseg - 1) / nseg);
+        I.ubar = d.ubar;
+        I.u = d.u;
+        const size_t vb = align_up((size_t)inst_points(d) * tsize, 256);
+        int slot = 0;
+        for (int v = 0; v < NVEC; ++v) I.vec[v] = vec_used(solver, v) ? (void *)(w + voff + (size_t)(slot++) * vb) : nullptr;
+        voff += (size_t)nvec_of(solver) * vb;
+        I.hist = d.history;
+        I.info = info + i;
+        I.geo = make_geo(d.ndim, nx, ny, nz, I.vw, I.R, L);
+        I.tile0 = tile0;
+        I.ntiles = geo_tiles(I.geo);
+        tile0 += I.ntiles;
+        gd_grid gi;
+        std::memset(&gi, 0, sizeof gi);
+        gi.ndim = d.ndim;
+        for (int k = 0; k < 3; ++k) {
+            gi.n[k] = d.n[k];
+            gi.h[k] = d.h[k];
+        }
+        I.hw = grid_weight(&gi);
+    }
+    if (tile0 > lay.tiles_max) return fail(GD_EINVAL, "internal: tile count exceeds the workspace bound");
+
+    Inst *dtab = (Inst *)(w + lay.off_tab);
+    for (int i = 0; i < count; i += kTableChunk) {
+        TableChunk c;
+        std::memset(&c, 0, sizeof c);
+        c.n = std::min(kTableChunk, count - i);
+        std::memcpy(c.inst, &tab[i], (size_t)c.n * sizeof(Inst));
+        c.dst = dtab + i;
+        hipLaunchKernelGGL(table_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(GD_EHIP, "table launch: %s", hipGetErrorString(e));
+    }
+
+    Params P;
+    std::memset(&P, 0, sizeof P);
+    P.table = dtab;
+    P.st = (State *)(w + lay.off_st);
+    P.sync = (Sync *)w;
+    P.part = (double *)(w + lay.off_part);
+    P.total_tiles = tile0;
+    P.wait_ticks = wait_ticks_of(o);
+    P.tol = o->tol;
+    P.ninst = count;
+    P.init = o->init;
+    P.norm_ref = o->norm_ref;
+    P.max_iter = o->max_iter;
+    P.steal = kSteal;
+    if (const char *e = getenv("GD_STEAL")) P.steal = std::max(0, atoi(e));
+    P.trace = g_trace;
+    P.trace_cap = g_trace_cap;
+    rc = launch_solve(P, kern, blocks_cap, (hipStream_t)stream);
+    if (rc == GD_OK) {
+        g_last_launch.variant = variant;
+        g_last_launch.vw = same ? tab[0].vw : 0;
+        g_last_launch.R = 1;
+        g_last_launch.L = count == 1 ? tab[0].geo.L : 0;
+    }
+    return rc;
+}
+
+// ---- autotuner ---------------------------------------------------------------
+
+// Time each candidate with short fixed-length solves (one warm-up, then the
+// best of three) and return the index of the fastest; candidate 0 is the
+// untuned default.
+template <typename Launch>
+int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStream_t stream, gd_tune_info *out) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(GD_EHIP, "hipEventCreate failed");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(GD_EHIP, "hipEventCreate failed");
+    }
+    int best = -1, rc = GD_OK;
+    double best_ms = 0, default_ms = 0;
+    for (size_t c = 0; c < cands.size() && rc == GD_OK; ++c) {
+        if ((rc = launch(cands[c]))) break;
+        double ms_min = 1e30;
+        for (int rep = 0; rep < 3 && rc == GD_OK; ++rep) {
+            (void)hipEventRecord(e0, stream);
+            if ((rc = launch(cands[c]))) break;
+            (void)hipEventRecord(e1, stream);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(GD_EHIP, "hipEventSynchronize failed");
+                break;
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms_min = std::min(ms_min, (double)ms);
+        }
+        if (rc) break;
+        if (c == 0) default_ms = ms_min;
+        if (best < 0 || ms_min < best_ms) {
+            best = (int)c;
+            best_ms = ms_min;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (out) {
+        out->candidates = (int32_t)cands.size();
+        out->best = best;
+        out->tiles_per_wave = cands[best].tpw;
+        out->rows = cands[best].rows;
+        out->best_ms = best_ms;
+        out->default_ms = default_ms;
+    }
+    return best;
+}
+
+gd_opts trial_opts() {
+    gd_opts o;
+    std::memset(&o, 0, sizeof o);
+    o.max_iter = 2;
+    o.init = GD_INIT_UBAR;
+    o.norm_ref = GD_REF_R0UBAR;
+    o.tol = 0.0;
+    return o;
+}
+
+const int kTpwCands[] = {kTilesPerWave, 2, 4, 6, 8};
+
 }  // namespace gd
 
 using namespace gd;
@@ -410,22 +788,85 @@ size_t deconvolve_workspace_bytes(const gd_grid *g, int32_t solver) {
 
 int deconvolve_vancittert(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work, size_t wb,
                           gd_info *info, void *stream) {
-    return solve_common(GD_VANCITTERT, g, ubar, u, o, work, wb, info, stream);
+    return solve_uniform(GD_VANCITTERT, g, ubar, u, o, work, wb, info, stream, nullptr);
 }
 
 int deconvolve_cg(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work, size_t wb,
                   gd_info *info, void *stream) {
-    return solve_common(GD_CG, g, ubar, u, o, work, wb, info, stream);
+    return solve_uniform(GD_CG, g, ubar, u, o, work, wb, info, stream, nullptr);
 }
 
 int deconvolve_bicgstab(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work, size_t wb,
                         gd_info *info, void *stream) {
-    return solve_common(GD_BICGSTAB, g, ubar, u, o, work, wb, info, stream);
+    return solve_uniform(GD_BICGSTAB, g, ubar, u, o, work, wb, info, stream, nullptr);
 }
 
 int deconvolve_steepest_descent(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work, size_t wb,
                                 gd_info *info, void *stream) {
-    return solve_common(GD_STEEPEST_DESCENT, g, ubar, u, o, work, wb, info, stream);
+    return solve_uniform(GD_STEEPEST_DESCENT, g, ubar, u, o, work, wb, info, stream, nullptr);
+}
+
+size_t deconvolve_batch_workspace_bytes(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count) {
+    if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return 0;
+    if ((dtype != GD_F32 && dtype != GD_F64) || !list || count < 1) return 0;
+    for (int i = 0; i < count; ++i)
+        if (validate_instance(list[i], i)) return 0;
+    return batch_layout(solver, dtype, list, count).total;
+}
+
+int deconvolve_batch(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count, const gd_opts *o,
+                     void *work, size_t wb, gd_info *info, void *stream) {
+    return solve_batch(solver, dtype, list, count, o, work, wb, info, stream, nullptr);
+}
+
+int deconvolve_autotune(int32_t solver, const gd_grid *g, const void *ubar, void *u, void *work, size_t wb,
+                        gd_info *info, void *stream, gd_tune_info *out) {
+    int rc = validate_grid(g);
+    if (rc) return rc;
+    if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
+    const gd_opts o = trial_opts();
+    std::vector<TuneCfg> cands;
+    std::vector<int> rows = {0};
+    if (g->ndim == 3) rows = {0, 1, 2, 4};
+    for (int r : rows)
+        for (int t : kTpwCands) {
+            TuneCfg c;
+            c.tpw = t;
+            c.rows = r;
+            cands.push_back(c);
+        }
+    // every candidate must launch; a shape the field cannot use falls back to
+    // the default rule inside solve_uniform, so duplicates are harmless
+    auto launch = [&](const TuneCfg &c) { return solve_uniform(solver, g, ubar, u, &o, work, wb, info, stream, &c); };
+    const int best = time_candidates(cands, launch, (hipStream_t)stream, out);
+    if (best < 0) return best;
+    const bool aligned = ((uintptr_t)ubar % 16 == 0) && ((uintptr_t)u % 16 == 0);
+    tune_store(key_uniform(solver, g, aligned), cands[best]);
+    return GD_OK;
+}
+
+int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count, void *work,
+                              size_t wb, gd_info *info, void *stream, gd_tune_info *out) {
+    const gd_opts o = trial_opts();
+    std::vector<TuneCfg> cands;
+    for (int t : kTpwCands) {
+        TuneCfg c;
+        c.tpw = t;
+        cands.push_back(c);
+    }
+    auto launch = [&](const TuneCfg &c) {
+        return solve_batch(solver, dtype, list, count, &o, work, wb, info, stream, &c);
+    };
+    const int best = time_candidates(cands, launch, (hipStream_t)stream, out);
+    if (best < 0) return best;
+    tune_store(key_batch(solver, dtype, list, count), cands[best]);
+    return GD_OK;
+}
+
+void gd_tune_reset(void) {
+    std::lock_guard<std::mutex> lk(gd::g_tune_mu);
+    gd::g_tune.clear();
+    gd::g_tune_loaded = true;  // a cache file is not read again after a reset
 }
 
 const char *gd_status_string(int32_t code) {

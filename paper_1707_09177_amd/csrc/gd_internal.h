@@ -12,10 +12,15 @@
 namespace gd {
 
 // Tile variants: a kernel is compiled for one (ndim, vw, R) shape, coded as
-// ndim*100 + vw*10 + R, or for VAR_ALL (shape chosen per instance).
+// ndim*100 + vw*10 + R, or for VAR_ALL (shape chosen per instance).  A uniform
+// batch finds instance i by offsetting instance 0; kTableBit + shape is the
+// same shape reading per-instance descriptors from a table (uneven batches
+// whose instances share one shape); VAR_ALL always reads the table.
 constexpr int VAR_ALL = 0;
+constexpr int kTableBit = 1000;
 __host__ __device__ constexpr int var_code(int ndim, int vw, int R) { return ndim * 100 + vw * 10 + R; }
-__host__ __device__ constexpr int var_ndim(int c) { return c / 100; }
+__host__ __device__ constexpr bool var_table(int c) { return c == VAR_ALL || c >= kTableBit; }
+__host__ __device__ constexpr int var_ndim(int c) { return (c % kTableBit) / 100; }
 __host__ __device__ constexpr int var_vw(int c) { return (c / 10) % 10; }
 __host__ __device__ constexpr int var_r(int c) { return c % 10; }
 
@@ -150,8 +155,7 @@ __host__ __device__ constexpr bool variant_ok(int tsize, int ndim, int vw, int R
 __host__ __device__ constexpr bool mixed_variant_ok(int tsize, int ndim, int vw, int R) {
     const int vm = 16 / tsize;
     if (ndim == 2) return R == 1 && (vw == vm || vw == 1);
-    if (vw == vm) return R == 1 || R == 2;
-    return vw == 1 && R == 1;
+    return (vw == vm || vw == 1) && R == 1;
 }
 
 // kernel entry points, one instantiation unit per dtype and solver

@@ -76,8 +76,7 @@ __device__ __forceinline__ void with_variant(const Inst &I, F &&f) {
             if (I.vw == VM) f.template operator()<2, VM, 1>();
             else f.template operator()<2, 1, 1>();
         } else if (I.vw == VM) {
-            if (I.R == 2) f.template operator()<3, VM, 2>();
-            else f.template operator()<3, VM, 1>();
+            f.template operator()<3, VM, 1>();
         } else {
             f.template operator()<3, 1, 1>();
         }
@@ -331,11 +330,11 @@ template <typename T, int VS, int PH>
 __device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch, int64_t t, int lane) {
     constexpr int nacc = PhaseNacc<PH>::v;
     const int64_t ntot = P.total_tiles;
-    const int i = inst_of<VS == VAR_ALL>(P, t);
+    const int i = inst_of<var_table(VS)>(P, t);
     State *S = &P.st[i];
     // finished instances skip their tiles (a wave-uniform decision)
     if (PH != PH_TRUE && __builtin_amdgcn_readfirstlane(ld_i32(&S->done)) != 0) return;
-    const Inst I = get_inst<VS == VAR_ALL>(P, i);
+    const Inst I = get_inst<var_table(VS)>(P, i);
     // diagnostics: count the claims of every (sweep, tile) pair
     const bool trc = P.trace && kTraceClaims + 4 * ((int64_t)epoch * ntot + t) + 3 < P.trace_cap;
     if (lane == 0 && trc) {
@@ -362,7 +361,7 @@ __device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch
     uint32_t prev = 0;
     if (lane == 0) prev = __hip_atomic_fetch_add(&S->cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     prev = (uint32_t)__builtin_amdgcn_readfirstlane(prev);
-    if (prev == (uint32_t)I.ntiles - 1) complete_instance<VS == VAR_ALL>(P, I, S, PH, lane, epoch);
+    if (prev == (uint32_t)I.ntiles - 1) complete_instance<var_table(VS)>(P, I, S, PH, lane, epoch);
 }
 
 // One sweep.  With P.steal > 0 the workgroup takes tiles from the sweep's
@@ -371,7 +370,7 @@ __device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch
 // for the whole workgroup.  With P.steal == 0, wave w takes tiles w, w + W,
 // ... (W waves).  A tile's result does not depend on which wave runs it.
 template <typename T, int VS, int PH>
-__device__ void run_phase(const Params &P, int it, uint32_t epoch) {
+__device__ __forceinline__ void run_phase(const Params &P, int it, uint32_t epoch) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
     const int64_t ntot = P.total_tiles;
@@ -404,7 +403,7 @@ __device__ void run_phase(const Params &P, int it, uint32_t epoch) {
 }
 
 template <bool TABLE>
-static __device__ void mark_timeout(const Params &P) {
+static __device__ __forceinline__ void mark_timeout(const Params &P) {
     __hip_atomic_store(&P.sync->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int i = 0; i < P.ninst; ++i) {
         const Inst I = get_inst<TABLE>(P, i);
@@ -428,7 +427,7 @@ static __device__ void mark_timeout(const Params &P) {
 // The workgroup's other waves share the CU's caches and are ordered behind
 // thread 0 by the workgroup barrier.
 template <bool TABLE>
-static __device__ int grid_sync(const Params &P, uint32_t &epoch) {
+static __device__ __forceinline__ int grid_sync(const Params &P, uint32_t &epoch) {
     __shared__ int s_last, s_abort, s_act;
     __syncthreads();
     const uint32_t nb = gridDim.x;
@@ -513,7 +512,7 @@ static __device__ int grid_sync(const Params &P, uint32_t &epoch) {
 
 template <typename T, int SOLVER, int VS>
 __global__ __launch_bounds__(BLOCK) void solve_kernel(Params P) {
-    constexpr bool TB = VS == VAR_ALL;
+    constexpr bool TB = var_table(VS);
     uint32_t epoch = 0;
     int act;
     // reference norm when it is not the initial residual itself

@@ -53,11 +53,23 @@ class LaunchInfo(ctypes.Structure):
                 ("blocks", ctypes.c_int64), ("waves", ctypes.c_int64)]
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
+                ("h", ctypes.c_double * 3), ("ubar", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("history", ctypes.c_void_p)]
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("best", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32),
+                ("rows", ctypes.c_int32), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
+
+
 INFO_BYTES = 40  # gd_info: int32 iters, int32 status, 4 doubles
 
 EXPORTS = ["filter_apply", "deconvolve_workspace_bytes", "deconvolve_vancittert", "deconvolve_cg",
            "deconvolve_bicgstab", "deconvolve_steepest_descent", "gd_status_string", "gd_last_error",
-           "gd_last_launch", "gd_set_trace"]
+           "gd_last_launch", "gd_set_trace", "deconvolve_batch_workspace_bytes", "deconvolve_batch",
+           "deconvolve_autotune", "deconvolve_batch_autotune", "gd_tune_reset"]
 
 _lib = None
 
@@ -88,6 +100,17 @@ def load(path: str = LIB_PATH):
     lib.gd_last_launch.restype = ctypes.c_int
     lib.gd_set_trace.argtypes = [ctypes.c_void_p, ctypes.c_int64]
     lib.gd_set_trace.restype = ctypes.c_int
+    ip, i32, tp = ctypes.POINTER(Instance), ctypes.c_int32, ctypes.POINTER(TuneInfo)
+    lib.deconvolve_batch_workspace_bytes.argtypes = [i32, i32, ip, i32]
+    lib.deconvolve_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.deconvolve_batch.argtypes = [i32, i32, ip, i32, op, vp, ctypes.c_size_t, vp, vp]
+    lib.deconvolve_batch.restype = ctypes.c_int
+    lib.deconvolve_autotune.argtypes = [i32, gp, vp, vp, vp, ctypes.c_size_t, vp, vp, tp]
+    lib.deconvolve_autotune.restype = ctypes.c_int
+    lib.deconvolve_batch_autotune.argtypes = [i32, i32, ip, i32, vp, ctypes.c_size_t, vp, vp, tp]
+    lib.deconvolve_batch_autotune.restype = ctypes.c_int
+    lib.gd_tune_reset.argtypes = []
+    lib.gd_tune_reset.restype = None
     _lib = lib
     return lib
 
@@ -231,6 +254,142 @@ class Deconvolver:
                       self.work.data_ptr(), self.work.numel(), self.info_dev.data_ptr(), _stream_handle(stream))
         _check(rc)
         return SolveResult(u, self.info_dev, history)
+
+
+def _make_opts(max_iter, tol, init, norm_ref, history, wait_limit_us) -> Opts:
+    o = Opts()
+    o.max_iter = int(max_iter)
+    o.init = INITS[init]
+    o.norm_ref = NORM_REFS[norm_ref]
+    o.tol = float(tol)
+    o.history = history
+    o.wait_limit_us = int(wait_limit_us)
+    return o
+
+
+def _tune_dict(t: TuneInfo) -> dict:
+    return {k: (float(getattr(t, k)) if k.endswith("_ms") else int(getattr(t, k))) for k, _ in TuneInfo._fields_}
+
+
+def autotune(solver: str, ubar: torch.Tensor, ndim: int = 2, out: torch.Tensor | None = None, stream=None) -> dict:
+    """Time the launch configurations for this (solver, shape, dtype) and keep
+    the fastest for later solves of the same signature (deconvolve_autotune).
+    ``out`` (or a scratch tensor) is overwritten.  Synchronous."""
+    d = Deconvolver(ubar.shape, ndim, ubar.dtype, solver, device=ubar.device)
+    u = torch.empty_like(ubar) if out is None else out
+    t = TuneInfo()
+    _check(d.lib.deconvolve_autotune(SOLVERS[solver], ctypes.byref(d.grid), _dev_ptr(ubar), _dev_ptr(u),
+                                     d.work.data_ptr(), d.work.numel(), d.info_dev.data_ptr(),
+                                     _stream_handle(stream), ctypes.byref(t)))
+    return _tune_dict(t)
+
+
+def tune_reset():
+    """Forget every tuning choice of this process (gd_tune_reset)."""
+    load().gd_tune_reset()
+
+
+@dataclass
+class BatchResult:
+    u: list
+    info_dev: torch.Tensor
+    history: list | None
+
+    def info(self) -> list[dict]:
+        """Per-instance outcome (synchronises with the device)."""
+        return decode_info(self.info_dev.cpu().numpy())
+
+
+class BatchDeconvolver:
+    """Uneven batch: instance i is a 2D (ny, nx) or 3D (nz, ny, nx) field of
+    its own size; all share solver and dtype.  One persistent launch solves
+    them all (deconvolve_batch); ``solve`` only launches, so it can be timed or
+    captured into a graph as long as the tensors it is given stay alive."""
+
+    def __init__(self, shapes, dtype: torch.dtype, solver: str, device=None, h=None):
+        self.lib = load()
+        self.shapes = [tuple(int(v) for v in sh) for sh in shapes]
+        if not self.shapes:
+            raise ValueError("empty batch")
+        self.dtype = dtype
+        self.dt = F32 if dtype == torch.float32 else F64 if dtype == torch.float64 else -1
+        if self.dt < 0:
+            raise ValueError("fields must be float32 or float64")
+        self.solver = solver
+        self.count = len(self.shapes)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.list = (Instance * self.count)()
+        for i, sh in enumerate(self.shapes):
+            if len(sh) not in (2, 3):
+                raise ValueError("instance shapes are (ny, nx) or (nz, ny, nx)")
+            inst = self.list[i]
+            inst.ndim = len(sh)
+            rev = sh[::-1]
+            for d in range(3):
+                inst.n[d] = rev[d] if d < len(sh) else 1
+                inst.h[d] = (h[i][d] if h is not None else 0.0) if d < len(sh) else 0.0
+        n = self.lib.deconvolve_batch_workspace_bytes(SOLVERS[solver], self.dt, self.list, self.count)
+        if n == 0:
+            raise GdError(-1, "bad instance list or solver")
+        self.work = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        self.info_dev = torch.zeros(self.count * INFO_BYTES, dtype=torch.uint8, device=self.device)
+
+    def _bind(self, ubars, us, histories):
+        if len(ubars) != self.count or len(us) != self.count:
+            raise ValueError(f"expected {self.count} fields")
+        for i, (ub, u, sh) in enumerate(zip(ubars, us, self.shapes)):
+            if tuple(ub.shape) != sh or tuple(u.shape) != sh or ub.dtype != self.dtype or u.dtype != self.dtype:
+                raise ValueError(f"instance {i}: fields must have shape {sh} and dtype {self.dtype}")
+            self.list[i].ubar = _dev_ptr(ub)
+            self.list[i].u = _dev_ptr(u)
+            self.list[i].history = _dev_ptr(histories[i]) if histories is not None else None
+
+    def solve(self, ubars, max_iter: int, tol: float = 0.0, init: str = "ubar", outs=None, norm_ref: str = "r0ubar",
+              histories=None, wait_limit_us: int = 0, stream=None) -> BatchResult:
+        if init == "given" and outs is None:
+            raise ValueError("init='given' reads the initial guesses from `outs`")
+        us = [torch.empty_like(b) for b in ubars] if outs is None else list(outs)
+        if histories is not None:
+            for hst in histories:
+                if hst.dtype != torch.float64 or hst.numel() < max_iter + 1:
+                    raise ValueError("each history must be float64 with max_iter+1 entries")
+        self._bind(ubars, us, histories)
+        o = _make_opts(max_iter, tol, init, norm_ref, None, wait_limit_us)
+        _check(self.lib.deconvolve_batch(SOLVERS[self.solver], self.dt, self.list, self.count, ctypes.byref(o),
+                                         self.work.data_ptr(), self.work.numel(), self.info_dev.data_ptr(),
+                                         _stream_handle(stream)))
+        return BatchResult(us, self.info_dev, histories)
+
+    def autotune(self, ubars, outs=None, stream=None) -> dict:
+        """Tune this batch's launch (deconvolve_batch_autotune); ``outs`` are
+        overwritten.  Synchronous."""
+        us = [torch.empty_like(b) for b in ubars] if outs is None else list(outs)
+        self._bind(ubars, us, None)
+        t = TuneInfo()
+        _check(self.lib.deconvolve_batch_autotune(SOLVERS[self.solver], self.dt, self.list, self.count,
+                                                  self.work.data_ptr(), self.work.numel(), self.info_dev.data_ptr(),
+                                                  _stream_handle(stream), ctypes.byref(t)))
+        return _tune_dict(t)
+
+
+def deconvolve_batch(solver: str, ubars, max_iter: int, tol: float = 0.0, init: str = "ubar", u0s=None,
+                     norm_ref: str = "r0ubar", history: bool = False, wait_limit_us: int = 0, stream=None):
+    """One-shot uneven-batch solve.  ``ubars``: list of 2D/3D tensors of one
+    dtype.  Returns (list of u, infos, list of histories or None)."""
+    b = BatchDeconvolver([t.shape for t in ubars], ubars[0].dtype, solver, device=ubars[0].device)
+    outs = None
+    if init == "given":
+        if u0s is None:
+            raise ValueError("init='given' needs u0s")
+        outs = [t.clone() for t in u0s]
+    hists = None
+    if history:
+        hists = [torch.full((max_iter + 1,), float("nan"), dtype=torch.float64, device=ubars[0].device)
+                 for _ in ubars]
+    res = b.solve(ubars, max_iter, tol, init=init, outs=outs, norm_ref=norm_ref, histories=hists,
+                  wait_limit_us=wait_limit_us, stream=stream)
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return res.u, res.info(), hists
 
 
 def deconvolve(solver: str, ubar: torch.Tensor, max_iter: int, tol: float = 0.0, ndim: int = 2, init: str = "ubar",

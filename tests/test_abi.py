@@ -78,3 +78,43 @@ def test_status_strings_and_host_side_validation():
     rc = lib.deconvolve_vancittert(ctypes.byref(g), ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000),
                                    ctypes.byref(o), ctypes.c_void_p(0x100000), 1 << 30, info, None)
     assert rc == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgdecon.so not built")
+def test_batch_host_side_validation():
+    """Uneven-batch workspace sizing and the argument checks made before any launch."""
+    from paper_1707_09177_amd import gdecon
+    lib = gdecon.load()
+    n = 3
+    lst = (gdecon.Instance * n)()
+    sizes = [(2, (64, 48, 1)), (3, (16, 12, 10)), (2, (9, 7, 1))]
+    for i, (nd, sz) in enumerate(sizes):
+        lst[i].ndim = nd
+        for d in range(3):
+            lst[i].n[d] = sz[d]
+    ws = lib.deconvolve_batch_workspace_bytes(2, 1, lst, n)
+    pts = 64 * 48 + 16 * 12 * 10 + 9 * 7
+    assert ws > 7 * pts * 4                      # BiCGSTAB keeps 7 work vectors per instance
+    assert lib.deconvolve_batch_workspace_bytes(0, 1, lst, n) < ws   # Van Cittert keeps 2
+    assert lib.deconvolve_batch_workspace_bytes(2, 1, lst, 0) == 0
+    assert lib.deconvolve_batch_workspace_bytes(9, 1, lst, n) == 0
+    o = gdecon._make_opts(5, 0.0, "ubar", "r0ubar", None, 0)
+    # NULL field pointers
+    assert lib.deconvolve_batch(2, 1, lst, n, ctypes.byref(o), 256, ws, 256, None) == -1
+    # fake, non-dereferenced addresses: the second output overlaps the first input
+    base = 1 << 40
+    for i in range(n):
+        lst[i].ubar = base + i * (1 << 24)
+        lst[i].u = base + (1 << 30) + i * (1 << 24)
+    lst[1].u = lst[0].ubar + 64
+    work = base + (1 << 34)
+    assert lib.deconvolve_batch(2, 1, lst, n, ctypes.byref(o), work, ws, work + ws, None) == -1
+    assert "overlaps" in lib.gd_last_error().decode()
+    # workspace too small / misaligned
+    lst[1].u = base + (1 << 30) + (1 << 24)
+    assert lib.deconvolve_batch(2, 1, lst, n, ctypes.byref(o), work, ws - 256, work + ws, None) == -2
+    assert lib.deconvolve_batch(2, 1, lst, n, ctypes.byref(o), work + 8, ws, work + ws, None) == -4
+    # bad instance
+    lst[2].ndim = 1
+    assert lib.deconvolve_batch(2, 1, lst, n, ctypes.byref(o), work, ws, work + ws, None) == -1
+    assert "instance 2" in lib.gd_last_error().decode()

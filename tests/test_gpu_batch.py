@@ -1,0 +1,229 @@
+"""Uneven batches in one persistent launch (deconvolve_batch), HIP-graph
+capture of that launch, and the autotuner, against the CPU FP64 oracle.
+
+Tolerances as in test_gpu_parity: FP64 relative L2 of u <= 1e-10 at equal
+pass counts; FP32 storage <= 1e-5 against the FP64 oracle on the same
+FP32-rounded input; pass counts and statuses exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import DEV, rel_l2, to_dev
+from paper_1707_09177_amd import gdecon, synth
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-10
+F32_TOL = 1e-5
+
+# mixed 2D / 3D, aligned and ragged x extents, tiny and multi-tile grids
+MIXED = [(64, 64), (9, 7), (3, 5, 7), (40, 130), (17, 33, 9), (1, 1), (20, 24, 36), (128, 300), (8, 13, 64),
+         (2, 3, 4)]
+ALIGNED_2D = [(64, 64), (96, 128), (40, 256), (200, 8), (33, 64)]
+ALIGNED_3D = [(16, 16, 16), (12, 20, 32), (9, 7, 64), (24, 24, 24)]
+
+
+def make_ubars(shapes, seed, dtype, smooth=0):
+    """ubar = G u for seeded fields u (white noise, or smoothed by `smooth`
+    extra filter passes so that tolerance-driven FP32 runs stay well posed)."""
+    out = []
+    for i, sh in enumerate(shapes):
+        u = np.random.default_rng(seed + i).standard_normal(sh)
+        for _ in range(smooth):
+            u = oracle.filter(u, len(sh))
+        u /= max(np.sqrt(np.mean(u * u)), 1e-300)
+        ub = oracle.filter(u, len(sh))
+        if dtype == torch.float32:
+            ub = ub.astype(np.float32).astype(np.float64)
+        out.append(ub)
+    return out
+
+
+def run_batch(solver, ubars_np, N, dtype, tol=0.0, init="ubar", u0s=None):
+    ubs = [to_dev(x, dtype) for x in ubars_np]
+    u0t = [to_dev(x, dtype) for x in u0s] if u0s is not None else None
+    us, infos, hists = gdecon.deconvolve_batch(solver, ubs, N, tol=tol, init=init, u0s=u0t, history=True)
+    return [u.double().cpu().numpy() for u in us], infos, [h.cpu().numpy() for h in hists]
+
+
+@pytest.mark.parametrize("solver", ["vc", "cg", "bicgstab", "sd"])
+def test_mixed_batch_fp64_matches_oracle(solver):
+    ubs = make_ubars(MIXED, 10, torch.float64)
+    N = 6
+    us, infos, hists = run_batch(solver, ubs, N, torch.float64)
+    for i, ub in enumerate(ubs):
+        want, winfo, whist = oracle.solve(solver, ub, ub.ndim, N, tol=0.0)
+        w = winfo[0]
+        assert infos[i]["iters"] == w["iters"], (i, MIXED[i])
+        assert infos[i]["status"] == w["status"], (i, MIXED[i])
+        assert rel_l2(us[i], want) <= F64_TOL, (i, MIXED[i])
+        k = w["iters"] + 1
+        np.testing.assert_allclose(hists[i][:k], whist[0][:k], rtol=1e-9, atol=1e-14 * max(1.0, w["r_ref"]))
+
+
+@pytest.mark.parametrize("solver", ["cg", "bicgstab"])
+def test_mixed_batch_fp32_to_tolerance(solver):
+    """FP32 storage decides the stop with FP64 scalars from FP32 vectors, the
+    oracle in FP64 throughout, so the pass count may differ by one at the
+    threshold; u is compared with the oracle run for the GPU's pass count."""
+    ubs = make_ubars(MIXED, 30, torch.float32, smooth=3)
+    us, infos, _ = run_batch(solver, ubs, 200, torch.float32, tol=1e-5)
+    for i, ub in enumerate(ubs):
+        if MIXED[i] == (1, 1):   # G is the identity: ubar - G ubar is zero (or rounding noise)
+            assert infos[i]["status_name"] in ("ZERO_REF", "CONVERGED") and infos[i]["iters"] <= 1
+            continue
+        _, winfo, _ = oracle.solve(solver, ub, ub.ndim, 200, tol=1e-5)
+        assert infos[i]["status_name"] == "CONVERGED", (i, MIXED[i], infos[i])
+        assert abs(infos[i]["iters"] - winfo[0]["iters"]) <= 1, (i, MIXED[i])
+        want, _, _ = oracle.solve(solver, ub, ub.ndim, infos[i]["iters"], tol=0.0)
+        assert rel_l2(us[i], want) <= F32_TOL, (i, MIXED[i])
+
+
+@pytest.mark.parametrize("shapes", [ALIGNED_2D, ALIGNED_3D], ids=["2d", "3d"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_shared_shape_table_kernel(shapes, dtype):
+    """All instances share one 16-byte-lane shape: the table kernel with a fixed
+    tile shape runs (not the per-instance-shape kernel)."""
+    ubs = make_ubars(shapes, 50, dtype)
+    N = 4
+    us, infos, _ = run_batch("bicgstab", ubs, N, dtype)
+    ll = gdecon.last_launch()
+    assert ll["variant"] >= 1000 and ll["vw"] == (4 if dtype == torch.float32 else 2)
+    tol = F64_TOL if dtype == torch.float64 else F32_TOL
+    for i, ub in enumerate(ubs):
+        want, winfo, _ = oracle.solve("bicgstab", ub, ub.ndim, N, tol=0.0)
+        assert infos[i]["iters"] == winfo[0]["iters"]
+        assert rel_l2(us[i], want) <= tol, (i, shapes[i])
+
+
+def test_batch_matches_single_calls():
+    ubs = make_ubars(MIXED, 70, torch.float64)
+    N = 5
+    us, infos, _ = run_batch("cg", ubs, N, torch.float64)
+    for i, ub in enumerate(ubs):
+        u1, inf1, _ = gdecon.deconvolve("cg", to_dev(ub, torch.float64), N, ndim=ub.ndim)
+        assert inf1[0]["iters"] == infos[i]["iters"]
+        assert rel_l2(us[i], u1.cpu().numpy()) <= 1e-12
+
+
+def test_batch_deterministic_and_given_start():
+    ubs = make_ubars(MIXED, 90, torch.float32)
+    a, ia, _ = run_batch("bicgstab", ubs, 4, torch.float32)
+    b, ib, _ = run_batch("bicgstab", ubs, 4, torch.float32)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert ia == ib
+    # warm start from the converged answer of each instance: done at once
+    ubs64 = make_ubars(MIXED, 91, torch.float64, smooth=3)
+    ex = [oracle.solve("bicgstab", ub, ub.ndim, 300, tol=1e-12)[0] for ub in ubs64]
+    us, infos, _ = run_batch("bicgstab", ubs64, 20, torch.float64, tol=1e-6, init="given", u0s=ex)
+    for i, inf in enumerate(infos):
+        assert inf["status_name"] in ("CONVERGED", "ZERO_REF") and inf["iters"] <= 1, (i, inf)
+
+
+def test_batch_large_uneven_workload_sampled():
+    """A slice of the 200-instance workload at its real sizes: pass counts
+    against the oracle on the smallest instances, convergence and the true
+    residual on all."""
+    sizes = synth.batch_instances(count=24)
+    shapes = [((n, n) if nd == 2 else (n, n, n)) for nd, n in sizes]
+    fields = [synth.batch_field(nd, n, i).astype(np.float32) for i, (nd, n) in enumerate(sizes)]
+    ubs = [gdecon.filter_apply(to_dev(f, torch.float32), ndim=f.ndim) for f in fields]
+    bd = gdecon.BatchDeconvolver(shapes, torch.float32, "bicgstab")
+    res = bd.solve(ubs, 200, tol=1e-6)
+    infos = res.info()
+    for i, inf in enumerate(infos):
+        assert inf["status_name"] == "CONVERGED", (i, shapes[i], inf)
+        assert inf["r_true"] <= 2e-6 * inf["r_ref"], (i, shapes[i], inf)
+    smallest = sorted(range(len(shapes)), key=lambda i: np.prod(shapes[i]))[:3]
+    for i in smallest:
+        ub = ubs[i].double().cpu().numpy()
+        _, winfo, _ = oracle.solve("bicgstab", ub, ub.ndim, 200, tol=1e-6)
+        assert abs(infos[i]["iters"] - winfo[0]["iters"]) <= 1, (i, shapes[i])
+        want, _, _ = oracle.solve("bicgstab", ub, ub.ndim, infos[i]["iters"], tol=0.0)
+        assert rel_l2(res.u[i].double().cpu().numpy(), want) <= F32_TOL
+
+
+def test_graph_capture_replays_match_eager():
+    """The batched launch captured into a HIP graph: every replay (with eager
+    work between replays) reproduces the eager result bit for bit."""
+    shapes = MIXED
+    ubs = [to_dev(x, torch.float32) for x in make_ubars(shapes, 110, torch.float32)]
+    bd = gdecon.BatchDeconvolver(shapes, torch.float32, "bicgstab")
+    outs = [torch.empty_like(u) for u in ubs]
+    res = bd.solve(ubs, 50, tol=1e-6, outs=outs)
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in outs]
+    eager_info = res.info()
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        bd.solve(ubs, 50, tol=1e-6, outs=outs, stream=s)   # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        bd.solve(ubs, 50, tol=1e-6, outs=outs)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        bd.info_dev.fill_(0xFF)
+        junk = torch.randn(1 << 20, device=DEV)        # unrelated eager work between replays
+        (junk * 2).sum().item()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, (o, e) in enumerate(zip(outs, eager)):
+            assert torch.equal(o, e), (rep, i)
+        assert res.info() == eager_info, rep
+
+
+def test_uniform_call_graph_capture():
+    """The single-grid entry point captured into a graph matches eager."""
+    ub = to_dev(make_ubars([(3, 96, 128)], 130, torch.float32)[0], torch.float32)
+    d = gdecon.Deconvolver(ub.shape, 2, torch.float32, "cg")
+    out = torch.empty_like(ub)
+    d.solve(ub, 30, 1e-6, out=out)
+    torch.cuda.synchronize()
+    eager = out.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        d.solve(ub, 30, 1e-6, out=out)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+
+
+def test_zz_autotune_batch_and_uniform(tmp_path, monkeypatch):
+    """The autotuner times its candidates, keeps a choice that later solves
+    use, writes it to the cache file, and tuned solves still match the oracle."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("GD_TUNE_CACHE", str(cache))
+    try:
+        ubs_np = make_ubars(MIXED, 150, torch.float64)
+        ubs = [to_dev(x, torch.float64) for x in ubs_np]
+        bd = gdecon.BatchDeconvolver(MIXED, torch.float64, "bicgstab")
+        t = bd.autotune(ubs)
+        assert t["candidates"] >= 2 and 0 <= t["best"] < t["candidates"]
+        assert t["best_ms"] <= t["default_ms"] + 1e-9
+        res = bd.solve(ubs, 5, tol=0.0)
+        infos = res.info()
+        for i, ub in enumerate(ubs_np):
+            want, winfo, _ = oracle.solve("bicgstab", ub, ub.ndim, 5, tol=0.0)
+            assert infos[i]["iters"] == winfo[0]["iters"]
+            assert rel_l2(res.u[i].cpu().numpy(), want) <= F64_TOL
+        ub3 = ubs_np[6]                         # a 3D field: rows per tile are tuned too
+        tu = gdecon.autotune("cg", to_dev(ub3, torch.float64), ndim=3)
+        assert tu["candidates"] >= 5 and tu["rows"] in (0, 1, 2, 4)
+        u, infos1, _ = gdecon.deconvolve("cg", to_dev(ub3, torch.float64), 6, ndim=3)
+        want, _, _ = oracle.solve("cg", ub3, 3, 6, tol=0.0)
+        assert rel_l2(u.cpu().numpy(), want) <= F64_TOL
+        lines = cache.read_text().splitlines()
+        assert len(lines) == 2 and lines[0].startswith("B:") and lines[1].startswith("U:")
+    finally:
+        gdecon.tune_reset()
