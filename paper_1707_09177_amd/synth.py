@@ -210,3 +210,35 @@ def batch_field(ndim: int, n: int, inst: int, seed_cfg=4, dtype=np.float64):
     if ndim == 2:
         return field_2d(n, spectrum_kraichnan, 4.0, n / 4.0, rng, dtype)
     return scalar_3d(n, spectrum_kolmogorov, 2.0, 0.3125 * n, rng, dtype)
+
+
+def cnn_init_params(seed: int, channels: int = 32, layers: int = 6) -> np.ndarray:
+    """Initial weights of the warm-start network, flat FP64, in the layer
+    order 1 -> C, C -> C (layers - 2 times), C -> 1, each layer W[cout][9][cin]
+    followed by bias[cout]: He-normal weights (fan-in 9*cin), zero biases, the
+    last layer scaled by 0.1 so the untrained network starts near u0 = ubar."""
+    rng = np.random.default_rng(np.random.SeedSequence([1707, 9177, 5, seed]))
+    dims = [(1, channels)] + [(channels, channels)] * (layers - 2) + [(channels, 1)]
+    parts = []
+    for li, (ci, co) in enumerate(dims):
+        W = rng.standard_normal((co, 9, ci)) * np.sqrt(2.0 / (9 * ci))
+        if li == len(dims) - 1:
+            W *= 0.1
+        parts += [W.ravel(), np.zeros(co)]
+    return np.concatenate(parts)
+
+
+def training_pairs(count: int, n: int = 512, crop: int = 128, seed0: int = 0, dtype=np.float32):
+    """Random crops of 2D k^-3 fields (4 <= k <= n/4) for the warm-start
+    network: `count` arrays (crop, crop).  The filtered inputs are made by the
+    caller (ubar = G u).  Crops of periodic fields are not periodic; the
+    network treats every sample as periodic anyway."""
+    out = []
+    per = max(1, (n // crop) ** 2)
+    for i in range((count + per - 1) // per):
+        f = field_2d(n, spectrum_kraichnan, 4.0, n / 4.0, rng_for(5, 1000 + seed0 + i), np.float64)
+        for cy in range(n // crop):
+            for cx in range(n // crop):
+                if len(out) < count:
+                    out.append(f[cy * crop:(cy + 1) * crop, cx * crop:(cx + 1) * crop].astype(dtype))
+    return out
