@@ -226,6 +226,60 @@ int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *
 /* Forget every tuning choice made or loaded by this process. */
 void gd_tune_reset(void);
 
+/*
+ * ---- Learned warm start -----------------------------------------------------
+ *
+ * The paper starts every deconvolution from u0 = ubar.  The warm start
+ * predicts a better u0 with a small periodic convolutional network and hands
+ * it to a solver with GD_INIT_GIVEN (the solver itself is unchanged; the
+ * plain start stays the fallback):
+ *     s  = RMS of ubar over the field,  x0 = ubar / s,
+ *     a_l = relu(conv_l(a_{l-1}))  for l = 1..5,   y = conv_6(a_5),
+ *     u0 = ubar + s * y,
+ * conv_l a periodic 3x3 cross-correlation with bias, channels
+ * 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1.  Activations are bfloat16, the 32 -> 32
+ * layers run on the matrix cores with FP32 accumulation.  Only 2D fields
+ * (gd_grid.ndim == 2, batch = number of fields) are supported.
+ *
+ * Parameters: one FP32 vector, layer by layer, each W[cout][tap][cin] with
+ * tap = 3*(dy+1) + (dx+1) for the offset (dy, dx) in y and x, then bias[cout].
+ */
+typedef struct gd_cnn {
+    int32_t ndim;      /* 2 */
+    int32_t channels;  /* 32 */
+    int32_t layers;    /* 6 */
+    int32_t reserved;  /* set to 0 */
+    float lr, beta1, beta2, eps;  /* Adam hyper-parameters (training only) */
+    float *params;     /* device, warmstart_param_count() FP32 values (in/out) */
+    float *grad;       /* device, same size, or NULL: the gradient of the last
+                          training step is written here (else into the workspace) */
+    float *adam_m;     /* device, same size, zero before the first step */
+    float *adam_v;     /* device, same size, zero before the first step */
+    int32_t *step;     /* device, one int: Adam steps taken (0 before the first) */
+} gd_cnn;
+
+/* Number of FP32 parameters (37601), or 0 for an unsupported shape. */
+int64_t warmstart_param_count(const gd_cnn *net);
+
+/* Workspace bytes for warmstart_forward (training == 0) or
+ * warmstart_train_step (training != 0) on this grid; 0 on bad arguments. */
+size_t warmstart_workspace_bytes(const gd_cnn *net, const gd_grid *grid, int32_t training);
+
+/* u0 = network(ubar) for every field of the batch.  ubar, u0: device fields of
+ * grid->dtype (FP32 or FP64; the network itself runs in bfloat16/FP32).
+ * Errors: GD_EINVAL (3D grid, unsupported network shape, NULL), GD_EWORKSPACE,
+ * GD_EALIGN. */
+int warmstart_forward(const gd_cnn *net, const gd_grid *grid, const void *ubar, void *u0, void *work,
+                      size_t work_bytes, void *stream);
+
+/* One training step on the pairs (ubar[b], u[b]): forward, the loss
+ * mean over all points of (y - (u - ubar)/s)^2 written to *loss (device
+ * double), backpropagation (gradient into net->grad when non-NULL), then one
+ * Adam update of net->params (bias-corrected with *net->step + 1, after which
+ * *net->step is incremented on the device).  Stream-ordered, capturable. */
+int warmstart_train_step(const gd_cnn *net, const gd_grid *grid, const void *ubar, const void *u, void *work,
+                         size_t work_bytes, double *loss, void *stream);
+
 /* Human-readable name of a return code (< 0) or of a gd_info status (>= 0). */
 const char *gd_status_string(int32_t code);
 

@@ -160,6 +160,10 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 const char *last_error() { return g_err.c_str(); }
 
+// Error text for the other translation units of the library (the warm-start
+// network), so that gd_last_error() reports every entry point.
+void set_error_text(const char *msg) { g_err = msg; }
+
 thread_local gd_launch_info g_last_launch;
 unsigned long long *g_trace = nullptr;
 int64_t g_trace_cap = 0;

@@ -64,12 +64,21 @@ class TuneInfo(ctypes.Structure):
                 ("rows", ctypes.c_int32), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
+class Cnn(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("channels", ctypes.c_int32), ("layers", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("params", ctypes.c_void_p),
+                ("grad", ctypes.c_void_p), ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
+                ("step", ctypes.c_void_p)]
+
+
 INFO_BYTES = 40  # gd_info: int32 iters, int32 status, 4 doubles
 
 EXPORTS = ["filter_apply", "deconvolve_workspace_bytes", "deconvolve_vancittert", "deconvolve_cg",
            "deconvolve_bicgstab", "deconvolve_steepest_descent", "gd_status_string", "gd_last_error",
            "gd_last_launch", "gd_set_trace", "deconvolve_batch_workspace_bytes", "deconvolve_batch",
-           "deconvolve_autotune", "deconvolve_batch_autotune", "gd_tune_reset"]
+           "deconvolve_autotune", "deconvolve_batch_autotune", "gd_tune_reset", "warmstart_param_count",
+           "warmstart_workspace_bytes", "warmstart_forward", "warmstart_train_step"]
 
 _lib = None
 
@@ -111,6 +120,15 @@ def load(path: str = LIB_PATH):
     lib.deconvolve_batch_autotune.restype = ctypes.c_int
     lib.gd_tune_reset.argtypes = []
     lib.gd_tune_reset.restype = None
+    cp = ctypes.POINTER(Cnn)
+    lib.warmstart_param_count.argtypes = [cp]
+    lib.warmstart_param_count.restype = ctypes.c_int64
+    lib.warmstart_workspace_bytes.argtypes = [cp, gp, i32]
+    lib.warmstart_workspace_bytes.restype = ctypes.c_size_t
+    lib.warmstart_forward.argtypes = [cp, gp, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.warmstart_forward.restype = ctypes.c_int
+    lib.warmstart_train_step.argtypes = [cp, gp, vp, vp, vp, ctypes.c_size_t, vp, vp]
+    lib.warmstart_train_step.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -390,6 +408,77 @@ def deconvolve_batch(solver: str, ubars, max_iter: int, tol: float = 0.0, init: 
                   wait_limit_us=wait_limit_us, stream=stream)
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     return res.u, res.info(), hists
+
+
+class WarmStart:
+    """The learned warm start (warmstart_forward / warmstart_train_step): a
+    2D periodic CNN whose output u0 = ubar + s * f(ubar / s) starts a solve with
+    init='given'.  Owns its FP32 parameters, Adam moments and step counter on
+    the device.  ``params``: initial flat FP32/FP64 vector (for example
+    synth.cnn_init_params(seed))."""
+
+    CHANNELS, LAYERS = 32, 6
+
+    def __init__(self, params, device=None, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8):
+        self.lib = load()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.net = Cnn()
+        self.net.ndim, self.net.channels, self.net.layers = 2, self.CHANNELS, self.LAYERS
+        self.net.lr, self.net.beta1, self.net.beta2, self.net.eps = lr, beta1, beta2, eps
+        n = int(self.lib.warmstart_param_count(ctypes.byref(self.net)))
+        p = torch.as_tensor(np.asarray(params), dtype=torch.float32).reshape(-1)
+        if p.numel() != n:
+            raise ValueError(f"the network has {n} parameters, got {p.numel()}")
+        self.params = p.to(self.device).contiguous()
+        self.grad = torch.zeros_like(self.params)
+        self.adam_m = torch.zeros_like(self.params)
+        self.adam_v = torch.zeros_like(self.params)
+        self.step = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.net.params, self.net.grad = self.params.data_ptr(), self.grad.data_ptr()
+        self.net.adam_m, self.net.adam_v = self.adam_m.data_ptr(), self.adam_v.data_ptr()
+        self.net.step = self.step.data_ptr()
+        self._work = {}
+        self.loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    def set_lr(self, lr: float):
+        self.net.lr = float(lr)
+
+    def _grid(self, x: torch.Tensor) -> Grid:
+        if x.dim() not in (2, 3):
+            raise ValueError("fields are (ny, nx) or (batch, ny, nx)")
+        return make_grid(x.shape, 2, x.dtype)
+
+    def _workspace(self, g: Grid, training: bool) -> torch.Tensor:
+        key = (int(g.n[0]), int(g.n[1]), int(g.batch), int(g.dtype), training)
+        w = self._work.get(key)
+        if w is None:
+            n = self.lib.warmstart_workspace_bytes(ctypes.byref(self.net), ctypes.byref(g), int(training))
+            if n == 0:
+                raise GdError(-1, "bad network or grid")
+            w = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+            self._work[key] = w
+        return w
+
+    def forward(self, ubar: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """u0 for every field of ubar (launch only, no synchronisation)."""
+        g = self._grid(ubar)
+        u0 = torch.empty_like(ubar) if out is None else out
+        w = self._workspace(g, False)
+        _check(self.lib.warmstart_forward(ctypes.byref(self.net), ctypes.byref(g), _dev_ptr(ubar), _dev_ptr(u0),
+                                          w.data_ptr(), w.numel(), _stream_handle(stream)))
+        return u0
+
+    def train_step(self, ubar: torch.Tensor, u: torch.Tensor, stream=None) -> torch.Tensor:
+        """One Adam step on the pairs (ubar, u); returns the device loss (before
+        the update).  Launch only."""
+        if ubar.shape != u.shape or ubar.dtype != u.dtype:
+            raise ValueError("ubar and u must match")
+        g = self._grid(ubar)
+        w = self._workspace(g, True)
+        _check(self.lib.warmstart_train_step(ctypes.byref(self.net), ctypes.byref(g), _dev_ptr(ubar), _dev_ptr(u),
+                                             w.data_ptr(), w.numel(), self.loss.data_ptr(), _stream_handle(stream)))
+        return self.loss
 
 
 def deconvolve(solver: str, ubar: torch.Tensor, max_iter: int, tol: float = 0.0, ndim: int = 2, init: str = "ubar",

@@ -1,0 +1,137 @@
+"""Learned warm start on the GPU (warmstart_forward / warmstart_train_step)
+against the FP64 network reference in oracle/cnn.py.
+
+Tolerances: the GPU stores weights, activations and activation gradients in
+bfloat16 and accumulates in FP32.  The reference run with `emulate_bf16`
+rounds the same quantities the same way, so the two differ only by FP32
+accumulation order, which flips an occasional bfloat16 rounding (one unit in
+the 8th bit): relative L2 <= 3e-3 on the network output and the loss, <= 2e-2
+on each layer's weight gradient (sums of many such products).  Against the
+unrounded FP64 reference the output must agree to bfloat16 precision (2e-2).
+The benefit of training is empirical (parity unpinned): only convergence of
+the warm-started solve is asserted.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import rel_l2, to_dev
+from oracle import cnn
+from paper_1707_09177_amd import gdecon, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def params_with_bias(seed):
+    p = synth.cnn_init_params(seed)
+    r = np.random.default_rng(seed + 100)
+    for W, b in cnn.unpack(p):
+        b[:] = 0.05 * r.standard_normal(b.shape)
+    return p
+
+
+def fields(shape, B, seed, dtype=np.float32):
+    u = np.stack([np.random.default_rng(seed + i).standard_normal(shape) for i in range(B)])
+    u = np.stack([oracle.filter(x, 2) for x in u])      # smooth-ish truth
+    ub = np.stack([oracle.filter(x, 2) for x in u])
+    return ub.astype(dtype).astype(np.float64), u.astype(dtype).astype(np.float64)
+
+
+@pytest.mark.parametrize("shape", [(40, 72), (1, 1), (3, 5), (64, 64), (33, 100)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_forward_matches_reference(shape, dtype):
+    p = params_with_bias(1)
+    ub, _ = fields(shape, 2, 10)
+    ws = gdecon.WarmStart(p)
+    u0 = ws.forward(to_dev(ub, dtype))
+    torch.cuda.synchronize()
+    got = u0.double().cpu().numpy()
+    ref = cnn.forward(p, ub, emulate_bf16=True)
+    s = ref["s"][:, None, None]
+    y_got, y_ref = (got - ub) / s, ref["y"]
+    assert rel_l2(y_got, y_ref) <= 3e-3, rel_l2(y_got, y_ref)
+    exact = cnn.forward(p, ub)["y"]
+    assert rel_l2(y_got, exact) <= 2e-2
+    # deterministic
+    u1 = ws.forward(to_dev(ub, dtype))
+    torch.cuda.synchronize()
+    assert torch.equal(u0, u1)
+
+
+def test_gradients_loss_and_adam_match_reference():
+    p = params_with_bias(2)
+    ub, u = fields((48, 80), 3, 20)
+    ws = gdecon.WarmStart(p, lr=1e-3)
+    loss = ws.train_step(to_dev(ub, torch.float32), to_dev(u, torch.float32))
+    torch.cuda.synchronize()
+    g_gpu = ws.grad.double().cpu().numpy()
+    l_ref, g_ref = cnn.loss_and_grad(p, ub, u, emulate_bf16=True)
+    assert abs(loss.item() - l_ref) <= 3e-3 * l_ref
+    off = 0
+    for li, (W, b) in enumerate(cnn.unpack(p)):
+        n = W.size + b.size
+        e = rel_l2(g_gpu[off:off + n], g_ref[off:off + n])
+        assert e <= 2e-2, (li, e)
+        off += n
+    # the Adam update is applied to the GPU's own gradient
+    p32 = p.astype(np.float32).astype(np.float64)
+    want, _, _ = cnn.adam_step(p32, np.zeros_like(p32), np.zeros_like(p32), g_gpu, 1, lr=1e-3)
+    got = ws.params.double().cpu().numpy()
+    np.testing.assert_allclose(got, want, rtol=1e-5, atol=1e-7)
+    assert int(ws.step.item()) == 1
+    # second step: bias corrections use step 2, moments carried over
+    m = 0.1 * g_gpu
+    v = 0.001 * g_gpu * g_gpu
+    ws.train_step(to_dev(ub, torch.float32), to_dev(u, torch.float32))
+    torch.cuda.synchronize()
+    g2 = ws.grad.double().cpu().numpy()
+    want2, _, _ = cnn.adam_step(got, m, v, g2, 2, lr=1e-3)
+    np.testing.assert_allclose(ws.params.double().cpu().numpy(), want2, rtol=1e-5, atol=1e-7)
+    assert int(ws.step.item()) == 2
+
+
+def test_train_step_deterministic():
+    p = params_with_bias(3)
+    ub, u = fields((32, 64), 2, 30)
+    a, b = gdecon.WarmStart(p), gdecon.WarmStart(p)
+    for _ in range(3):
+        la = a.train_step(to_dev(ub, torch.float32), to_dev(u, torch.float32)).clone()
+        lb = b.train_step(to_dev(ub, torch.float32), to_dev(u, torch.float32)).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a.params, b.params) and torch.equal(la, lb)
+
+
+def test_training_lowers_loss_and_warm_start_solves():
+    """Empirical: a short training run on k^-3 crops lowers the loss; the
+    trained network's u0 then starts BiCGSTAB, which still converges with a
+    true residual within the stopping tolerance."""
+    crops = synth.training_pairs(16, n=256, crop=64)
+    u = torch.from_numpy(np.stack(crops)).cuda()
+    ub = gdecon.filter_apply(u, ndim=2)
+    ws = gdecon.WarmStart(synth.cnn_init_params(0), lr=2e-3)
+    first = ws.train_step(ub, u).item()
+    for _ in range(150):
+        ws.train_step(ub, u)
+    last = ws.train_step(ub, u).item()
+    assert last < 0.7 * first, (first, last)
+    test = torch.from_numpy(synth.field_2d(128, synth.spectrum_kraichnan, 4.0, 32.0, synth.rng_for(5, 99),
+                                           np.float32)).cuda()[None]
+    tub = gdecon.filter_apply(test, ndim=2)
+    u0 = ws.forward(tub)
+    uw, infos_w, _ = gdecon.deconvolve("bicgstab", tub, 100, tol=1e-6, init="given", u0=u0)
+    _, infos_b, _ = gdecon.deconvolve("bicgstab", tub, 100, tol=1e-6)
+    print("iterations: warm start", infos_w[0]["iters"], "ubar start", infos_b[0]["iters"])
+    assert infos_w[0]["status_name"] == "CONVERGED"
+    assert infos_w[0]["r_true"] <= 2e-6 * infos_w[0]["r_ref"]
+
+
+def test_rejects_3d_and_bad_shapes():
+    ws = gdecon.WarmStart(synth.cnn_init_params(0))
+    g = gdecon.make_grid((4, 8, 8), 3, torch.float32)
+    lib = gdecon.load()
+    assert lib.warmstart_workspace_bytes(ws.net, g, 0) == 0
+    x = torch.zeros((4, 8, 8), device="cuda")
+    assert lib.warmstart_forward(ws.net, g, x.data_ptr(), torch.zeros_like(x).data_ptr(), x.data_ptr(), 1 << 20,
+                                 None) == -1
+    assert "2D" in lib.gd_last_error().decode()
