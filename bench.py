@@ -58,6 +58,10 @@ WORKLOADS = {
                     "and 3D n=16*U{4..12} (k^-5/3 on 2<=k<=0.3125n) with probability 1/2, BiCGSTAB to rel. residual "
                     "1e-6 (FP32 storage, FP64 dots/scalars), launch autotuned before timing",
                cfg=4, count=200, key="uneven200", batch=True),
+    "c5": dict(desc="learned warm start: 2D CNN trained on the GPU (Adam, 128^2 crops of 512^2 k^-3 fields), "
+                    "evaluated on 64 held-out 1024^2 fields (k^-3 on 4<=k<=256): BiCGSTAB to rel. residual 1e-6 "
+                    "from the CNN start (network forward included) vs the ubar and zero starts",
+               cfg=5, count=64, n=1024, key="warmstart64", warm=True),
     "c3": dict(desc="3D periodic 256^3 x 3 velocity components, E(k)~k^-5/3 on 2<=k<=80, divergence-free, "
                     "BiCGSTAB per component to rel. residual 1e-6 (FP32 storage, FP64 dots/scalars)",
                cfg=3, ndim=3, n=256, count=3, key="256cube_x3"),
@@ -206,6 +210,82 @@ def main_batch(args, w, torch, gd, dev):
     print(json.dumps(out))
 
 
+def main_warm(args, w, torch, gd, dev):
+    """Train the warm-start network, then time BiCGSTAB from three starts."""
+    from paper_1707_09177_amd import synth
+    crops = synth.training_pairs(256, n=512, crop=128)
+    ut = torch.from_numpy(np.stack(crops)).to(dev)
+    ubt = gd.filter_apply(ut, ndim=2)
+    net = gd.WarmStart(synth.cnn_init_params(0), lr=1e-3)
+    steps_train, batch = args.train_steps, 32
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    first = None
+    for k in range(steps_train):
+        lo = (k * batch) % len(crops)
+        loss = net.train_step(ubt[lo:lo + batch], ut[lo:lo + batch])
+        if k == 0:
+            first = loss.item()
+        if k == (2 * steps_train) // 3:
+            net.set_lr(3e-4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    last = loss.item()
+    fields = np.stack([synth.field_2d(w["n"], synth.spectrum_kraichnan, 4.0, w["n"] / 4.0,
+                                      synth.rng_for(5, 50000 + i), np.float32) for i in range(w["count"])])
+    u_eval = torch.from_numpy(fields).to(dev)
+    ubar = gd.filter_apply(u_eval, ndim=2)
+    npts = int(ubar.numel())
+    d = gd.Deconvolver(ubar.shape, 2, ubar.dtype, "bicgstab")
+    out = torch.empty_like(ubar)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, e in evs:
+            a.record(stream)
+            fn()
+            e.record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(e) for a, e in evs]))
+
+    res = {}
+    for start in ("ubar", "zero"):
+        ms = timed(lambda: d.solve(ubar, 500, 1e-6, init=start, out=out), args.steps)
+        inf = d.solve(ubar, 500, 1e-6, init=start, out=out).info()
+        res[start] = dict(ms=ms, iters_mean=float(np.mean([i["iters"] for i in inf])),
+                          status=sorted({i["status_name"] for i in inf}),
+                          worst_true_rel_residual=max(i["r_true"] / i["r_ref"] for i in inf))
+    u0 = torch.empty_like(ubar)
+
+    def cnn_solve():
+        net.forward(ubar, out=u0)
+        out.copy_(u0)
+        d.solve(ubar, 500, 1e-6, init="given", out=out)
+
+    ms_fwd = timed(lambda: net.forward(ubar, out=u0), args.steps)
+    ms_total = timed(cnn_solve, args.steps)
+    net.forward(ubar, out=out)
+    inf = d.solve(ubar, 500, 1e-6, init="given", out=out).info()
+    res["cnn"] = dict(ms=ms_total, ms_forward=ms_fwd, iters_mean=float(np.mean([i["iters"] for i in inf])),
+                      status=sorted({i["status_name"] for i in inf}),
+                      worst_true_rel_residual=max(i["r_true"] / i["r_ref"] for i in inf),
+                      r0_over_ref_mean=float(np.mean([i["r0"] / i["r_ref"] for i in inf])))
+    m = res["cnn"]
+    out_line = {
+        "metric": METRIC, "value": npts / (m["ms"] * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": m["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": w["desc"], "fields": w["count"], "grid": [w["n"], w["n"]], "points": npts,
+                   "solver": "bicgstab", "tol": 1e-6, "train_steps": steps_train, "train_batch": batch},
+        "warmstart": {"train_seconds": train_s, "loss_first": first, "loss_last": last, "starts": res,
+                      "cnn_vs_ubar_time": res["ubar"]["ms"] / m["ms"]},
+    }
+    print(json.dumps(out_line))
+
+
 def time_solver(gd, torch, ubar, w, solver, steps, warmup, tol=1e-6, max_iter=500):
     d = gd.Deconvolver(ubar.shape, w["ndim"], ubar.dtype, solver)
     out = torch.empty_like(ubar)
@@ -249,6 +329,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--solvers", default="bicgstab,cg,vc")
+    ap.add_argument("--train-steps", type=int, default=1500, help="warm-start workload: Adam steps")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (x5): the reference kernel that scales "
                          "FETCH_SIZE / WRITE_SIZE counter readings to bytes")
@@ -275,6 +356,8 @@ def main():
     w = WORKLOADS[args.workload]
     if w.get("batch"):
         return main_batch(args, w, torch, gd, dev)
+    if w.get("warm"):
+        return main_warm(args, w, torch, gd, dev)
     u32, ubar = make_inputs(w, torch, gd, dev)
     npts = int(ubar.numel())
     itemsize = ubar.element_size()

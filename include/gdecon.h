@@ -234,10 +234,11 @@ void gd_tune_reset(void);
  * it to a solver with GD_INIT_GIVEN (the solver itself is unchanged; the
  * plain start stays the fallback):
  *     s  = RMS of ubar over the field,  x0 = ubar / s,
- *     a_l = relu(conv_l(a_{l-1}))  for l = 1..5,   y = conv_6(a_5),
+ *     a_l = relu(conv_l(a_{l-1}))  for l = 1..5,   y = G conv_6(a_5),
  *     u0 = ubar + s * y,
  * conv_l a periodic 3x3 cross-correlation with bias, channels
- * 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1.  Activations are bfloat16, the 32 -> 32
+ * 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, G the deconvolution filter (so the
+ * correction lies in the range of G, like the paper's start ubar).  Activations are bfloat16, the 32 -> 32
  * layers run on the matrix cores with FP32 accumulation.  Only 2D fields
  * (gd_grid.ndim == 2, batch = number of fields) are supported.
  *

@@ -11,13 +11,17 @@ u0 with a residual correction predicted by a small convolutional network:
     s   = RMS of ubar over the sample
     x0  = ubar / s                                   (1 channel)
     a_l = relu(conv_l(a_{l-1}))       l = 1 .. L-1   (C channels)
-    y   = conv_L(a_{L-1})                            (1 channel, no activation)
+    z   = conv_L(a_{L-1})                            (1 channel, no activation)
+    y   = G z                                        (the deconvolution filter)
     u0  = ubar + s * y
 
 conv_l is a periodic 3x3 cross-correlation with bias (the fields are periodic,
-like the filter G).  Training minimises the mean over all points of
-(y - t)^2 with t = (u - ubar) / s, the per-sample normalised correction, with
-Adam.
+like the filter G).  The final G keeps the correction in the range of G, as
+the paper's own start u0 = ubar is: without it, the correction carries
+content where G's transfer function nearly vanishes (next to the Nyquist
+planes), the one place where the Krylov solvers converge slowly.  Training
+minimises the mean over all points of (y - t)^2 with t = (u - ubar) / s, the
+per-sample normalised correction, with Adam.
 
 Layouts: activations (B, ny, nx, C) (channels fastest); the weights of layer
 l are W[cout][tap][cin] with tap = 3 * (dy + 1) + (dx + 1), dy, dx in
@@ -31,6 +35,8 @@ network stores them in bfloat16; everything else stays FP64.
 from __future__ import annotations
 
 import numpy as np
+
+from . import filter as g_filter
 
 TAPS = [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
 
@@ -123,7 +129,7 @@ def forward(params, ubar, channels=32, layers=6, emulate_bf16=False):
     for li, (W, b) in enumerate(P):
         z = conv(a, W, b)
         if li == len(P) - 1:
-            y = z[..., 0]
+            y = g_filter(z[..., 0], 2)
             break
         a = np.maximum(z, 0.0)
         if emulate_bf16:
@@ -142,7 +148,7 @@ def loss_and_grad(params, ubar, u, channels=32, layers=6, emulate_bf16=False):
     r = f["y"] - t
     n = r.size
     loss = float(np.sum(r * r) / n)
-    g = (2.0 / n) * r[..., None]            # dL/dy, one channel
+    g = g_filter((2.0 / n) * r, 2)[..., None]   # dL/dz = G dL/dy (G is symmetric)
     grads = [None] * len(f["P"])
     ins = [f["x0"]] + f["acts"]
     for li in range(len(f["P"]) - 1, -1, -1):

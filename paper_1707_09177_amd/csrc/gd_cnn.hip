@@ -7,7 +7,10 @@
 //
 // Network (2D): 6 layers of periodic 3x3 cross-correlation with bias,
 // 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 channels, ReLU after every layer but the
-// last; s is the per-sample RMS of ubar.  Weights of layer l are
+// last, then the deconvolution filter G itself, u0 = ubar + s * G z: the
+// correction stays in the range of G like the paper's start u0 = ubar, so it
+// adds nothing where G's transfer function vanishes (where the Krylov solvers
+// are slowest); s is the per-sample RMS of ubar.  Weights of layer l are
 // W[cout][tap][cin] (tap = 3 (dy + 1) + (dx + 1)) followed by bias[cout], all
 // layers packed into one FP32 parameter vector.
 //
@@ -203,11 +206,8 @@ __global__ __launch_bounds__(256) void k_conv_mid(const bf16 *in, const bf16 *wm
     }
 }
 
-// layer 6: 32 channels -> 1, no activation.  Writes y (training) and/or
-// u0 = ubar + s * y.
-template <typename T>
-__global__ void k_conv_out(const bf16 *a, const bf16 *w6, const float *b6, const T *ub, const double *s, float *y_out,
-                           T *u0, int H, int W, int64_t N) {
+// layer 6: 32 channels -> 1, no activation: z
+__global__ void k_conv_out(const bf16 *a, const bf16 *w6, const float *b6, float *z, int H, int W, int64_t N) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int64_t HW = (int64_t)H * W;
@@ -223,8 +223,40 @@ __global__ void k_conv_out(const bf16 *a, const bf16 *w6, const float *b6, const
 #pragma unroll
         for (int c = 0; c < C; ++c) acc += (float)v[c] * (float)w6[t * C + c];
     }
-    if (y_out) y_out[p] = acc;
-    if (u0) u0[p] = ub[p] + (T)(s[b] * (double)acc);
+    z[p] = acc;
+}
+
+// out = G in: the periodic trapezoidal filter (1/4, 1/2, 1/4) per axis
+__device__ __forceinline__ float g_apply(const float *in, int64_t base, int y, int x, int H, int W) {
+    const int ym = wrap(y - 1, H), yp = wrap(y + 1, H), xm = wrap(x - 1, W), xp = wrap(x + 1, W);
+    auto row = [&](int yy) {
+        const float *r = in + base + (int64_t)yy * W;
+        return 0.5f * r[x] + 0.25f * (r[xm] + r[xp]);
+    };
+    return 0.5f * row(y) + 0.25f * (row(ym) + row(yp));
+}
+
+// y = G z; writes y (training) and/or u0 = ubar + s * y
+template <typename T>
+__global__ void k_gfin(const float *z, const T *ub, const double *s, float *y_out, T *u0, int H, int W, int64_t N) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int64_t HW = (int64_t)H * W;
+    const int64_t b = p / HW;
+    const int rem = (int)(p % HW), y = rem / W, x = rem % W;
+    const float v = g_apply(z, b * HW, y, x, H, W);
+    if (y_out) y_out[p] = v;
+    if (u0) u0[p] = ub[p] + (T)(s[b] * (double)v);
+}
+
+// out = G in (the adjoint of the final filter: G is symmetric)
+__global__ void k_gfilt(const float *in, float *out, int H, int W, int64_t N) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int64_t HW = (int64_t)H * W;
+    const int64_t b = p / HW;
+    const int rem = (int)(p % HW), y = rem / W, x = rem % W;
+    out[p] = g_apply(in, b * HW, y, x, H, W);
 }
 
 // dL/dy = 2 (y - t) / N with t = (u - ubar) / s; per-block partial sums of (y - t)^2
@@ -400,7 +432,7 @@ int fail(int code, const char *fmt, ...) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t wbf, wT, s, rms, act, y, dy, dz, lpart, wpart, grad, total;
+    size_t wbf, wT, s, rms, act, z, y, dy, dyz, dz, lpart, wpart, grad, total;
     int64_t N, nblk_pix;
     int nblk_w;
 };
@@ -428,10 +460,14 @@ Layout layout(const gd_grid *g, bool training, bool own_grad) {
     L.act = o;
     const size_t actb = align_up((size_t)L.N * C * 2, 256);
     o += (training ? NL - 1 : 2) * actb;
+    L.z = o;
+    o = align_up(o + (size_t)L.N * 4, 256);
     if (training) {
         L.y = o;
         o = align_up(o + (size_t)L.N * 4, 256);
         L.dy = o;
+        o = align_up(o + (size_t)L.N * 4, 256);
+        L.dyz = o;
         o = align_up(o + (size_t)L.N * 4, 256);
         L.dz = o;
         o += 2 * actb;
@@ -505,8 +541,10 @@ int run_forward(const gd_cnn *net, const gd_grid *g, const Layout &L, char *w, c
                   (const bf16 *)nullptr, dst, H, W, tiles_x, tiles_y);
     }
     bf16 *last = train ? act(NL - 2) : act(NMID & 1);
-    GD_LAUNCH(k_conv_out<T>, dim3(pblk), dim3(256), 0, st, last, wbf + off.W[NL - 1], net->params + off.b[NL - 1], ub,
-              s, train ? (float *)(w + L.y) : (float *)nullptr, train ? (T *)nullptr : u0, H, W, N);
+    GD_LAUNCH(k_conv_out, dim3(pblk), dim3(256), 0, st, (const bf16 *)last, (const bf16 *)(wbf + off.W[NL - 1]),
+              (const float *)(net->params + off.b[NL - 1]), (float *)(w + L.z), H, W, N);
+    GD_LAUNCH(k_gfin<T>, dim3(pblk), dim3(256), 0, st, (const float *)(w + L.z), ub, (const double *)s,
+              train ? (float *)(w + L.y) : (float *)nullptr, train ? (T *)nullptr : u0, H, W, N);
     return GD_OK;
 }
 
@@ -547,9 +585,12 @@ int run_train(const gd_cnn *net, const gd_grid *g, const Layout &L, char *w, con
     GD_LAUNCH(k_loss<T>, dim3(pblk), dim3(256), 0, st, (const float *)(w + L.y), ub, u, s, dy,
               (double *)(w + L.lpart), HW, N);
     GD_LAUNCH(k_loss_fin, dim3(1), dim3(64), 0, st, (const double *)(w + L.lpart), L.nblk_pix, N, loss);
+    // through the final filter: dL/dz = G dL/dy
+    float *dyz = (float *)(w + L.dyz);
+    GD_LAUNCH(k_gfilt, dim3(pblk), dim3(256), 0, st, (const float *)dy, dyz, H, W, N);
     // layer 6
-    if ((rc = wgrad_layer<C, 1, T>(g, L, w, act(NL - 2), ub, s, nullptr, dy, grad + off.W[NL - 1], st))) return rc;
-    GD_LAUNCH(k_out_bwd, dim3(pblk), dim3(256), 0, st, (const float *)dy, (const bf16 *)(wbf + off.W[NL - 1]),
+    if ((rc = wgrad_layer<C, 1, T>(g, L, w, act(NL - 2), ub, s, nullptr, dyz, grad + off.W[NL - 1], st))) return rc;
+    GD_LAUNCH(k_out_bwd, dim3(pblk), dim3(256), 0, st, (const float *)dyz, (const bf16 *)(wbf + off.W[NL - 1]),
               (const bf16 *)act(NL - 2), dz(0), H, W, N);
     // layers 5 .. 2: dz(k) holds the gradient at the output of layer l
     const int tiles_x = (W + TX - 1) / TX, tiles_y = (H + TY - 1) / TY;

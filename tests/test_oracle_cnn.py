@@ -8,6 +8,7 @@ rounding checked against hand-made bit patterns.
 import numpy as np
 import pytest
 
+import oracle
 from oracle import cnn
 from paper_1707_09177_amd import synth
 
@@ -104,14 +105,27 @@ def test_scale_equivariance():
 
 def test_identity_path_network():
     """Delta kernels and positive pre-activations carry x0 straight through:
-    with every layer passing channel 0's centre tap, y = x0 and u0 = 2 ubar."""
+    with every layer passing channel 0's centre tap, z = x0, so
+    u0 = ubar + G ubar."""
     p = np.zeros(cnn.param_count())
     layers = cnn.unpack(p)
     ub = np.abs(rng(13).standard_normal((1, 5, 6))) + 0.1   # positive, so the ReLUs pass it
     for W, b in layers:
         W[0, 4, 0] = 1.0
     f = cnn.forward(p, ub)
-    np.testing.assert_allclose(f["u0"], 2 * ub, rtol=1e-14)
+    np.testing.assert_allclose(f["u0"], ub + oracle.filter(ub, 2), rtol=1e-14)
+
+
+def test_correction_lies_in_the_range_of_g():
+    """On an even grid the stencil's transfer function vanishes on the Nyquist
+    lines, so the correction u0 - ubar has no content there (checked by FFT)."""
+    p = synth.cnn_init_params(6)
+    p[cnn.param_count() - 1] = 0.2
+    ub = rng(14).standard_normal((2, 8, 6))
+    corr = cnn.forward(p, ub)["u0"] - ub
+    F = np.fft.fft2(corr)
+    assert np.max(np.abs(F[:, 4, :])) <= 1e-12 * np.max(np.abs(F))
+    assert np.max(np.abs(F[:, :, 3])) <= 1e-12 * np.max(np.abs(F))
 
 
 def test_adam_first_step_closed_form():
