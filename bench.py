@@ -286,9 +286,10 @@ def main_warm(args, w, torch, gd, dev):
     print(json.dumps(out_line))
 
 
-def time_solver(gd, torch, ubar, w, solver, steps, warmup, tol=1e-6, max_iter=500):
+def time_solver(gd, torch, ubar, w, solver, steps, warmup, tol=1e-6, max_iter=500, tune=True):
     d = gd.Deconvolver(ubar.shape, w["ndim"], ubar.dtype, solver)
     out = torch.empty_like(ubar)
+    tuned = gd.autotune(solver, ubar, ndim=w["ndim"], out=out) if tune else None   # first-call tuning, untimed
     for _ in range(warmup):
         d.solve(ubar, max_iter, tol, out=out)
     torch.cuda.synchronize()
@@ -304,7 +305,8 @@ def time_solver(gd, torch, ubar, w, solver, steps, warmup, tol=1e-6, max_iter=50
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     ms = [a.elapsed_time(b) for a, b in evs]
-    return dict(info=info, ms_events=float(np.mean(ms)), ms_min=float(np.min(ms)), wall_ms=wall * 1e3, u=out)
+    return dict(info=info, ms_events=float(np.mean(ms)), ms_min=float(np.min(ms)), wall_ms=wall * 1e3, u=out,
+                tune=tuned, launch=gd.last_launch())
 
 
 def cpu_baseline(w, u32, tol=1e-6, sample_fields=12):
@@ -328,6 +330,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tune", action="store_true", help="use the default launch configuration")
     ap.add_argument("--solvers", default="bicgstab,cg,vc")
     ap.add_argument("--train-steps", type=int, default=1500, help="warm-start workload: Adam steps")
     ap.add_argument("--copy-calib", action="store_true",
@@ -365,7 +368,7 @@ def main():
     results = {}
     for s in args.solvers.split(","):
         r = time_solver(gd, torch, ubar, w, s, args.steps if s == "bicgstab" else max(3, args.steps // 2),
-                        args.warmup)
+                        args.warmup, tune=not args.no_tune)
         iters = [i["iters"] for i in r["info"]]
         st = {i["status_name"] for i in r["info"]}
         worst_true = max(i["r_true"] / i["r_ref"] for i in r["info"])
@@ -374,7 +377,7 @@ def main():
         results[s] = dict(ms=r["ms_events"], ms_min=r["ms_min"], wall_ms=r["wall_ms"], iters=iters,
                           status=sorted(st), worst_true_rel_residual=worst_true,
                           points_per_s=npts / (r["ms_events"] * 1e-3), accesses_per_point=acc,
-                          algorithmic_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS)
+                          algorithmic_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS, tune=r["tune"], launch=r["launch"])
         del r
     main_s = "bicgstab" if "bicgstab" in results else list(results)[0]
     m = results[main_s]

@@ -192,7 +192,12 @@ double grid_weight(const gd_grid *g) {
     return w;
 }
 
-Geo make_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int vw, int R, int64_t L) {
+// Tile geometry of a field.  Every column (x segment x row tile) is cut into
+// long tiles of L planes and, over roughly the last tail_pct percent of its
+// planes, short tiles of L2 = L / 4 planes (at least kMinL): the short tiles
+// are claimed last, so the end of a sweep, when waves finish at different
+// times, is made of work that finishes quickly.
+Geo make_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int vw, int R, int64_t L, int tail_pct) {
     Geo g;
     g.nx = nx;
     if (ndim == 2) {
@@ -208,14 +213,31 @@ Geo make_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int vw, int R, int64_
     }
     g.nxs = (nx + (int64_t)WAVE * vw - 1) / ((int64_t)WAVE * vw);
     g.L = L;
+    const int64_t cols = g.nxs * g.nrs;
+    const int64_t L2 = std::max<int64_t>(kMinL, L / 4);
+    const int64_t nlong = tail_pct > 0 ? (g.nmarch * (100 - tail_pct) / 100) / L : 0;
+    if (tail_pct > 0 && L2 < L && nlong >= 1 && nlong * L < g.nmarch) {
+        g.L2 = L2;
+        g.mb = nlong * L;
+        g.nbig = cols * nlong;
+    } else {  // long tiles only
+        g.L2 = L;
+        g.mb = g.nmarch;
+        g.nbig = cols * ((g.nmarch + L - 1) / L);
+    }
     return g;
 }
 
-int64_t geo_tiles(const Geo &g) { return g.nxs * g.nrs * ((g.nmarch + g.L - 1) / g.L); }
+int64_t geo_tiles(const Geo &g) {
+    const int64_t rest = g.nmarch - g.mb;
+    return g.nbig + (rest > 0 ? g.nxs * g.nrs * ((rest + g.L2 - 1) / g.L2) : 0);
+}
 
 // Upper bound on the tile count of any shape the library may pick for a field.
 int64_t max_tiles(int ndim, int64_t nx, int64_t ny, int64_t nz) {
-    return geo_tiles(make_geo(ndim, nx, ny, nz, 1, 1, kMinL));
+    // long tiles cover at most nmarch / kMinL segments, short ones add at most one more
+    const Geo g = make_geo(ndim, nx, ny, nz, 1, 1, kMinL, 0);
+    return g.nxs * g.nrs * ((g.nmarch + kMinL - 1) / kMinL + 1);
 }
 
 size_t workspace_layout(const gd_grid *g, int solver, int64_t ninst, int64_t tiles_total_max, size_t *off_st,
@@ -296,6 +318,7 @@ bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
 struct TuneCfg {
     int tpw = kTilesPerWave;
     int rows = 0;
+    int tail = kTailPct;
 };
 
 std::mutex g_tune_mu;
@@ -318,11 +341,13 @@ void tune_load_locked() {
     char line[1024];
     while (fgets(line, sizeof line, fp)) {
         char key[900];
-        int tpw = 0, rows = 0;
-        if (sscanf(line, "%899s %d %d", key, &tpw, &rows) == 3 && tpw >= 1 && tpw <= 64 && rows >= 0 && rows <= 4) {
+        int tpw = 0, rows = 0, tail = 0;
+        if (sscanf(line, "%899s %d %d %d", key, &tpw, &rows, &tail) == 4 && tpw >= 1 && tpw <= 64 && rows >= 0 &&
+            rows <= 4 && tail >= 0 && tail <= 50) {
             TuneCfg c;
             c.tpw = tpw;
             c.rows = rows;
+            c.tail = tail;
             g_tune[key] = c;
         }
     }
@@ -344,7 +369,7 @@ void tune_store(const std::string &key, const TuneCfg &c) {
     g_tune[key] = c;
     if (const char *f = tune_file()) {
         if (FILE *fp = fopen(f, "a")) {
-            fprintf(fp, "%s %d %d\n", key.c_str(), c.tpw, c.rows);
+            fprintf(fp, "%s %d %d %d\n", key.c_str(), c.tpw, c.rows, c.tail);
             fclose(fp);
         }
     }
@@ -417,7 +442,7 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
     }
     I.hist = o->history;
     I.info = info;
-    I.geo = make_geo(g->ndim, nx, ny, nz, ts.vw, ts.R, ts.L);
+    I.geo = make_geo(g->ndim, nx, ny, nz, ts.vw, ts.R, ts.L, cfg.tail);
     I.tile0 = 0;
     I.ntiles = geo_tiles(I.geo);
     I.hw = grid_weight(g);
@@ -431,6 +456,7 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
     P.stride_bytes = npts * (int64_t)tsize;
     P.tiles_per_inst = I.ntiles;
     P.total_tiles = I.ntiles * g->batch;
+    P.big_total = I.geo.nbig * g->batch;
     P.wait_ticks = wait_ticks_of(o);
     P.tol = o->tol;
     P.ninst = (int32_t)g->batch;
@@ -457,7 +483,7 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
 // Instance descriptors are written into the workspace by this kernel, whose
 // argument carries up to kTableChunk of them: the values travel with the
 // launch itself, so no host buffer has to outlive the call or a captured graph.
-constexpr int kTableChunk = 16;
+constexpr int kTableChunk = 12;
 struct TableChunk {
     Inst inst[kTableChunk];
     Inst *dst;
@@ -608,7 +634,7 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
     const double pts_per_tile = std::max(1.0, ptot / target_tiles);
     char *w = (char *)work;
     size_t voff = lay.off_vec;
-    int64_t tile0 = 0;
+    int64_t tile0 = 0, big0 = 0, small0 = 0;
     for (int i = 0; i < count; ++i) {
         const gd_instance &d = list[i];
         Inst &I = tab[i];
@@ -627,10 +653,14 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
         voff += (size_t)nvec_of(solver) * vb;
         I.hist = d.history;
         I.info = info + i;
-        I.geo = make_geo(d.ndim, nx, ny, nz, I.vw, I.R, L);
+        I.geo = make_geo(d.ndim, nx, ny, nz, I.vw, I.R, L, cfg.tail);
         I.tile0 = tile0;
         I.ntiles = geo_tiles(I.geo);
         tile0 += I.ntiles;
+        I.b0 = big0;
+        I.s0 = small0;
+        big0 += I.geo.nbig;
+        small0 += I.ntiles - I.geo.nbig;
         gd_grid gi;
         std::memset(&gi, 0, sizeof gi);
         gi.ndim = d.ndim;
@@ -661,6 +691,7 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
     P.sync = (Sync *)w;
     P.part = (double *)(w + lay.off_part);
     P.total_tiles = tile0;
+    P.big_total = big0;
     P.wait_ticks = wait_ticks_of(o);
     P.tol = o->tol;
     P.ninst = count;
@@ -726,6 +757,8 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
         out->best = best;
         out->tiles_per_wave = cands[best].tpw;
         out->rows = cands[best].rows;
+        out->tail_pct = cands[best].tail;
+        out->reserved = 0;
         out->best_ms = best_ms;
         out->default_ms = default_ms;
     }
@@ -742,7 +775,8 @@ gd_opts trial_opts() {
     return o;
 }
 
-const int kTpwCands[] = {kTilesPerWave, 2, 4, 6, 8};
+const int kTpwCands[] = {kTilesPerWave, 1, 3, 4, 6};
+const int kTailCands[] = {kTailPct, 0, 25};
 
 }  // namespace gd
 
@@ -765,7 +799,7 @@ int filter_apply(const gd_grid *g, const void *x, void *y, void *stream) {
     std::memset(&I, 0, sizeof I);
     I.ubar = x;
     I.u = y;
-    I.geo = make_geo(g->ndim, nx, ny, nz, ts.vw, ts.R, ts.L);
+    I.geo = make_geo(g->ndim, nx, ny, nz, ts.vw, ts.R, ts.L, 0);
     I.ndim = g->ndim;
     I.vw = ts.vw;
     I.R = ts.R;
@@ -833,12 +867,14 @@ int deconvolve_autotune(int32_t solver, const gd_grid *g, const void *ubar, void
     std::vector<int> rows = {0};
     if (g->ndim == 3) rows = {0, 1, 2, 4};
     for (int r : rows)
-        for (int t : kTpwCands) {
-            TuneCfg c;
-            c.tpw = t;
-            c.rows = r;
-            cands.push_back(c);
-        }
+        for (int t : kTpwCands)
+            for (int tl : kTailCands) {
+                TuneCfg c;
+                c.tpw = t;
+                c.rows = r;
+                c.tail = tl;
+                cands.push_back(c);
+            }
     // every candidate must launch; a shape the field cannot use falls back to
     // the default rule inside solve_uniform, so duplicates are harmless
     auto launch = [&](const TuneCfg &c) { return solve_uniform(solver, g, ubar, u, &o, work, wb, info, stream, &c); };
@@ -853,11 +889,13 @@ int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *
                               size_t wb, gd_info *info, void *stream, gd_tune_info *out) {
     const gd_opts o = trial_opts();
     std::vector<TuneCfg> cands;
-    for (int t : kTpwCands) {
-        TuneCfg c;
-        c.tpw = t;
-        cands.push_back(c);
-    }
+    for (int t : kTpwCands)
+        for (int tl : kTailCands) {
+            TuneCfg c;
+            c.tpw = t;
+            c.tail = tl;
+            cands.push_back(c);
+        }
     auto launch = [&](const TuneCfg &c) {
         return solve_batch(solver, dtype, list, count, &o, work, wb, info, stream, &c);
     };

@@ -75,7 +75,10 @@ struct Geo {
     int64_t plane;   // elements per plane (nx in 2D, nx*ny in 3D)
     int64_t nxs;     // x segments of WAVE*VW columns
     int64_t nrs;     // row tiles of R rows (1 in 2D)
-    int64_t L;       // planes per tile along the march axis
+    int64_t L;       // planes per long tile along the march axis
+    int64_t L2;      // planes per short tile (the tail of every column)
+    int64_t mb;      // planes [0, mb) are cut into long tiles, [mb, nmarch) into short ones
+    int64_t nbig;    // long tiles of the field (they come first in the tile order)
 };
 
 template <int N> struct Arr { static constexpr int n = N > 0 ? N : 1; };
@@ -89,18 +92,28 @@ struct TilePos {
 template <int VW, int R>
 __device__ __forceinline__ TilePos tile_pos(const Geo &g, int64_t lt, int lane) {
     TilePos p;
-    const int64_t xs = lt % g.nxs;
-    const int64_t rest = lt / g.nxs;
-    const int64_t rs = rest % g.nrs;
-    const int64_t ms = rest / g.nrs;
+    const int64_t cols = g.nxs * g.nrs;
+    int64_t c, mend;
+    if (lt < g.nbig) {  // long tiles: planes [0, mb)
+        c = lt % cols;
+        p.m0 = (lt / cols) * g.L;
+        mend = p.m0 + g.L;
+        if (mend > g.mb) mend = g.mb;
+    } else {  // short tiles: planes [mb, nmarch)
+        const int64_t l2 = lt - g.nbig;
+        c = l2 % cols;
+        p.m0 = g.mb + (l2 / cols) * g.L2;
+        mend = p.m0 + g.L2;
+    }
+    p.m1 = mend < g.nmarch ? mend : g.nmarch;
+    const int64_t xs = c % g.nxs;
+    const int64_t rs = c / g.nxs;
     p.x0 = xs * (WAVE * VW) + (int64_t)lane * VW;
     p.act = p.x0 < g.nx;
     p.xc = p.act ? p.x0 : g.nx - VW;  // a valid column for inactive lanes
     p.xl = p.xc == 0 ? g.nx - 1 : p.xc - 1;
     p.xr = (p.xc + VW >= g.nx) ? p.xc + VW - g.nx : p.xc + VW;
     p.row0 = rs * R;
-    p.m0 = ms * g.L;
-    p.m1 = (p.m0 + g.L < g.nmarch) ? p.m0 + g.L : g.nmarch;
     return p;
 }
 

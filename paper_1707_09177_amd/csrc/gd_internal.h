@@ -53,7 +53,8 @@ struct Inst {
     double *hist;
     gd_info *info;
     Geo geo;
-    int64_t tile0, ntiles;  // global tile range of this instance
+    int64_t tile0, ntiles;  // partial-sum slots [tile0, tile0 + ntiles) of this instance
+    int64_t b0, s0;         // first long / short tile in the claim order (table mode)
     double hw;              // h^d of the inner product
     int32_t ndim, vw, R, pad;
 };
@@ -98,7 +99,9 @@ struct Sync {
 constexpr int kSteal = NGRP;
 // Target tiles per resident wave: the dynamic pools need several per wave to
 // even out the per-wave speed differences at the end of a sweep.
-constexpr int kTilesPerWave = 3;
+constexpr int kTilesPerWave = 2;
+// Percent of every column's planes cut into short tiles (claimed last).
+constexpr int kTailPct = 15;
 // diagnostics buffer layout: 4 entries per barrier for the first 64 barriers,
 // then one claim counter per (sweep, tile)
 constexpr int64_t kTraceClaims = 256;
@@ -112,6 +115,7 @@ struct Params {
     int64_t stride_bytes; // uniform batch: bytes between consecutive fields
     int64_t tiles_per_inst;
     int64_t total_tiles;
+    int64_t big_total;    // tiles are claimed long ones first (all instances), then short ones
     int64_t wait_ticks;   // bound on one barrier wait, wall-clock ticks
     double tol;
     int32_t ninst, init, norm_ref, max_iter;
@@ -161,7 +165,7 @@ __host__ __device__ constexpr bool mixed_variant_ok(int tsize, int ndim, int vw,
 // kernel entry points, one instantiation unit per dtype and solver
 const void *solve_kernel_ptr(int dtype, int solver, int variant);
 const void *filter_kernel_ptr(int dtype, int variant);
-Geo make_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int vw, int R, int64_t L);
+Geo make_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int vw, int R, int64_t L, int tail_pct);
 int64_t geo_tiles(const Geo &g);
 
 }  // namespace gd

@@ -50,16 +50,34 @@ static __device__ __forceinline__ Inst get_inst(const Params &P, int i) {
     return I;
 }
 
+// Tile t of the claim order -> instance, and the instance's local tile lt.
+// Claims take every instance's long tiles first, then the short ones, so the
+// end of a sweep is made of short tiles.
 template <bool TABLE>
-static __device__ __forceinline__ int inst_of(const Params &P, int64_t t) {
-    if constexpr (!TABLE) return (int)(t / P.tiles_per_inst);
-    int lo = 0, hi = P.ninst - 1;
-    while (lo < hi) {  // last instance with tile0 <= t
-        const int mid = (lo + hi + 1) >> 1;
-        if (P.table[mid].tile0 <= t) lo = mid;
-        else hi = mid - 1;
+static __device__ __forceinline__ int locate(const Params &P, int64_t t, int64_t &lt) {
+    if constexpr (!TABLE) {
+        const int64_t nb = P.tmpl.geo.nbig;
+        if (t < P.big_total) {
+            lt = t % nb;
+            return (int)(t / nb);
+        }
+        const int64_t ns = P.tiles_per_inst - nb;
+        const int64_t t2 = t - P.big_total;
+        lt = nb + t2 % ns;
+        return (int)(t2 / ns);
+    } else {
+        const bool big = t < P.big_total;
+        const int64_t key = big ? t : t - P.big_total;
+        int lo = 0, hi = P.ninst - 1;
+        while (lo < hi) {  // last instance whose range starts at or before key
+            const int mid = (lo + hi + 1) >> 1;
+            const int64_t v = big ? P.table[mid].b0 : P.table[mid].s0;
+            if (v <= key) lo = mid;
+            else hi = mid - 1;
+        }
+        lt = big ? key - P.table[lo].b0 : P.table[lo].geo.nbig + (key - P.table[lo].s0);
+        return lo;
     }
-    return lo;
 }
 
 // Call f.template operator()<NDIM, VW, R>() for the instance's tile variant.
@@ -330,7 +348,8 @@ template <typename T, int VS, int PH>
 __device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch, int64_t t, int lane) {
     constexpr int nacc = PhaseNacc<PH>::v;
     const int64_t ntot = P.total_tiles;
-    const int i = inst_of<var_table(VS)>(P, t);
+    int64_t lt = 0;
+    const int i = locate<var_table(VS)>(P, t, lt);
     State *S = &P.st[i];
     // finished instances skip their tiles (a wave-uniform decision)
     if (PH != PH_TRUE && __builtin_amdgcn_readfirstlane(ld_i32(&S->done)) != 0) return;
@@ -345,14 +364,15 @@ __device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch
         c[2] = wall_clock64();
     }
     double acc[NACC] = {0.0, 0.0, 0.0};
-    tile_body<T, VS, PH>(I, S, it, t - I.tile0, acc, lane);
+    tile_body<T, VS, PH>(I, S, it, lt, acc, lane);
     if (lane == 0 && trc) P.trace[kTraceClaims + 4 * ((int64_t)epoch * ntot + t) + 3] = wall_clock64();
     // publish this tile's partials, then count the tile done
 #pragma unroll
     for (int k2 = 0; k2 < nacc; ++k2) {
         const double v = wave_sum(acc[k2]);
         // agent-coherent store (no L2 write-back of unrelated lines needed)
-        if (lane == 0) __hip_atomic_store(&P.part[t * NACC + k2], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0)
+            __hip_atomic_store(&P.part[(I.tile0 + lt) * NACC + k2], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // wait until this wave's partial stores have completed, then count the
     // tile; the completing wave reads the partials with agent-coherent loads
@@ -384,20 +404,22 @@ __device__ __forceinline__ void run_phase(const Params &P, int it, uint32_t epoc
     const uint32_t nb = gridDim.x;
     const uint32_t ng = nb < (uint32_t)NGRP ? nb : (uint32_t)NGRP;
     const uint32_t grp = blockIdx.x % NGRP;
+    // pool pl hands out tiles pl, pl + ng, pl + 2 ng, ...: every pool walks the
+    // claim order (long tiles first, short ones last) at the same pace
     for (uint32_t h = 0; h < (uint32_t)P.steal && h < ng; ++h) {
         const uint32_t pl = (grp + h) % ng;
-        const int64_t lo = ntot * pl / ng, hi = ntot * (pl + 1) / ng;
+        const int64_t cnt = (ntot - (int64_t)pl + ng - 1) / ng;  // claims in this pool
         uint32_t *ctr = &P.sync->pool[epoch & 1][pl].v;
         for (;;) {
             __syncthreads();  // every wave has read the previous round's s_base
             if (threadIdx.x == 0)
-                s_base = lo + (int64_t)__hip_atomic_fetch_add(ctr, (uint32_t)WPB, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT);
+                s_base = (int64_t)__hip_atomic_fetch_add(ctr, (uint32_t)WPB, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
             __syncthreads();
-            const int64_t base = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)(s_base - lo)) + lo;
-            if (base >= hi) break;  // same decision in every wave of the workgroup
-            const int64_t t = base + wave;
-            if (t < hi) run_tile<T, VS, PH>(P, it, epoch, t, lane);
+            const int64_t base = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)s_base);
+            if (base >= cnt) break;  // same decision in every wave of the workgroup
+            const int64_t k = base + wave;
+            if (k < cnt) run_tile<T, VS, PH>(P, it, epoch, (int64_t)pl + k * ng, lane);
         }
     }
 }
