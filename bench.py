@@ -330,7 +330,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-tune", action="store_true", help="use the default launch configuration")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="do not run the autotuner (choices come from the GD_TUNE_CACHE file when it is set, "
+                         "else the defaults)")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="run the autotuner for the workload's solvers and exit (with GD_TUNE_CACHE set, the "
+                         "choices are saved for later --no-tune runs, e.g. under a profiler)")
     ap.add_argument("--solvers", default="bicgstab,cg,vc")
     ap.add_argument("--train-steps", type=int, default=1500, help="warm-start workload: Adam steps")
     ap.add_argument("--copy-calib", action="store_true",
@@ -362,6 +367,10 @@ def main():
     if w.get("warm"):
         return main_warm(args, w, torch, gd, dev)
     u32, ubar = make_inputs(w, torch, gd, dev)
+    if args.tune_only:
+        for s in args.solvers.split(","):
+            print(json.dumps({"solver": s, "tune": gd.autotune(s, ubar, ndim=w["ndim"])}))
+        return
     npts = int(ubar.numel())
     itemsize = ubar.element_size()
 
