@@ -200,7 +200,8 @@ int deconvolve_batch(int32_t solver, int32_t dtype, const gd_instance *list, int
  *
  * Times the candidate launch configurations of a solve (tile granularity:
  * target tiles per resident wave; the share of short tiles claimed at the end
- * of every sweep; 3D rows per tile where the uniform kernels offer a choice) with short fixed-length trial solves on the caller's
+ * of every sweep; the tile-pool layout; 3D rows per tile where the uniform
+ * kernels offer a choice) with short fixed-length trial solves on the caller's
  * buffers and remembers the fastest for this (solver, dtype, sizes)
  * signature.  Later deconvolve_* / deconvolve_batch calls with the same
  * signature use it.  With the environment variable GD_TUNE_CACHE naming a
@@ -215,7 +216,8 @@ typedef struct gd_tune_info {
     int32_t tiles_per_wave;  /* chosen tile granularity */
     int32_t rows;            /* chosen 3D rows per tile (0 = default rule) */
     int32_t tail_pct;        /* chosen percent of each column cut into short tiles */
-    int32_t reserved;
+    int32_t interleave;      /* chosen tile-pool layout: 0 contiguous shares
+                                (halo reuse in L2), 1 interleaved over the XCDs */
     double best_ms;          /* trial time of the chosen configuration */
     double default_ms;       /* trial time of the untuned default */
 } gd_tune_info;

@@ -319,6 +319,7 @@ struct TuneCfg {
     int tpw = kTilesPerWave;
     int rows = 0;
     int tail = kTailPct;
+    int ilv = 0;  // interleaved tile pools
 };
 
 std::mutex g_tune_mu;
@@ -341,13 +342,14 @@ void tune_load_locked() {
     char line[1024];
     while (fgets(line, sizeof line, fp)) {
         char key[900];
-        int tpw = 0, rows = 0, tail = 0;
-        if (sscanf(line, "%899s %d %d %d", key, &tpw, &rows, &tail) == 4 && tpw >= 1 && tpw <= 64 && rows >= 0 &&
-            rows <= 4 && tail >= 0 && tail <= 50) {
+        int tpw = 0, rows = 0, tail = 0, ilv = 0;
+        if (sscanf(line, "%899s %d %d %d %d", key, &tpw, &rows, &tail, &ilv) == 5 && tpw >= 1 && tpw <= 64 &&
+            rows >= 0 && rows <= 4 && tail >= 0 && tail <= 50 && (ilv == 0 || ilv == 1)) {
             TuneCfg c;
             c.tpw = tpw;
             c.rows = rows;
             c.tail = tail;
+            c.ilv = ilv;
             g_tune[key] = c;
         }
     }
@@ -369,7 +371,7 @@ void tune_store(const std::string &key, const TuneCfg &c) {
     g_tune[key] = c;
     if (const char *f = tune_file()) {
         if (FILE *fp = fopen(f, "a")) {
-            fprintf(fp, "%s %d %d %d\n", key.c_str(), c.tpw, c.rows, c.tail);
+            fprintf(fp, "%s %d %d %d %d\n", key.c_str(), c.tpw, c.rows, c.tail, c.ilv);
             fclose(fp);
         }
     }
@@ -466,6 +468,7 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
     P.hist_stride = o->max_iter + 1;
     P.steal = kSteal;
     if (const char *e = getenv("GD_STEAL")) P.steal = std::max(0, atoi(e));
+    P.interleave = cfg.ilv;
     P.trace = g_trace;
     P.trace_cap = g_trace_cap;
     rc = launch_solve(P, kern, blocks_cap, (hipStream_t)stream);
@@ -700,6 +703,7 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
     P.max_iter = o->max_iter;
     P.steal = kSteal;
     if (const char *e = getenv("GD_STEAL")) P.steal = std::max(0, atoi(e));
+    P.interleave = cfg.ilv;
     P.trace = g_trace;
     P.trace_cap = g_trace_cap;
     rc = launch_solve(P, kern, blocks_cap, (hipStream_t)stream);
@@ -713,6 +717,8 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
 }
 
 // ---- autotuner ---------------------------------------------------------------
+
+constexpr double kTuneMargin = 0.02;
 
 // Time each candidate with short fixed-length solves (one warm-up, then the
 // best of three) and return the index of the fastest; candidate 0 is the
@@ -744,7 +750,9 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
         }
         if (rc) break;
         if (c == 0) default_ms = ms_min;
-        if (best < 0 || ms_min < best_ms) {
+        // a later candidate must win by a clear margin: ties within the trial
+        // noise keep the earlier (default-like, contiguous-pool) configuration
+        if (best < 0 || ms_min < best_ms * (1.0 - kTuneMargin)) {
             best = (int)c;
             best_ms = ms_min;
         }
@@ -758,7 +766,7 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
         out->tiles_per_wave = cands[best].tpw;
         out->rows = cands[best].rows;
         out->tail_pct = cands[best].tail;
-        out->reserved = 0;
+        out->interleave = cands[best].ilv;
         out->best_ms = best_ms;
         out->default_ms = default_ms;
     }
@@ -868,13 +876,15 @@ int deconvolve_autotune(int32_t solver, const gd_grid *g, const void *ubar, void
     if (g->ndim == 3) rows = {0, 1, 2, 4};
     for (int r : rows)
         for (int t : kTpwCands)
-            for (int tl : kTailCands) {
-                TuneCfg c;
-                c.tpw = t;
-                c.rows = r;
-                c.tail = tl;
-                cands.push_back(c);
-            }
+            for (int tl : kTailCands)
+                for (int il = 0; il < 2; ++il) {
+                    TuneCfg c;
+                    c.tpw = t;
+                    c.rows = r;
+                    c.tail = tl;
+                    c.ilv = il;
+                    cands.push_back(c);
+                }
     // every candidate must launch; a shape the field cannot use falls back to
     // the default rule inside solve_uniform, so duplicates are harmless
     auto launch = [&](const TuneCfg &c) { return solve_uniform(solver, g, ubar, u, &o, work, wb, info, stream, &c); };
@@ -890,12 +900,14 @@ int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *
     const gd_opts o = trial_opts();
     std::vector<TuneCfg> cands;
     for (int t : kTpwCands)
-        for (int tl : kTailCands) {
-            TuneCfg c;
-            c.tpw = t;
-            c.tail = tl;
-            cands.push_back(c);
-        }
+        for (int tl : kTailCands)
+            for (int il = 0; il < 2; ++il) {
+                TuneCfg c;
+                c.tpw = t;
+                c.tail = tl;
+                c.ilv = il;
+                cands.push_back(c);
+            }
     auto launch = [&](const TuneCfg &c) {
         return solve_batch(solver, dtype, list, count, &o, work, wb, info, stream, &c);
     };

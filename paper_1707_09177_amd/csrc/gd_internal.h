@@ -125,8 +125,8 @@ struct Params {
     // last arrival, release, latest instance completion (wall-clock ticks)
     unsigned long long *trace;
     int64_t trace_cap;
-    int32_t steal;  // pools a wave visits (its own first)
-    int32_t pad2;
+    int32_t steal;       // pools a wave visits (its own first)
+    int32_t interleave;  // pool layout: 0 contiguous shares, 1 tiles pl, pl + ng, ...
 };
 
 // Tile shape of a field: lanes hold vw consecutive x values, a 3D tile spans

@@ -404,11 +404,19 @@ __device__ __forceinline__ void run_phase(const Params &P, int it, uint32_t epoc
     const uint32_t nb = gridDim.x;
     const uint32_t ng = nb < (uint32_t)NGRP ? nb : (uint32_t)NGRP;
     const uint32_t grp = blockIdx.x % NGRP;
-    // pool pl hands out tiles pl, pl + ng, pl + 2 ng, ...: every pool walks the
-    // claim order (long tiles first, short ones last) at the same pace
+    // Pool pl owns a contiguous share of the long tiles and a contiguous share
+    // of the short ones and hands out its long tiles first: neighbouring tiles
+    // (which share halo planes and rows) stay on one XCD and its L2, and the
+    // end of a sweep is made of short tiles.
+    const int64_t nbig = P.big_total, nsmall = ntot - P.big_total;
     for (uint32_t h = 0; h < (uint32_t)P.steal && h < ng; ++h) {
         const uint32_t pl = (grp + h) % ng;
-        const int64_t cnt = (ntot - (int64_t)pl + ng - 1) / ng;  // claims in this pool
+        const int64_t blo = nbig * pl / ng, bcnt = nbig * (pl + 1) / ng - blo;
+        const int64_t slo = nbig + nsmall * pl / ng, scnt = nsmall * (pl + 1) / ng - (slo - nbig);
+        // interleaved layout: pool pl hands out tiles pl, pl + ng, ... instead
+        // (spreads each field over every XCD, at the cost of halo reuse in L2)
+        const bool ilv = P.interleave != 0;
+        const int64_t cnt = ilv ? (ntot - (int64_t)pl + ng - 1) / ng : bcnt + scnt;  // claims in this pool
         uint32_t *ctr = &P.sync->pool[epoch & 1][pl].v;
         for (;;) {
             __syncthreads();  // every wave has read the previous round's s_base
@@ -419,7 +427,9 @@ __device__ __forceinline__ void run_phase(const Params &P, int it, uint32_t epoc
             const int64_t base = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)s_base);
             if (base >= cnt) break;  // same decision in every wave of the workgroup
             const int64_t k = base + wave;
-            if (k < cnt) run_tile<T, VS, PH>(P, it, epoch, (int64_t)pl + k * ng, lane);
+            if (k < cnt)
+                run_tile<T, VS, PH>(P, it, epoch, ilv ? (int64_t)pl + k * ng : (k < bcnt ? blo + k : slo + (k - bcnt)),
+                                    lane);
         }
     }
 }

@@ -61,7 +61,7 @@ class Instance(ctypes.Structure):
 
 class TuneInfo(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int32), ("best", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32),
-                ("rows", ctypes.c_int32), ("tail_pct", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rows", ctypes.c_int32), ("tail_pct", ctypes.c_int32), ("interleave", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
