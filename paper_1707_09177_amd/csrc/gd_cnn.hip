@@ -21,8 +21,9 @@
 // with its periodic halo sits in LDS and the layer's weights in registers.
 // Their input gradients reuse the same kernel with transposed, tap-flipped
 // weights.  The 1 -> 32 and 32 -> 1 layers (288 multiply-adds per point) and
-// the weight gradients use plain FP32 arithmetic.  Weight gradients are
-// reduced deterministically (per-block partial sums added in block order).
+// the weight gradients of the end layers use plain FP32 arithmetic; the
+// 32 -> 32 weight gradients run on the matrix cores too.  Weight gradients are
+// reduced deterministically (per-block partial sums added in a fixed order).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -283,10 +284,16 @@ __global__ void k_loss(const float *yv, const T *ub, const T *u, const double *s
 }
 
 __global__ void k_loss_fin(const double *part, int64_t nblk, int64_t N, double *loss) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    __shared__ double red[256];
     double acc = 0.0;
-    for (int64_t k = 0; k < nblk; ++k) acc += part[k];
-    loss[0] = acc / (double)N;
+    for (int64_t k = threadIdx.x; k < nblk; k += blockDim.x) acc += part[k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0] / (double)N;
 }
 
 // input gradient of layer 6 through the ReLU of layer 5:
@@ -388,14 +395,103 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *xa, const T *ub, cons
     }
 }
 
+// Weight gradient of a 32 -> 32 layer on the matrix cores: for every tap t the
+// 32 x 32 block dW[o][t][c] = sum_p g[p][o] x[p + off(t)][c] is a GEMM with
+// K = points (16 per MFMA step).  LDS holds the tile's output gradient
+// transposed, gT[o][p], and three transposed copies of the input tile with its
+// halo, shifted by dx = 0, 1, 2 (xs[dx][c][row][j] = x[row][j + dx]), so every
+// 8-point operand is one aligned 16-byte read.  Wave w owns taps w, w+4, w+8.
+// Also the bias gradient db[o] = sum_p g[p][o].  part[block][32 * 288 + 32].
+__global__ __launch_bounds__(256) void k_wgrad_mid(const bf16 *xa, const bf16 *ga, float *part, int H, int W,
+                                                   int tiles_x, int tiles_y, int64_t ntiles) {
+    constexpr int NP = WGY * WGX;        // points per tile
+    constexpr int XR = WGY + 2;          // input rows with the halo
+    constexpr int GST = NP + 8;          // padded row of gT (bf16)
+    constexpr int XST = XR * WGX + 8;    // padded channel plane of an xs copy (bf16)
+    constexpr int NWL = C * K + C;
+    __shared__ __attribute__((aligned(16))) bf16 gT[C * GST];
+    __shared__ __attribute__((aligned(16))) bf16 xs[3 * C * XST];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int j = lane & 31, kh = lane >> 5;
+    f32x16 acc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[q] = f32x16{};
+    float db = 0.0f;
+    const int64_t HW = (int64_t)H * W;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tx = (int)(tile % tiles_x), ty = (int)((tile / tiles_x) % tiles_y);
+        const int64_t b = tile / ((int64_t)tiles_x * tiles_y);
+        const int x0 = tx * WGX, y0 = ty * WGY;
+        for (int q = tid; q < NP * C; q += 256) {
+            const int p = q / C, o = q % C;
+            const int y = y0 + p / WGX, x = x0 + p % WGX;
+            bf16 v = (bf16)0.0f;  // points outside the field contribute nothing
+            if (y < H && x < W) v = ga[(b * HW + (int64_t)y * W + x) * C + o];
+            gT[o * GST + p] = v;
+        }
+        for (int q = tid; q < XR * (WGX + 2) * C; q += 256) {
+            const int pix = q / C, c = q % C;
+            const int r = pix / (WGX + 2), col = pix % (WGX + 2);
+            const int gy = (int)((y0 + r - 1 + (int64_t)H) % H), gx = (int)((x0 + col - 1 + (int64_t)W) % W);
+            const bf16 v = xa[(b * HW + (int64_t)gy * W + gx) * C + c];
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int jc = col - dx;
+                if (jc >= 0 && jc < WGX) xs[(dx * C + c) * XST + r * WGX + jc] = v;
+            }
+        }
+        __syncthreads();
+        if (tid < C)
+            for (int p = 0; p < NP; ++p) db += (float)gT[tid * GST + p];
+#pragma unroll 2
+        for (int ks = 0; ks < NP / 16; ++ks) {
+            const int p0 = ks * 16, py = p0 / WGX, px0 = p0 % WGX;
+            const bf16x8 A = *reinterpret_cast<const bf16x8 *>(gT + j * GST + p0 + kh * 8);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int t = wave + 4 * q;
+                if (t < 9) {
+                    const int dy = t / 3, dx = t % 3;
+                    const bf16x8 Bv =
+                        *reinterpret_cast<const bf16x8 *>(xs + (dx * C + j) * XST + (py + dy) * WGX + px0 + kh * 8);
+                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bv, acc[q], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    float *pb = part + (int64_t)blockIdx.x * NWL;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int t = wave + 4 * q;
+        if (t < 9)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int o = 8 * (v >> 2) + 4 * kh + (v & 3);
+                pb[(o * 9 + t) * C + j] = acc[q][v];
+            }
+    }
+    if (tid < C) pb[C * K + tid] = db;
+}
+
 // grad[w] = sum over blocks (in block order) of part[block][w]; the layer's
 // weights and biases are consecutive in the parameter vector.
 __global__ void k_reduce(const float *part, int nblk, int nw, float *grad) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nw) return;
+    // 32 weights per workgroup, 8 lanes per weight summing every 8th block,
+    // then the 8 lane sums in lane order: a fixed order for every run
+    __shared__ double red[8][32];
+    const int wl = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int i = blockIdx.x * 32 + wl;
     double acc = 0.0;
-    for (int k = 0; k < nblk; ++k) acc += (double)part[(int64_t)k * nw + i];
-    grad[i] = (float)acc;
+    if (i < nw)
+        for (int k = g; k < nblk; k += 8) acc += (double)part[(int64_t)k * nw + i];
+    red[g][wl] = acc;
+    __syncthreads();
+    if (g == 0 && i < nw) {
+        double t = 0.0;
+        for (int q = 0; q < 8; ++q) t += red[q][wl];
+        grad[i] = (float)t;
+    }
 }
 
 __global__ void k_adam(float *p, float *m, float *v, const float *g, int64_t n, const int32_t *step, float lr, float b1,
@@ -556,10 +652,15 @@ int wgrad_layer(const gd_grid *g, const Layout &L, char *w, const bf16 *xa, cons
     const int tiles_x = (W + WGX - 1) / WGX, tiles_y = (H + WGY - 1) / WGY;
     const int64_t ntiles = wgrad_tiles(g);
     float *part = (float *)(w + L.wpart);
-    auto kern = k_wgrad<CI, CO, T>;
-    GD_LAUNCH(kern, dim3((unsigned)L.nblk_w), dim3(256), 0, st, xa, ub, s, ga, gf, part, H, W, tiles_x, tiles_y,
-              ntiles);
-    GD_LAUNCH(k_reduce, dim3((NWL + 255) / 256), dim3(256), 0, st, (const float *)part, L.nblk_w, NWL, grad_layer);
+    if constexpr (CI == C && CO == C) {
+        GD_LAUNCH(k_wgrad_mid, dim3((unsigned)L.nblk_w), dim3(256), 0, st, xa, ga, part, H, W, tiles_x, tiles_y,
+                  ntiles);
+    } else {
+        auto kern = k_wgrad<CI, CO, T>;
+        GD_LAUNCH(kern, dim3((unsigned)L.nblk_w), dim3(256), 0, st, xa, ub, s, ga, gf, part, H, W, tiles_x, tiles_y,
+                  ntiles);
+    }
+    GD_LAUNCH(k_reduce, dim3((NWL + 31) / 32), dim3(256), 0, st, (const float *)part, L.nblk_w, NWL, grad_layer);
     return GD_OK;
 }
 
@@ -584,7 +685,7 @@ int run_train(const gd_cnn *net, const gd_grid *g, const Layout &L, char *w, con
               off.W[2] - off.W[1], wT);
     GD_LAUNCH(k_loss<T>, dim3(pblk), dim3(256), 0, st, (const float *)(w + L.y), ub, u, s, dy,
               (double *)(w + L.lpart), HW, N);
-    GD_LAUNCH(k_loss_fin, dim3(1), dim3(64), 0, st, (const double *)(w + L.lpart), L.nblk_pix, N, loss);
+    GD_LAUNCH(k_loss_fin, dim3(1), dim3(256), 0, st, (const double *)(w + L.lpart), L.nblk_pix, N, loss);
     // through the final filter: dL/dz = G dL/dy
     float *dyz = (float *)(w + L.dyz);
     GD_LAUNCH(k_gfilt, dim3(pblk), dim3(256), 0, st, (const float *)dy, dyz, H, W, N);
