@@ -61,6 +61,10 @@ __global__ void prep_kernel(Params P) {
     }
     if (i < 2) P.sync->snap[i].v = 0;
     if (i < NGRP) {
+        int64_t c = 0;  // claims in pool i (the kernel's pool layouts)
+        const int64_t ng = P.npools, ntot = P.total_tiles, nb = P.big_total, ns = ntot - nb;
+        if (i < ng) c = P.interleave ? (ntot - i + ng - 1) / ng : (nb * (i + 1) / ng - nb * i / ng) + (ns * (i + 1) / ng - ns * i / ng);
+        P.sync->pcnt[i] = c;
         P.sync->cnt[i].v = 0;
         P.sync->gen[i].v = 0;
         P.sync->pool[0][i].v = 0;
@@ -275,6 +279,7 @@ int launch_solve(Params &P, const void *k, int64_t blocks_cap, hipStream_t strea
     const int64_t want = (P.total_tiles + WPB - 1) / WPB;
     const int64_t blocks = std::max<int64_t>(1, std::min(want, blocks_cap));
     if (P.wait_ticks <= 0) P.wait_ticks = (int64_t)10 * 1000 * dp.wall_khz;  // 10 s
+    P.npools = (int32_t)std::min<int64_t>(blocks, NGRP);
     const int prep_blocks = (int)((std::max<int64_t>(P.ninst, NGRP) + 255) / 256);
     hipLaunchKernelGGL(prep_kernel, dim3(prep_blocks), dim3(256), 0, stream, P);
     hipError_t e = hipGetLastError();

@@ -93,6 +93,9 @@ struct Sync {
     // takes its loop decision from this snapshot, never from `active` itself
     // (which the next sweep's reductions already decrement)
     SyncLine snap[2];
+    // claims in each tile pool (written by the prep kernel for the launch's
+    // pool count), read when a workgroup looks for pools to steal from
+    int64_t pcnt[NGRP];
 };
 
 // A workgroup drains its own group's pool, then helps with the others.
@@ -127,6 +130,8 @@ struct Params {
     int64_t trace_cap;
     int32_t steal;       // pools a wave visits (its own first)
     int32_t interleave;  // pool layout: 0 contiguous shares, 1 tiles pl, pl + ng, ...
+    int32_t npools;      // tile pools of the launch: min(workgroups, NGRP)
+    int32_t pad3;
 };
 
 // Tile shape of a field: lanes hold vw consecutive x values, a 3D tile spans

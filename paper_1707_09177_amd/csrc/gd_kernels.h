@@ -409,14 +409,33 @@ __device__ __forceinline__ void run_phase(const Params &P, int it, uint32_t epoc
     // (which share halo planes and rows) stay on one XCD and its L2, and the
     // end of a sweep is made of short tiles.
     const int64_t nbig = P.big_total, nsmall = ntot - P.big_total;
+    // interleaved layout: pool pl hands out tiles pl, pl + ng, ... instead
+    // (spreads each field over every XCD, at the cost of halo reuse in L2)
+    const bool ilv = P.interleave != 0;
+    auto pool_blo = [&](uint32_t pl) { return nbig * pl / ng; };
+    auto pool_bcnt = [&](uint32_t pl) { return nbig * (pl + 1) / ng - nbig * pl / ng; };
+    auto pool_slo = [&](uint32_t pl) { return nbig + nsmall * pl / ng; };
+    auto pool_cnt = [&](uint32_t pl) -> int64_t {  // claims in pool pl
+        return ilv ? (ntot - (int64_t)pl + ng - 1) / ng : pool_bcnt(pl) + (nsmall * (pl + 1) / ng - nsmall * pl / ng);
+    };
+    __shared__ uint32_t s_left[NGRP];
     for (uint32_t h = 0; h < (uint32_t)P.steal && h < ng; ++h) {
         const uint32_t pl = (grp + h) % ng;
-        const int64_t blo = nbig * pl / ng, bcnt = nbig * (pl + 1) / ng - blo;
-        const int64_t slo = nbig + nsmall * pl / ng, scnt = nsmall * (pl + 1) / ng - (slo - nbig);
-        // interleaved layout: pool pl hands out tiles pl, pl + ng, ... instead
-        // (spreads each field over every XCD, at the cost of halo reuse in L2)
-        const bool ilv = P.interleave != 0;
-        const int64_t cnt = ilv ? (ntot - (int64_t)pl + ng - 1) / ng : bcnt + scnt;  // claims in this pool
+        if (h == 1) {
+            // Own pool empty: read every pool's counter at once (one round
+            // trip) and steal only from pools that still had tiles.  Counters
+            // only grow, so a pool seen empty stays empty and is skipped.
+            __syncthreads();
+            if (threadIdx.x < ng) {
+                const uint32_t q = threadIdx.x;
+                const uint32_t c = __hip_atomic_load(&P.sync->pool[epoch & 1][q].v, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                s_left[q] = (int64_t)c < P.sync->pcnt[q] ? 1u : 0u;
+            }
+            __syncthreads();
+        }
+        if (h > 0 && s_left[pl] == 0) continue;  // the flags do not change: the same choice in every wave
+        const int64_t blo = pool_blo(pl), bcnt = pool_bcnt(pl), slo = pool_slo(pl), cnt = pool_cnt(pl);
         uint32_t *ctr = &P.sync->pool[epoch & 1][pl].v;
         for (;;) {
             __syncthreads();  // every wave has read the previous round's s_base
