@@ -198,10 +198,10 @@ int deconvolve_batch(int32_t solver, int32_t dtype, const gd_instance *list, int
 /*
  * ---- Autotuner -------------------------------------------------------------
  *
- * Times the candidate launch configurations of a solve (tile granularity:
+ * Times (4-pass trial solves) the candidate launch configurations of a solve (tile granularity:
  * target tiles per resident wave; the share of short tiles claimed at the end
- * of every sweep; the tile-pool layout; 3D rows per tile where the uniform
- * kernels offer a choice) with short fixed-length trial solves on the caller's
+ * of every sweep; the tile-pool layout; per-wave or per-workgroup tile
+ * claims; 3D rows per tile where the uniform kernels offer a choice) with short fixed-length trial solves on the caller's
  * buffers and remembers the fastest for this (solver, dtype, sizes)
  * signature.  Later deconvolve_* / deconvolve_batch calls with the same
  * signature use it.  With the environment variable GD_TUNE_CACHE naming a
@@ -218,6 +218,9 @@ typedef struct gd_tune_info {
     int32_t tail_pct;        /* chosen percent of each column cut into short tiles */
     int32_t interleave;      /* chosen tile-pool layout: 0 contiguous shares
                                 (halo reuse in L2), 1 interleaved over the XCDs */
+    int32_t wave_claims;     /* 1: every wave claims its own tiles; 0: a
+                                workgroup claims tiles for its four waves */
+    int32_t reserved;
     double best_ms;          /* trial time of the chosen configuration */
     double default_ms;       /* trial time of the untuned default */
 } gd_tune_info;
@@ -226,6 +229,16 @@ int deconvolve_autotune(int32_t solver, const gd_grid *grid, const void *ubar, v
                         gd_info *info, void *stream, gd_tune_info *out);
 int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count, void *work,
                               size_t work_bytes, gd_info *info, void *stream, gd_tune_info *out);
+
+/* Pin the launch configuration of a signature without timing anything (for
+ * reproducible runs): later solves with the same solver, grid and pointer
+ * alignment (the alignment of ubar and u decides the lane width), or the same
+ * instance list, use `choice` (its tiles_per_wave, rows, tail_pct, interleave
+ * and wave_claims; the timing fields are ignored).  Also written to the
+ * GD_TUNE_CACHE file when it is set.  Errors: GD_EINVAL. */
+int gd_tune_set(int32_t solver, const gd_grid *grid, const void *ubar, const void *u, const gd_tune_info *choice);
+int gd_tune_set_batch(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count,
+                      const gd_tune_info *choice);
 
 /* Forget every tuning choice made or loaded by this process. */
 void gd_tune_reset(void);

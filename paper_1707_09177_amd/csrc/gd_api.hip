@@ -325,6 +325,7 @@ struct TuneCfg {
     int rows = 0;
     int tail = kTailPct;
     int ilv = 0;  // interleaved tile pools
+    int wc = 0;   // per-wave tile claims
 };
 
 std::mutex g_tune_mu;
@@ -347,14 +348,15 @@ void tune_load_locked() {
     char line[1024];
     while (fgets(line, sizeof line, fp)) {
         char key[900];
-        int tpw = 0, rows = 0, tail = 0, ilv = 0;
-        if (sscanf(line, "%899s %d %d %d %d", key, &tpw, &rows, &tail, &ilv) == 5 && tpw >= 1 && tpw <= 64 &&
-            rows >= 0 && rows <= 4 && tail >= 0 && tail <= 50 && (ilv == 0 || ilv == 1)) {
+        int tpw = 0, rows = 0, tail = 0, ilv = 0, wc = 0;
+        if (sscanf(line, "%899s %d %d %d %d %d", key, &tpw, &rows, &tail, &ilv, &wc) == 6 && tpw >= 1 && tpw <= 64 &&
+            rows >= 0 && rows <= 4 && tail >= 0 && tail <= 50 && (ilv == 0 || ilv == 1) && (wc == 0 || wc == 1)) {
             TuneCfg c;
             c.tpw = tpw;
             c.rows = rows;
             c.tail = tail;
             c.ilv = ilv;
+            c.wc = wc;
             g_tune[key] = c;
         }
     }
@@ -376,7 +378,7 @@ void tune_store(const std::string &key, const TuneCfg &c) {
     g_tune[key] = c;
     if (const char *f = tune_file()) {
         if (FILE *fp = fopen(f, "a")) {
-            fprintf(fp, "%s %d %d %d %d\n", key.c_str(), c.tpw, c.rows, c.tail, c.ilv);
+            fprintf(fp, "%s %d %d %d %d %d\n", key.c_str(), c.tpw, c.rows, c.tail, c.ilv, c.wc);
             fclose(fp);
         }
     }
@@ -474,6 +476,7 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
     P.steal = kSteal;
     if (const char *e = getenv("GD_STEAL")) P.steal = std::max(0, atoi(e));
     P.interleave = cfg.ilv;
+    P.wave_claims = cfg.wc;
     P.trace = g_trace;
     P.trace_cap = g_trace_cap;
     rc = launch_solve(P, kern, blocks_cap, (hipStream_t)stream);
@@ -709,6 +712,7 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
     P.steal = kSteal;
     if (const char *e = getenv("GD_STEAL")) P.steal = std::max(0, atoi(e));
     P.interleave = cfg.ilv;
+    P.wave_claims = cfg.wc;
     P.trace = g_trace;
     P.trace_cap = g_trace_cap;
     rc = launch_solve(P, kern, blocks_cap, (hipStream_t)stream);
@@ -725,8 +729,8 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
 
 constexpr double kTuneMargin = 0.02;
 
-// Time each candidate with short fixed-length solves (one warm-up, then the
-// best of three) and return the index of the fastest; candidate 0 is the
+// Time each candidate with short fixed-length solves (4 passes; one warm-up,
+// then the best of three) and return the index of the fastest; candidate 0 is the
 // untuned default.
 template <typename Launch>
 int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStream_t stream, gd_tune_info *out) {
@@ -772,6 +776,8 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
         out->rows = cands[best].rows;
         out->tail_pct = cands[best].tail;
         out->interleave = cands[best].ilv;
+        out->wave_claims = cands[best].wc;
+        out->reserved = 0;
         out->best_ms = best_ms;
         out->default_ms = default_ms;
     }
@@ -781,7 +787,7 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
 gd_opts trial_opts() {
     gd_opts o;
     std::memset(&o, 0, sizeof o);
-    o.max_iter = 2;
+    o.max_iter = 4;  // enough passes that the sweeps, not init and exit, decide
     o.init = GD_INIT_UBAR;
     o.norm_ref = GD_REF_R0UBAR;
     o.tol = 0.0;
@@ -882,14 +888,16 @@ int deconvolve_autotune(int32_t solver, const gd_grid *g, const void *ubar, void
     for (int r : rows)
         for (int t : kTpwCands)
             for (int tl : kTailCands)
-                for (int il = 0; il < 2; ++il) {
-                    TuneCfg c;
-                    c.tpw = t;
-                    c.rows = r;
-                    c.tail = tl;
-                    c.ilv = il;
-                    cands.push_back(c);
-                }
+                for (int il = 0; il < 2; ++il)
+                    for (int wc = 0; wc < 2; ++wc) {
+                        TuneCfg c;
+                        c.tpw = t;
+                        c.rows = r;
+                        c.tail = tl;
+                        c.ilv = il;
+                        c.wc = wc;
+                        cands.push_back(c);
+                    }
     // every candidate must launch; a shape the field cannot use falls back to
     // the default rule inside solve_uniform, so duplicates are harmless
     auto launch = [&](const TuneCfg &c) { return solve_uniform(solver, g, ubar, u, &o, work, wb, info, stream, &c); };
@@ -906,19 +914,58 @@ int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *
     std::vector<TuneCfg> cands;
     for (int t : kTpwCands)
         for (int tl : kTailCands)
-            for (int il = 0; il < 2; ++il) {
-                TuneCfg c;
-                c.tpw = t;
-                c.tail = tl;
-                c.ilv = il;
-                cands.push_back(c);
-            }
+            for (int il = 0; il < 2; ++il)
+                for (int wc = 0; wc < 2; ++wc) {
+                    TuneCfg c;
+                    c.tpw = t;
+                    c.tail = tl;
+                    c.ilv = il;
+                    c.wc = wc;
+                    cands.push_back(c);
+                }
     auto launch = [&](const TuneCfg &c) {
         return solve_batch(solver, dtype, list, count, &o, work, wb, info, stream, &c);
     };
     const int best = time_candidates(cands, launch, (hipStream_t)stream, out);
     if (best < 0) return best;
     tune_store(key_batch(solver, dtype, list, count), cands[best]);
+    return GD_OK;
+}
+
+static int tune_choice(const gd_tune_info *c, TuneCfg *cfg) {
+    if (!c) return fail(GD_EINVAL, "choice is NULL");
+    if (c->tiles_per_wave < 1 || c->tiles_per_wave > 64 || c->rows < 0 || c->rows > 4 || c->tail_pct < 0 ||
+        c->tail_pct > 50 || (c->interleave != 0 && c->interleave != 1) || (c->wave_claims != 0 && c->wave_claims != 1))
+        return fail(GD_EINVAL, "launch configuration out of range");
+    cfg->tpw = c->tiles_per_wave;
+    cfg->rows = c->rows;
+    cfg->tail = c->tail_pct;
+    cfg->ilv = c->interleave;
+    cfg->wc = c->wave_claims;
+    return GD_OK;
+}
+
+int gd_tune_set(int32_t solver, const gd_grid *g, const void *ubar, const void *u, const gd_tune_info *choice) {
+    int rc = validate_grid(g);
+    if (rc) return rc;
+    if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
+    TuneCfg cfg;
+    if ((rc = tune_choice(choice, &cfg))) return rc;
+    const bool aligned = ((uintptr_t)ubar % 16 == 0) && ((uintptr_t)u % 16 == 0);
+    tune_store(key_uniform(solver, g, aligned), cfg);
+    return GD_OK;
+}
+
+int gd_tune_set_batch(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count,
+                      const gd_tune_info *choice) {
+    if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
+    if ((dtype != GD_F32 && dtype != GD_F64) || !list || count < 1) return fail(GD_EINVAL, "bad instance list");
+    int rc;
+    for (int i = 0; i < count; ++i)
+        if ((rc = validate_instance(list[i], i))) return rc;
+    TuneCfg cfg;
+    if ((rc = tune_choice(choice, &cfg))) return rc;
+    tune_store(key_batch(solver, dtype, list, count), cfg);
     return GD_OK;
 }
 

@@ -131,7 +131,7 @@ struct Params {
     int32_t steal;       // pools a wave visits (its own first)
     int32_t interleave;  // pool layout: 0 contiguous shares, 1 tiles pl, pl + ng, ...
     int32_t npools;      // tile pools of the launch: min(workgroups, NGRP)
-    int32_t pad3;
+    int32_t wave_claims; // 1: every wave claims its own tiles; 0: a workgroup claims for its waves
 };
 
 // Tile shape of a field: lanes hold vw consecutive x values, a 3D tile spans

@@ -437,6 +437,22 @@ __device__ __forceinline__ void run_phase(const Params &P, int it, uint32_t epoc
         if (h > 0 && s_left[pl] == 0) continue;  // the flags do not change: the same choice in every wave
         const int64_t blo = pool_blo(pl), bcnt = pool_bcnt(pl), slo = pool_slo(pl), cnt = pool_cnt(pl);
         uint32_t *ctr = &P.sync->pool[epoch & 1][pl].v;
+        if (P.wave_claims) {
+            // every wave claims its own tiles.  All lanes take part in the
+            // atomic (lane 0 adds 1, the others 0) and lane 0's result is the
+            // claim, so the loop has no lane-dependent branch: a claim taken
+            // under `if (lane == 0)` and broadcast was turned by the compiler
+            // into a loop that re-read an old claim.
+            for (;;) {
+                const uint32_t r = __hip_atomic_fetch_add(ctr, lane == 0 ? 1u : 0u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                const int64_t k = (int64_t)__builtin_amdgcn_readfirstlane(r);
+                if (k >= cnt) break;  // same value in every lane
+                run_tile<T, VS, PH>(P, it, epoch, ilv ? (int64_t)pl + k * ng : (k < bcnt ? blo + k : slo + (k - bcnt)),
+                                    lane);
+            }
+            continue;
+        }
         for (;;) {
             __syncthreads();  // every wave has read the previous round's s_base
             if (threadIdx.x == 0)

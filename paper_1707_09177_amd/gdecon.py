@@ -62,6 +62,7 @@ class Instance(ctypes.Structure):
 class TuneInfo(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int32), ("best", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32),
                 ("rows", ctypes.c_int32), ("tail_pct", ctypes.c_int32), ("interleave", ctypes.c_int32),
+                ("wave_claims", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
@@ -78,7 +79,7 @@ INFO_BYTES = 40  # gd_info: int32 iters, int32 status, 4 doubles
 EXPORTS = ["filter_apply", "deconvolve_workspace_bytes", "deconvolve_vancittert", "deconvolve_cg",
            "deconvolve_bicgstab", "deconvolve_steepest_descent", "gd_status_string", "gd_last_error",
            "gd_last_launch", "gd_set_trace", "deconvolve_batch_workspace_bytes", "deconvolve_batch",
-           "deconvolve_autotune", "deconvolve_batch_autotune", "gd_tune_reset", "warmstart_param_count",
+           "deconvolve_autotune", "deconvolve_batch_autotune", "gd_tune_reset", "gd_tune_set", "gd_tune_set_batch", "warmstart_param_count",
            "warmstart_workspace_bytes", "warmstart_forward", "warmstart_train_step"]
 
 _lib = None
@@ -121,6 +122,10 @@ def load(path: str = LIB_PATH):
     lib.deconvolve_batch_autotune.restype = ctypes.c_int
     lib.gd_tune_reset.argtypes = []
     lib.gd_tune_reset.restype = None
+    lib.gd_tune_set.argtypes = [i32, gp, vp, vp, tp]
+    lib.gd_tune_set.restype = ctypes.c_int
+    lib.gd_tune_set_batch.argtypes = [i32, i32, ip, i32, tp]
+    lib.gd_tune_set_batch.restype = ctypes.c_int
     cp = ctypes.POINTER(Cnn)
     lib.warmstart_param_count.argtypes = [cp]
     lib.warmstart_param_count.restype = ctypes.c_int64
@@ -303,6 +308,23 @@ def autotune(solver: str, ubar: torch.Tensor, ndim: int = 2, out: torch.Tensor |
     return _tune_dict(t)
 
 
+def _choice(tiles_per_wave=2, rows=0, tail_pct=0, interleave=0, wave_claims=0) -> TuneInfo:
+    t = TuneInfo()
+    t.tiles_per_wave, t.rows, t.tail_pct, t.interleave, t.wave_claims = (int(tiles_per_wave), int(rows), int(tail_pct),
+                                                                         int(interleave), int(wave_claims))
+    return t
+
+
+def tune_set(solver: str, ubar: torch.Tensor, out: torch.Tensor, ndim: int = 2, **choice):
+    """Pin the launch configuration for solves of `solver` on fields shaped
+    like ubar whose input and output are aligned like ubar and out
+    (gd_tune_set).  choice: tiles_per_wave, rows, tail_pct, interleave,
+    wave_claims."""
+    g = make_grid(ubar.shape, ndim, ubar.dtype)
+    t = _choice(**choice)
+    _check(load().gd_tune_set(SOLVERS[solver], ctypes.byref(g), _dev_ptr(ubar), _dev_ptr(out), ctypes.byref(t)))
+
+
 def tune_reset():
     """Forget every tuning choice of this process (gd_tune_reset)."""
     load().gd_tune_reset()
@@ -378,6 +400,12 @@ class BatchDeconvolver:
                                          self.work.data_ptr(), self.work.numel(), self.info_dev.data_ptr(),
                                          _stream_handle(stream)))
         return BatchResult(us, self.info_dev, histories)
+
+    def tune_set(self, ubars, outs, **choice):
+        """Pin this batch's launch configuration (gd_tune_set_batch)."""
+        self._bind(ubars, outs, None)
+        t = _choice(**choice)
+        _check(self.lib.gd_tune_set_batch(SOLVERS[self.solver], self.dt, self.list, self.count, ctypes.byref(t)))
 
     def autotune(self, ubars, outs=None, stream=None) -> dict:
         """Tune this batch's launch (deconvolve_batch_autotune); ``outs`` are

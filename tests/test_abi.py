@@ -118,3 +118,17 @@ def test_batch_host_side_validation():
     lst[2].ndim = 1
     assert lib.deconvolve_batch(2, 1, lst, n, ctypes.byref(o), work, ws, work + ws, None) == -1
     assert "instance 2" in lib.gd_last_error().decode()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgdecon.so not built")
+def test_tune_set_validates_choices():
+    from paper_1707_09177_amd import gdecon
+    lib = gdecon.load()
+    g = gdecon.Grid()
+    g.ndim, g.dtype, g.batch = 2, 1, 1
+    g.n[0], g.n[1], g.n[2] = 64, 32, 1
+    bad = gdecon._choice(tiles_per_wave=0)
+    assert lib.gd_tune_set(2, ctypes.byref(g), 256, 512, ctypes.byref(bad)) == -1
+    bad = gdecon._choice(wave_claims=2)
+    assert lib.gd_tune_set(2, ctypes.byref(g), 256, 512, ctypes.byref(bad)) == -1
+    assert lib.gd_tune_set(7, ctypes.byref(g), 256, 512, ctypes.byref(gdecon._choice())) == -1
