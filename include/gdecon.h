@@ -198,7 +198,7 @@ int deconvolve_batch(int32_t solver, int32_t dtype, const gd_instance *list, int
 /*
  * ---- Autotuner -------------------------------------------------------------
  *
- * Times (4-pass trial solves) the candidate launch configurations of a solve (tile granularity:
+ * Times (short fixed-length trial solves) the candidate launch configurations of a solve (tile granularity:
  * target tiles per resident wave; the share of short tiles claimed at the end
  * of every sweep; the tile-pool layout; per-wave or per-workgroup tile
  * claims; 3D rows per tile where the uniform kernels offer a choice) with short fixed-length trial solves on the caller's

@@ -729,8 +729,8 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
 
 constexpr double kTuneMargin = 0.02;
 
-// Time each candidate with short fixed-length solves (4 passes; one warm-up,
-// then the best of three) and return the index of the fastest; candidate 0 is the
+// Time each candidate with short fixed-length solves (4 Krylov or 10 Van
+// Cittert / steepest-descent passes; one warm-up, then the best of three) and return the index of the fastest; candidate 0 is the
 // untuned default.
 template <typename Launch>
 int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStream_t stream, gd_tune_info *out) {
@@ -784,10 +784,12 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
     return best;
 }
 
-gd_opts trial_opts() {
+gd_opts trial_opts(int solver) {
     gd_opts o;
     std::memset(&o, 0, sizeof o);
-    o.max_iter = 4;  // enough passes that the sweeps, not init and exit, decide
+    // enough passes that the sweeps, not init and exit, decide (Van Cittert
+    // and steepest descent passes move a third to a half of a Krylov pass)
+    o.max_iter = (solver == GD_VANCITTERT || solver == GD_STEEPEST_DESCENT) ? 10 : 4;
     o.init = GD_INIT_UBAR;
     o.norm_ref = GD_REF_R0UBAR;
     o.tol = 0.0;
@@ -881,7 +883,7 @@ int deconvolve_autotune(int32_t solver, const gd_grid *g, const void *ubar, void
     int rc = validate_grid(g);
     if (rc) return rc;
     if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
-    const gd_opts o = trial_opts();
+    const gd_opts o = trial_opts(solver);
     std::vector<TuneCfg> cands;
     std::vector<int> rows = {0};
     if (g->ndim == 3) rows = {0, 1, 2, 4};
@@ -910,7 +912,7 @@ int deconvolve_autotune(int32_t solver, const gd_grid *g, const void *ubar, void
 
 int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count, void *work,
                               size_t wb, gd_info *info, void *stream, gd_tune_info *out) {
-    const gd_opts o = trial_opts();
+    const gd_opts o = trial_opts(solver);
     std::vector<TuneCfg> cands;
     for (int t : kTpwCands)
         for (int tl : kTailCands)

@@ -577,8 +577,15 @@ static __device__ __forceinline__ int grid_sync(const Params &P, uint32_t &epoch
     return s_act;
 }
 
+// Waves per SIMD the kernels of a variant must reach: the FP32 table-driven
+// kernels (uneven batches) sit just above the 256 registers that two waves
+// allow, so they are held to two (a few bytes spill); the others keep the
+// count their registers give.
+template <typename T, int VS> constexpr int kMinWavesPerEU = (var_table(VS) && sizeof(T) == 4) ? 2 : 1;
+
 template <typename T, int SOLVER, int VS>
-__global__ __launch_bounds__(BLOCK) void solve_kernel(Params P) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<T, VS>))) void solve_kernel(
+    Params P) {
     constexpr bool TB = var_table(VS);
     uint32_t epoch = 0;
     int act;
