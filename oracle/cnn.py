@@ -4,6 +4,9 @@ TEST INFRASTRUCTURE ONLY: nothing in the product path imports this module.
 It exists so the GPU network kernels can be checked against a version simple
 enough to read by eye, and it shares no code with them.
 
+The network exists for 2D fields (3x3 taps) and 3D fields (3x3x3 taps, the
+same construction with one more axis).
+
 The paper has no learned component: it starts every deconvolution from the
 filtered field, u0 = ubar (Algorithms 1-4).  The warm start replaces that
 u0 with a residual correction predicted by a small convolutional network:
@@ -23,10 +26,11 @@ planes), the one place where the Krylov solvers converge slowly.  Training
 minimises the mean over all points of (y - t)^2 with t = (u - ubar) / s, the
 per-sample normalised correction, with Adam.
 
-Layouts: activations (B, ny, nx, C) (channels fastest); the weights of layer
-l are W[cout][tap][cin] with tap = 3 * (dy + 1) + (dx + 1), dy, dx in
-{-1, 0, 1}, followed by the bias[cout]; all layers are packed in order into
-one flat parameter vector.
+Layouts: activations (B, ny, nx, C) or (B, nz, ny, nx, C) (channels
+fastest); the weights of layer l are W[cout][tap][cin] with
+tap = 3 (dy + 1) + (dx + 1) in 2D and 9 (dz + 1) + 3 (dy + 1) + (dx + 1) in 3D,
+offsets in {-1, 0, 1}, followed by the bias[cout]; all layers are packed in
+order into one flat parameter vector.
 
 `emulate_bf16=True` rounds the weights and every stored activation and
 activation gradient to bfloat16 (round to nearest even) where the GPU
@@ -39,6 +43,11 @@ import numpy as np
 from . import filter as g_filter
 
 TAPS = [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+TAPS3 = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+def taps(ndim: int):
+    return TAPS if ndim == 2 else TAPS3
 
 
 def layer_dims(channels: int = 32, layers: int = 6):
@@ -49,16 +58,18 @@ def layer_dims(channels: int = 32, layers: int = 6):
     return dims
 
 
-def param_count(channels: int = 32, layers: int = 6) -> int:
-    return sum(co * 9 * ci + co for ci, co in layer_dims(channels, layers))
+def param_count(channels: int = 32, layers: int = 6, ndim: int = 2) -> int:
+    nt = len(taps(ndim))
+    return sum(co * nt * ci + co for ci, co in layer_dims(channels, layers))
 
 
-def unpack(params: np.ndarray, channels: int = 32, layers: int = 6):
+def unpack(params: np.ndarray, channels: int = 32, layers: int = 6, ndim: int = 2):
     """Views (W, b) per layer into the flat parameter vector."""
+    nt = len(taps(ndim))
     out, off = [], 0
     for ci, co in layer_dims(channels, layers):
-        W = params[off:off + co * 9 * ci].reshape(co, 9, ci)
-        off += co * 9 * ci
+        W = params[off:off + co * nt * ci].reshape(co, nt, ci)
+        off += co * nt * ci
         b = params[off:off + co]
         off += co
         out.append((W, b))
@@ -74,37 +85,43 @@ def bf16(x: np.ndarray) -> np.ndarray:
     return bits.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def shifted(x: np.ndarray, dy: int, dx: int) -> np.ndarray:
-    """x[:, (y + dy) mod ny, (x + dx) mod nx, :]."""
-    return np.roll(x, shift=(-dy, -dx), axis=(1, 2))
+def shifted(x: np.ndarray, off) -> np.ndarray:
+    """x at the point offset by `off` (per spatial axis, periodic):
+    x[:, (y + dy) mod ny, (x + dx) mod nx, :] in 2D, likewise in 3D."""
+    nd = len(off)
+    return np.roll(x, shift=tuple(-o for o in off), axis=tuple(range(1, nd + 1)))
 
 
 def conv(x: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """Periodic 3x3 cross-correlation: out[., y, x, o] = b[o] +
-    sum_tap sum_c W[o, tap, c] * x[., y + dy, x + dx, c]."""
-    out = np.zeros(x.shape[:3] + (W.shape[0],))
-    for t, (dy, dx) in enumerate(TAPS):
-        out += shifted(x, dy, dx) @ W[:, t, :].T
+    """Periodic 3x3 (3x3x3) cross-correlation: out[., p, o] = b[o] +
+    sum_tap sum_c W[o, tap, c] * x[., p + off(tap), c]."""
+    nd = x.ndim - 2
+    out = np.zeros(x.shape[:-1] + (W.shape[0],))
+    for t, off in enumerate(taps(nd)):
+        out += shifted(x, off) @ W[:, t, :].T
     return out + b
 
 
 def conv_grad_input(g: np.ndarray, W: np.ndarray) -> np.ndarray:
-    """Adjoint of conv in its input: dx[., y, x, c] =
-    sum_tap sum_o W[o, tap, c] * g[., y - dy, x - dx, o]."""
-    out = np.zeros(g.shape[:3] + (W.shape[2],))
-    for t, (dy, dx) in enumerate(TAPS):
-        out += shifted(g, -dy, -dx) @ W[:, t, :]
+    """Adjoint of conv in its input: dx[., p, c] =
+    sum_tap sum_o W[o, tap, c] * g[., p - off(tap), o]."""
+    nd = g.ndim - 2
+    out = np.zeros(g.shape[:-1] + (W.shape[2],))
+    for t, off in enumerate(taps(nd)):
+        out += shifted(g, tuple(-o for o in off)) @ W[:, t, :]
     return out
 
 
 def conv_grad_weight(x: np.ndarray, g: np.ndarray):
-    """dW[o, tap, c] = sum_points g[., y, x, o] * x[., y + dy, x + dx, c];
-    db[o] = sum_points g[., y, x, o]."""
+    """dW[o, tap, c] = sum_points g[., p, o] * x[., p + off(tap), c];
+    db[o] = sum_points g[., p, o]."""
+    nd = x.ndim - 2
     co, ci = g.shape[-1], x.shape[-1]
-    dW = np.zeros((co, 9, ci))
+    tp = taps(nd)
+    dW = np.zeros((co, len(tp), ci))
     gf = g.reshape(-1, co)
-    for t, (dy, dx) in enumerate(TAPS):
-        dW[:, t, :] = gf.T @ shifted(x, dy, dx).reshape(-1, ci)
+    for t, off in enumerate(tp):
+        dW[:, t, :] = gf.T @ shifted(x, off).reshape(-1, ci)
     return dW, gf.sum(axis=0)
 
 
@@ -114,41 +131,42 @@ def rms(ubar: np.ndarray) -> np.ndarray:
     return np.where(s > 0, s, 1.0)
 
 
-def forward(params, ubar, channels=32, layers=6, emulate_bf16=False):
-    """Network forward on ubar (B, ny, nx).  Returns a dict with the input
-    scale s, the input x0, the stored activations a_1 .. a_{L-1}, the output y
-    and the warm start u0."""
+def forward(params, ubar, channels=32, layers=6, emulate_bf16=False, ndim=2):
+    """Network forward on ubar (B, ny, nx) or (B, nz, ny, nx).  Returns a dict
+    with the input scale s, the input x0, the stored activations a_1 ..
+    a_{L-1}, the output y and the warm start u0."""
     ubar = np.asarray(ubar, dtype=np.float64)
-    P = unpack(np.asarray(params, dtype=np.float64), channels, layers)
+    P = unpack(np.asarray(params, dtype=np.float64), channels, layers, ndim)
     if emulate_bf16:
         P = [(bf16(W), b) for W, b in P]
     s = rms(ubar)
-    x0 = (ubar / s[:, None, None])[..., None]
+    sb = s.reshape((-1,) + (1,) * ndim)
+    x0 = (ubar / sb)[..., None]
     acts = []
     a = x0
     for li, (W, b) in enumerate(P):
         z = conv(a, W, b)
         if li == len(P) - 1:
-            y = g_filter(z[..., 0], 2)
+            y = g_filter(z[..., 0], ndim)
             break
         a = np.maximum(z, 0.0)
         if emulate_bf16:
             a = bf16(a)
         acts.append(a)
-    u0 = ubar + s[:, None, None] * y
+    u0 = ubar + sb * y
     return {"s": s, "x0": x0, "acts": acts, "y": y, "u0": u0, "P": P}
 
 
-def loss_and_grad(params, ubar, u, channels=32, layers=6, emulate_bf16=False):
+def loss_and_grad(params, ubar, u, channels=32, layers=6, emulate_bf16=False, ndim=2):
     """Training loss mean((y - t)^2), t = (u - ubar) / s, and its gradient
     with respect to the flat parameter vector (backpropagation)."""
-    f = forward(params, ubar, channels, layers, emulate_bf16)
-    s = f["s"]
-    t = (np.asarray(u, dtype=np.float64) - ubar) / s[:, None, None]
+    f = forward(params, ubar, channels, layers, emulate_bf16, ndim)
+    s = f["s"].reshape((-1,) + (1,) * ndim)
+    t = (np.asarray(u, dtype=np.float64) - ubar) / s
     r = f["y"] - t
     n = r.size
     loss = float(np.sum(r * r) / n)
-    g = g_filter((2.0 / n) * r, 2)[..., None]   # dL/dz = G dL/dy (G is symmetric)
+    g = g_filter((2.0 / n) * r, ndim)[..., None]   # dL/dz = G dL/dy (G is symmetric)
     grads = [None] * len(f["P"])
     ins = [f["x0"]] + f["acts"]
     for li in range(len(f["P"]) - 1, -1, -1):

@@ -212,16 +212,18 @@ def batch_field(ndim: int, n: int, inst: int, seed_cfg=4, dtype=np.float64):
     return scalar_3d(n, spectrum_kolmogorov, 2.0, 0.3125 * n, rng, dtype)
 
 
-def cnn_init_params(seed: int, channels: int = 32, layers: int = 6) -> np.ndarray:
+def cnn_init_params(seed: int, channels: int = 32, layers: int = 6, ndim: int = 2) -> np.ndarray:
     """Initial weights of the warm-start network, flat FP64, in the layer
-    order 1 -> C, C -> C (layers - 2 times), C -> 1, each layer W[cout][9][cin]
+    order 1 -> C, C -> C (layers - 2 times), C -> 1, each layer W[cout][taps][cin]
+    (9 taps in 2D, 27 in 3D)
     followed by bias[cout]: He-normal weights (fan-in 9*cin), zero biases, the
     last layer scaled by 0.1 so the untrained network starts near u0 = ubar."""
-    rng = np.random.default_rng(np.random.SeedSequence([1707, 9177, 5, seed]))
+    rng = np.random.default_rng(np.random.SeedSequence([1707, 9177, 5 if ndim == 2 else 6, seed]))
+    nt = 9 if ndim == 2 else 27
     dims = [(1, channels)] + [(channels, channels)] * (layers - 2) + [(channels, 1)]
     parts = []
     for li, (ci, co) in enumerate(dims):
-        W = rng.standard_normal((co, 9, ci)) * np.sqrt(2.0 / (9 * ci))
+        W = rng.standard_normal((co, nt, ci)) * np.sqrt(2.0 / (nt * ci))
         if li == len(dims) - 1:
             W *= 0.1
         parts += [W.ravel(), np.zeros(co)]
@@ -242,3 +244,10 @@ def training_pairs(count: int, n: int = 512, crop: int = 128, seed0: int = 0, dt
                 if len(out) < count:
                     out.append(f[cy * crop:(cy + 1) * crop, cx * crop:(cx + 1) * crop].astype(dtype))
     return out
+
+
+def training_pairs_3d(count: int, n: int = 64, seed0: int = 0, dtype=np.float32):
+    """3D scalar fields for the 3D warm-start network: `count` arrays (n, n, n)
+    with a k^-5/3 spectrum on 2 <= k <= 0.3125 n (the uneven-batch 3D law)."""
+    return [scalar_3d(n, spectrum_kolmogorov, 2.0, 0.3125 * n, rng_for(6, 2000 + seed0 + i), dtype)
+            for i in range(count)]

@@ -146,3 +146,68 @@ def test_bf16_rounding_bit_patterns():
     x = np.array([one, one + ulp / 2, one + 1.5 * ulp, one + 0.3 * ulp, -2.0 - 0.7 * ulp * 2, 0.0])
     want = np.array([one, one, one + 2 * ulp, one, -2.0 - 2 * ulp, 0.0])
     np.testing.assert_array_equal(cnn.bf16(x), want)
+
+
+# ------------------------------------------------------------------ 3D network
+def fft_correlate3(x, w):
+    """3D periodic cross-correlation with a 3x3x3 kernel through the FFT."""
+    k = np.zeros(x.shape)
+    for t, (dz, dy, dx) in enumerate(cnn.TAPS3):
+        k[(-dz) % x.shape[0], (-dy) % x.shape[1], (-dx) % x.shape[2]] += w[t]
+    return np.real(np.fft.ifftn(np.fft.fftn(x) * np.fft.fftn(k)))
+
+
+@pytest.mark.parametrize("shape", [(4, 5, 6), (3, 3, 3), (1, 2, 5)])
+def test_conv3d_is_fft_circular_correlation(shape):
+    x = rng(21).standard_normal((2,) + shape + (3,))
+    W = rng(22).standard_normal((2, 27, 3))
+    b = rng(23).standard_normal(2)
+    out = cnn.conv(x, W, b)
+    for bb in range(2):
+        for o in range(2):
+            want = b[o] + sum(fft_correlate3(x[bb, ..., c], W[o, :, c]) for c in range(3))
+            np.testing.assert_allclose(out[bb, ..., o], want, rtol=0, atol=1e-12)
+
+
+def test_conv3d_adjoints():
+    x = rng(24).standard_normal((1, 3, 4, 5, 2))
+    g = rng(25).standard_normal((1, 3, 4, 5, 3))
+    W = rng(26).standard_normal((3, 27, 2))
+    lhs = np.sum(cnn.conv(x, W, np.zeros(3)) * g)
+    assert abs(lhs - np.sum(x * cnn.conv_grad_input(g, W))) <= 1e-11 * abs(lhs)
+    dW, _ = cnn.conv_grad_weight(x, g)
+    assert abs(np.sum(dW * W) - lhs) <= 1e-11 * abs(lhs)
+
+
+def test_param_count_3d():
+    assert cnn.param_count(ndim=3) == (864 + 32) + 4 * (27648 + 32) + (864 + 1) == 112481
+    assert synth.cnn_init_params(0, ndim=3).size == 112481
+
+
+def test_backprop_3d_matches_central_differences():
+    params = synth.cnn_init_params(3, channels=4, ndim=3)
+    params[-1] = 0.05
+    ub = rng(27).standard_normal((2, 3, 4, 5))
+    u = ub + 0.3 * rng(28).standard_normal((2, 3, 4, 5))
+    loss, g = cnn.loss_and_grad(params, ub, u, channels=4, ndim=3)
+    pick = rng(29).choice(params.size, size=60, replace=False)
+    eps = 1e-6
+    for i in pick:
+        p1, p2 = params.copy(), params.copy()
+        p1[i] += eps
+        p2[i] -= eps
+        fd = (cnn.loss_and_grad(p1, ub, u, channels=4, ndim=3)[0] - cnn.loss_and_grad(p2, ub, u, channels=4, ndim=3)[0]) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1e-3, abs(g[i])) + 1e-9, (i, fd, g[i])
+
+
+def test_3d_correction_in_range_of_g_and_scale_equivariant():
+    p = synth.cnn_init_params(7, ndim=3)
+    p[cnn.param_count(ndim=3) - 1] = 0.2
+    ub = rng(30).standard_normal((1, 4, 6, 8))
+    f = cnn.forward(p, ub, ndim=3)
+    F = np.fft.fftn(f["u0"][0] - ub[0])
+    for ax, n in enumerate((4, 6, 8)):
+        sl = [slice(None)] * 3
+        sl[ax] = n // 2
+        assert np.max(np.abs(F[tuple(sl)])) <= 1e-12 * np.max(np.abs(F))
+    np.testing.assert_allclose(cnn.forward(p, 3.0 * ub, ndim=3)["u0"], 3.0 * f["u0"], rtol=1e-12, atol=1e-12)
