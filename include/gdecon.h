@@ -253,17 +253,19 @@ void gd_tune_reset(void);
  *     s  = RMS of ubar over the field,  x0 = ubar / s,
  *     a_l = relu(conv_l(a_{l-1}))  for l = 1..5,   y = G conv_6(a_5),
  *     u0 = ubar + s * y,
- * conv_l a periodic 3x3 cross-correlation with bias, channels
- * 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1, G the deconvolution filter (so the
- * correction lies in the range of G, like the paper's start ubar).  Activations are bfloat16, the 32 -> 32
- * layers run on the matrix cores with FP32 accumulation.  Only 2D fields
- * (gd_grid.ndim == 2, batch = number of fields) are supported.
+ * conv_l a periodic 3x3 (gd_cnn.ndim == 2) or 3x3x3 (ndim == 3)
+ * cross-correlation with bias, channels 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1,
+ * G the deconvolution filter (so the correction lies in the range of G, like
+ * the paper's start ubar).  Activations are bfloat16, the 32 -> 32 layers
+ * run on the matrix cores with FP32 accumulation.  The grid's ndim must equal
+ * the network's; batch = number of fields.
  *
  * Parameters: one FP32 vector, layer by layer, each W[cout][tap][cin] with
- * tap = 3*(dy+1) + (dx+1) for the offset (dy, dx) in y and x, then bias[cout].
+ * tap = 3*(dy+1) + (dx+1) for the offset (dy, dx) in y and x (in 3D
+ * 9*(dz+1) + 3*(dy+1) + (dx+1)), then bias[cout].
  */
 typedef struct gd_cnn {
-    int32_t ndim;      /* 2 */
+    int32_t ndim;      /* 2 or 3 */
     int32_t channels;  /* 32 */
     int32_t layers;    /* 6 */
     int32_t reserved;  /* set to 0 */
@@ -276,7 +278,8 @@ typedef struct gd_cnn {
     int32_t *step;     /* device, one int: Adam steps taken (0 before the first) */
 } gd_cnn;
 
-/* Number of FP32 parameters (37601), or 0 for an unsupported shape. */
+/* Number of FP32 parameters (37601 in 2D, 112481 in 3D), or 0 for an
+ * unsupported shape. */
 int64_t warmstart_param_count(const gd_cnn *net);
 
 /* Workspace bytes for warmstart_forward (training == 0) or
@@ -285,7 +288,8 @@ size_t warmstart_workspace_bytes(const gd_cnn *net, const gd_grid *grid, int32_t
 
 /* u0 = network(ubar) for every field of the batch.  ubar, u0: device fields of
  * grid->dtype (FP32 or FP64; the network itself runs in bfloat16/FP32).
- * Errors: GD_EINVAL (3D grid, unsupported network shape, NULL), GD_EWORKSPACE,
+ * Errors: GD_EINVAL (grid and network of different ndim, unsupported network
+ * shape, NULL), GD_EWORKSPACE,
  * GD_EALIGN. */
 int warmstart_forward(const gd_cnn *net, const gd_grid *grid, const void *ubar, void *u0, void *work,
                       size_t work_bytes, void *stream);

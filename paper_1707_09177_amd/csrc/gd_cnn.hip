@@ -5,14 +5,20 @@
 // The paper starts every iteration from u0 = ubar (Algorithms 1-4); the
 // network only replaces that starting point, the solve itself is unchanged.
 //
-// Network (2D): 6 layers of periodic 3x3 cross-correlation with bias,
-// 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 channels, ReLU after every layer but the
-// last, then the deconvolution filter G itself, u0 = ubar + s * G z: the
+// Network: 6 layers of periodic 3x3 (2D) or 3x3x3 (3D) cross-correlation with
+// bias, 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1 channels, ReLU after every layer
+// but the last, then the deconvolution filter G itself, u0 = ubar + s * G z: the
 // correction stays in the range of G like the paper's start u0 = ubar, so it
 // adds nothing where G's transfer function vanishes (where the Krylov solvers
 // are slowest); s is the per-sample RMS of ubar.  Weights of layer l are
-// W[cout][tap][cin] (tap = 3 (dy + 1) + (dx + 1)) followed by bias[cout], all
-// layers packed into one FP32 parameter vector.
+// W[cout][tap][cin] (tap = 3 (dy + 1) + (dx + 1), in 3D 9 (dz + 1) + ...)
+// followed by bias[cout], all layers packed into one FP32 parameter vector.
+//
+// A 3D field is a stack of nz planes and a 3D convolution is the sum of three
+// 2D convolutions of the planes shifted by dz = -1, 0, +1, each with its own
+// 3x3 slice of the weights: the 2D matrix-core kernels run once per dz, with
+// the plane shift as an argument, accumulating into an FP32 buffer that a
+// final pass turns into bf16 (bias and ReLU, or the ReLU mask).
 //
 // Data layout: activations are bfloat16, channels fastest (NHWC, 64 bytes per
 // point).  The four 32 -> 32 layers run as implicit GEMMs on the matrix cores
@@ -46,8 +52,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int C = 32;           // channels
+constexpr int K9 = 9 * C;       // reduction length of one 3x3 slice
 constexpr int NL = 6;           // layers
-constexpr int K = 9 * C;        // reduction length of a 32 -> 32 layer
+constexpr int K = K9;           // reduction length of a 2D 32 -> 32 layer (one MFMA pass)
 constexpr int NMID = NL - 2;    // 32 -> 32 layers
 constexpr int TY = 8, TX = 32;  // conv tile: 8 rows x 32 points (one MFMA M-tile per row)
 constexpr int PSTR = 40;        // LDS stride of one point (32 channels + 8 pad) in bf16
@@ -60,13 +67,14 @@ struct Offsets {
     int64_t W[NL], b[NL], total;
 };
 
-Offsets offsets() {
+// parameter offsets for NT taps per layer (9 in 2D, 27 in 3D)
+Offsets offsets(int NT) {
     Offsets o;
     int64_t off = 0;
     for (int l = 0; l < NL; ++l) {
         const int ci = l == 0 ? 1 : C, co = l == NL - 1 ? 1 : C;
         o.W[l] = off;
-        off += (int64_t)co * 9 * ci;
+        off += (int64_t)co * NT * ci;
         o.b[l] = off;
         off += co;
     }
@@ -76,6 +84,17 @@ Offsets offsets() {
 
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// plane pz = sample * nz + z shifted by dz planes within its sample (periodic)
+__device__ __forceinline__ int64_t plane_shift(int64_t pz, int nz, int dz) {
+    const int z = (int)(pz % nz);
+    return pz - z + wrap(z + dz, nz);
+}
+
+// offsets of tap t of NT (9: 2D, 27: 3D)
+template <int NT> __device__ __forceinline__ int tap_dz(int t) { return NT == 27 ? t / 9 - 1 : 0; }
+__device__ __forceinline__ int tap_dy(int t) { return (t % 9) / 3 - 1; }
+__device__ __forceinline__ int tap_dx(int t) { return t % 3 - 1; }
+
 // ---------------------------------------------------------------- small kernels
 
 __global__ void k_cvt(const float *p, bf16 *q, int64_t n) {
@@ -83,15 +102,23 @@ __global__ void k_cvt(const float *p, bf16 *q, int64_t n) {
     if (i < n) q[i] = (bf16)p[i];
 }
 
-// Input-gradient weights of the 32 -> 32 layers: WT[m][cin][t][cout] =
-// W[m][cout][8 - t][cin] (tap 8 - t is the mirrored offset of tap t).
-__global__ void k_transpose(const bf16 *wbf, int64_t off_w1, int64_t layer_stride, bf16 *wT) {
+// Per-dz 3x3 weight slices of the 32 -> 32 layers for the matrix-core kernel,
+// out[m][dzi][row][t * 32 + col] (ndz = NT / 9 slices):
+//   forward (BWD = false): row = cout, col = cin: W[m][cout][dzi * 9 + t][cin];
+//   input gradient (BWD):  row = cin, col = cout: W[m][cout][NT - 1 - (dzi * 9 + t)][cin]
+// (the mirrored tap: the input gradient correlates with the flipped kernel).
+template <bool BWD>
+__global__ void k_repack(const bf16 *wbf, int64_t off_w1, int64_t layer_stride, int NT, bf16 *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)NMID * C * K) return;
-    const int m = (int)(i / (C * K));
-    const int r = (int)(i % (C * K));
-    const int cin = r / K, t = (r % K) / C, cout = r % C;
-    wT[i] = wbf[off_w1 + m * layer_stride + ((int64_t)cout * 9 + (8 - t)) * C + cin];
+    const int ndz = NT / 9;
+    if (i >= (int64_t)NMID * ndz * C * K9) return;
+    const int m = (int)(i / ((int64_t)ndz * C * K9));
+    const int r = (int)(i % ((int64_t)ndz * C * K9));
+    const int dzi = r / (C * K9), r2 = r % (C * K9);
+    const int row = r2 / K9, t = (r2 % K9) / C, col = r2 % C;
+    const int cout = BWD ? col : row, cin = BWD ? row : col;
+    const int tap = BWD ? NT - 1 - (dzi * 9 + t) : dzi * 9 + t;
+    out[i] = wbf[off_w1 + m * layer_stride + ((int64_t)cout * NT + tap) * C + cin];
 }
 
 template <typename T>
@@ -123,27 +150,27 @@ __global__ void k_rms_fin(const double *part, int B, int64_t P, double *s) {
 }
 
 // layer 1: one input channel (ubar / s, FP32) -> 32 channels, ReLU
-template <typename T>
+template <typename T, int NT>
 __global__ void k_conv_in(const T *ub, const double *s, const bf16 *w1, const float *b1, bf16 *out, int H, int W,
-                          int64_t N) {
+                          int nz, int64_t N) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int64_t HW = (int64_t)H * W;
-    const int64_t b = p / HW;
+    const int64_t pz = p / HW;
     const int rem = (int)(p % HW), y = rem / W, x = rem % W;
-    const float inv = (float)(1.0 / s[b]);
-    float xv[9];
+    const float inv = (float)(1.0 / s[pz / nz]);
+    float xv[NT];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int yy = wrap(y + t / 3 - 1, H), xx = wrap(x + t % 3 - 1, W);
-        xv[t] = (float)ub[b * HW + (int64_t)yy * W + xx] * inv;
+    for (int t = 0; t < NT; ++t) {
+        const int yy = wrap(y + tap_dy(t), H), xx = wrap(x + tap_dx(t), W);
+        xv[t] = (float)ub[plane_shift(pz, nz, tap_dz<NT>(t)) * HW + (int64_t)yy * W + xx] * inv;
     }
     alignas(16) bf16 o[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         float acc = b1[c];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc += (float)w1[c * 9 + t] * xv[t];
+        for (int t = 0; t < NT; ++t) acc += (float)w1[c * NT + t] * xv[t];
         o[c] = (bf16)fmaxf(acc, 0.0f);
     }
     uint4 *dst = reinterpret_cast<uint4 *>(out + p * C);
@@ -151,20 +178,24 @@ __global__ void k_conv_in(const T *ub, const double *s, const bf16 *w1, const fl
     for (int q = 0; q < 4; ++q) dst[q] = reinterpret_cast<const uint4 *>(o)[q];
 }
 
-// 32 -> 32 layer on the matrix cores.  Forward: out = relu(conv(in) + bias).
-// Input gradient (BWD): out = conv'(in) * (mask > 0), where `in` holds the
-// output gradient, `wmat` the transposed weights and `mask` the layer's input
-// activation.  wmat: [cout][K] with K = tap * 32 + cin.
-template <bool BWD>
+// 32 -> 32 layer (one 3x3 slice) on the matrix cores; the input is the plane
+// shifted by dzo within its sample (0 in 2D).  wmat: [cout][K] with
+// K = tap * 32 + cin.  MODE 0 (forward): out = relu(conv(in) + bias);
+// MODE 1 (input gradient): out = conv'(in) * (mask > 0), with `in` the output
+// gradient, `wmat` the transposed weights and `mask` the layer's input
+// activation; MODE 2 (one dz of a 3D layer): accb (FP32) = or += conv(in).
+constexpr int kFwd = 0, kBwd = 1, kAcc = 2;
+template <int MODE>
 __global__ __launch_bounds__(256) void k_conv_mid(const bf16 *in, const bf16 *wmat, const float *bias, const bf16 *mask,
-                                                  bf16 *out, int H, int W, int tiles_x, int tiles_y) {
+                                                  bf16 *out, float *accb, int first, int H, int W, int nz, int dzo,
+                                                  int tiles_x, int tiles_y) {
     __shared__ __attribute__((aligned(16))) bf16 tile[(TY + 2) * (TX + 2) * PSTR];
     const int blk = blockIdx.x;
     const int tx = blk % tiles_x, ty = (blk / tiles_x) % tiles_y;
-    const int64_t b = blk / (tiles_x * tiles_y);
+    const int64_t pz = blk / (tiles_x * tiles_y);  // output plane
     const int x0 = tx * TX, y0 = ty * TY;
     const int64_t HW = (int64_t)H * W;
-    const bf16 *inb = in + b * HW * C;
+    const bf16 *inb = in + plane_shift(pz, nz, dzo) * HW * C;
     const int tid = threadIdx.x;
     // tile with a one-point periodic halo, 16-byte chunks of 8 channels
     for (int q = tid; q < (TY + 2) * (TX + 2) * 4; q += 256) {
@@ -180,7 +211,7 @@ __global__ __launch_bounds__(256) void k_conv_mid(const bf16 *in, const bf16 *wm
 #pragma unroll
     for (int ks = 0; ks < K / 16; ++ks) Bf[ks] = *reinterpret_cast<const bf16x8 *>(wmat + j * K + ks * 16 + kh * 8);
     float bj = 0.0f;
-    if constexpr (!BWD) bj = bias[j];
+    if constexpr (MODE == kFwd) bj = bias[j];
     __syncthreads();
     for (int rr = wave; rr < TY; rr += 4) {
         f32x16 acc = {};
@@ -198,26 +229,41 @@ __global__ __launch_bounds__(256) void k_conv_mid(const bf16 *in, const bf16 *wm
             const int i = 8 * (v >> 2) + 4 * kh + (v & 3);
             const int x = x0 + i;
             if (x >= W) continue;
-            const int64_t idx = ((b * H + y) * (int64_t)W + x) * C + j;
+            const int64_t idx = ((pz * H + y) * (int64_t)W + x) * C + j;
             float val = acc[v];
-            if constexpr (BWD) val = (float)mask[idx] > 0.0f ? val : 0.0f;
-            else val = fmaxf(val + bj, 0.0f);
-            out[idx] = (bf16)val;
+            if constexpr (MODE == kAcc) {
+                accb[idx] = first ? val : accb[idx] + val;
+            } else {
+                if constexpr (MODE == kBwd) val = (float)mask[idx] > 0.0f ? val : 0.0f;
+                else val = fmaxf(val + bj, 0.0f);
+                out[idx] = (bf16)val;
+            }
         }
     }
 }
 
+// the last step of a 3D layer: out = relu(accb + bias) (forward) or
+// accb * (mask > 0) (input gradient), in bf16
+__global__ void k_finish(const float *accb, const float *bias, const bf16 *mask, bf16 *out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = accb[i];
+    out[i] = (bf16)(mask ? ((float)mask[i] > 0.0f ? v : 0.0f) : fmaxf(v + bias[i % C], 0.0f));
+}
+
 // layer 6: 32 channels -> 1, no activation: z
-__global__ void k_conv_out(const bf16 *a, const bf16 *w6, const float *b6, float *z, int H, int W, int64_t N) {
+template <int NT>
+__global__ void k_conv_out(const bf16 *a, const bf16 *w6, const float *b6, float *z, int H, int W, int nz, int64_t N) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int64_t HW = (int64_t)H * W;
-    const int64_t b = p / HW;
+    const int64_t pz = p / HW;
     const int rem = (int)(p % HW), y = rem / W, x = rem % W;
     float acc = b6[0];
-    for (int t = 0; t < 9; ++t) {
-        const int yy = wrap(y + t / 3 - 1, H), xx = wrap(x + t % 3 - 1, W);
-        const uint4 *src = reinterpret_cast<const uint4 *>(a + (b * HW + (int64_t)yy * W + xx) * C);
+    for (int t = 0; t < NT; ++t) {
+        const int yy = wrap(y + tap_dy(t), H), xx = wrap(x + tap_dx(t), W);
+        const uint4 *src =
+            reinterpret_cast<const uint4 *>(a + (plane_shift(pz, nz, tap_dz<NT>(t)) * HW + (int64_t)yy * W + xx) * C);
         alignas(16) bf16 v[C];
 #pragma unroll
         for (int q = 0; q < 4; ++q) reinterpret_cast<uint4 *>(v)[q] = src[q];
@@ -227,37 +273,44 @@ __global__ void k_conv_out(const bf16 *a, const bf16 *w6, const float *b6, float
     z[p] = acc;
 }
 
-// out = G in: the periodic trapezoidal filter (1/4, 1/2, 1/4) per axis
-__device__ __forceinline__ float g_apply(const float *in, int64_t base, int y, int x, int H, int W) {
+// out = G in: the periodic trapezoidal filter (1/4, 1/2, 1/4) per axis (the
+// z pass only when the field has several planes)
+__device__ __forceinline__ float g_apply(const float *in, int64_t pz, int y, int x, int H, int W, int nz) {
     const int ym = wrap(y - 1, H), yp = wrap(y + 1, H), xm = wrap(x - 1, W), xp = wrap(x + 1, W);
-    auto row = [&](int yy) {
-        const float *r = in + base + (int64_t)yy * W;
-        return 0.5f * r[x] + 0.25f * (r[xm] + r[xp]);
+    const int64_t HW = (int64_t)H * W;
+    auto plane = [&](int64_t q) {
+        auto row = [&](int yy) {
+            const float *r = in + q * HW + (int64_t)yy * W;
+            return 0.5f * r[x] + 0.25f * (r[xm] + r[xp]);
+        };
+        return 0.5f * row(y) + 0.25f * (row(ym) + row(yp));
     };
-    return 0.5f * row(y) + 0.25f * (row(ym) + row(yp));
+    if (nz == 1) return plane(pz);
+    return 0.5f * plane(pz) + 0.25f * (plane(plane_shift(pz, nz, -1)) + plane(plane_shift(pz, nz, 1)));
 }
 
 // y = G z; writes y (training) and/or u0 = ubar + s * y
 template <typename T>
-__global__ void k_gfin(const float *z, const T *ub, const double *s, float *y_out, T *u0, int H, int W, int64_t N) {
+__global__ void k_gfin(const float *z, const T *ub, const double *s, float *y_out, T *u0, int H, int W, int nz,
+                       int64_t N) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int64_t HW = (int64_t)H * W;
-    const int64_t b = p / HW;
+    const int64_t pz = p / HW;
     const int rem = (int)(p % HW), y = rem / W, x = rem % W;
-    const float v = g_apply(z, b * HW, y, x, H, W);
+    const float v = g_apply(z, pz, y, x, H, W, nz);
     if (y_out) y_out[p] = v;
-    if (u0) u0[p] = ub[p] + (T)(s[b] * (double)v);
+    if (u0) u0[p] = ub[p] + (T)(s[pz / nz] * (double)v);
 }
 
 // out = G in (the adjoint of the final filter: G is symmetric)
-__global__ void k_gfilt(const float *in, float *out, int H, int W, int64_t N) {
+__global__ void k_gfilt(const float *in, float *out, int H, int W, int nz, int64_t N) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int64_t HW = (int64_t)H * W;
-    const int64_t b = p / HW;
+    const int64_t pz = p / HW;
     const int rem = (int)(p % HW), y = rem / W, x = rem % W;
-    out[p] = g_apply(in, b * HW, y, x, H, W);
+    out[p] = g_apply(in, pz, y, x, H, W, nz);
 }
 
 // dL/dy = 2 (y - t) / N with t = (u - ubar) / s; per-block partial sums of (y - t)^2
@@ -298,17 +351,18 @@ __global__ void k_loss_fin(const double *part, int64_t nblk, int64_t N, double *
 
 // input gradient of layer 6 through the ReLU of layer 5:
 // dz5[p][c] = (sum_t W6[t][c] dy[p - off(t)]) * (a5[p][c] > 0)
-__global__ void k_out_bwd(const float *dy, const bf16 *w6, const bf16 *a5, bf16 *dz, int H, int W, int64_t N) {
+template <int NT>
+__global__ void k_out_bwd(const float *dy, const bf16 *w6, const bf16 *a5, bf16 *dz, int H, int W, int nz, int64_t N) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int64_t HW = (int64_t)H * W;
-    const int64_t b = p / HW;
+    const int64_t pz = p / HW;
     const int rem = (int)(p % HW), y = rem / W, x = rem % W;
-    float g[9];
+    float g[NT];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int yy = wrap(y - (t / 3 - 1), H), xx = wrap(x - (t % 3 - 1), W);
-        g[t] = dy[b * HW + (int64_t)yy * W + xx];
+    for (int t = 0; t < NT; ++t) {
+        const int yy = wrap(y - tap_dy(t), H), xx = wrap(x - tap_dx(t), W);
+        g[t] = dy[plane_shift(pz, nz, -tap_dz<NT>(t)) * HW + (int64_t)yy * W + xx];
     }
     alignas(16) bf16 m[C], o[C];
 #pragma unroll
@@ -317,21 +371,22 @@ __global__ void k_out_bwd(const float *dy, const bf16 *w6, const bf16 *a5, bf16 
     for (int c = 0; c < C; ++c) {
         float acc = 0.0f;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc += (float)w6[t * C + c] * g[t];
+        for (int t = 0; t < NT; ++t) acc += (float)w6[t * C + c] * g[t];
         o[c] = (bf16)((float)m[c] > 0.0f ? acc : 0.0f);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) reinterpret_cast<uint4 *>(dz + p * C)[q] = reinterpret_cast<const uint4 *>(o)[q];
 }
 
-// Weight gradient of one layer over the points of this block's tiles:
+// Weight gradient of one layer (one 3x3 slice: the input x is read from the
+// plane shifted by dzo) over the points of this block's tiles:
 // dW[o][t][c] = sum_p g[p][o] x[p + off(t)][c], db[o] = sum_p g[p][o].
 // x: CI channels (32: bf16 activations; 1: ubar / s); g: CO channels
 // (32: bf16 gradients; 1: FP32 dL/dy).  part[block][CO*9*CI + CO].
 template <int CI, int CO, typename T>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16 *xa, const T *ub, const double *s, const bf16 *ga,
-                                               const float *gf, float *part, int H, int W, int tiles_x, int tiles_y,
-                                               int64_t ntiles) {
+                                               const float *gf, float *part, int H, int W, int nz, int dzo,
+                                               int tiles_x, int tiles_y, int64_t ntiles) {
     constexpr int NWL = CO * 9 * CI + CO;
     constexpr int SLOTS = (NWL + 255) / 256;
     __shared__ float xs[(WGY + 2) * (WGX + 2) * CI];
@@ -343,15 +398,16 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *xa, const T *ub, cons
     const int64_t HW = (int64_t)H * W;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int tx = (int)(tile % tiles_x), ty = (int)((tile / tiles_x) % tiles_y);
-        const int64_t b = tile / ((int64_t)tiles_x * tiles_y);
+        const int64_t b = tile / ((int64_t)tiles_x * tiles_y);  // output plane
+        const int64_t bx = plane_shift(b, nz, dzo);              // input plane
         const int x0 = tx * WGX, y0 = ty * WGY;
         for (int q = tid; q < (WGY + 2) * (WGX + 2) * CI; q += 256) {
             const int pix = q / CI, c = q % CI;
             const int r = pix / (WGX + 2), cc = pix % (WGX + 2);
             const int gy = (int)((y0 + r - 1 + (int64_t)H) % H), gx = (int)((x0 + cc - 1 + (int64_t)W) % W);
-            const int64_t g = b * HW + (int64_t)gy * W + gx;
+            const int64_t g = bx * HW + (int64_t)gy * W + gx;
             float v;
-            if constexpr (CI == 1) v = (float)ub[g] * (float)(1.0 / s[b]);
+            if constexpr (CI == 1) v = (float)ub[g] * (float)(1.0 / s[bx / nz]);
             else v = (float)xa[g * CI + c];
             xs[q] = v;
         }
@@ -401,9 +457,10 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *xa, const T *ub, cons
 // transposed, gT[o][p], and three transposed copies of the input tile with its
 // halo, shifted by dx = 0, 1, 2 (xs[dx][c][row][j] = x[row][j + dx]), so every
 // 8-point operand is one aligned 16-byte read.  Wave w owns taps w, w+4, w+8.
-// Also the bias gradient db[o] = sum_p g[p][o].  part[block][32 * 288 + 32].
-__global__ __launch_bounds__(256) void k_wgrad_mid(const bf16 *xa, const bf16 *ga, float *part, int H, int W,
-                                                   int tiles_x, int tiles_y, int64_t ntiles) {
+// Also the bias gradient db[o] = sum_p g[p][o].  The input comes from the
+// plane shifted by dzo (one 3x3 slice of a 3D layer).  part[block][32*288+32].
+__global__ __launch_bounds__(256) void k_wgrad_mid(const bf16 *xa, const bf16 *ga, float *part, int H, int W, int nz,
+                                                   int dzo, int tiles_x, int tiles_y, int64_t ntiles) {
     constexpr int NP = WGY * WGX;        // points per tile
     constexpr int XR = WGY + 2;          // input rows with the halo
     constexpr int GST = NP + 8;          // padded row of gT (bf16)
@@ -433,7 +490,7 @@ __global__ __launch_bounds__(256) void k_wgrad_mid(const bf16 *xa, const bf16 *g
             const int pix = q / C, c = q % C;
             const int r = pix / (WGX + 2), col = pix % (WGX + 2);
             const int gy = (int)((y0 + r - 1 + (int64_t)H) % H), gx = (int)((x0 + col - 1 + (int64_t)W) % W);
-            const bf16 v = xa[(b * HW + (int64_t)gy * W + gx) * C + c];
+            const bf16 v = xa[(plane_shift(b, nz, dzo) * HW + (int64_t)gy * W + gx) * C + c];
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
                 const int jc = col - dx;
@@ -474,9 +531,12 @@ __global__ __launch_bounds__(256) void k_wgrad_mid(const bf16 *xa, const bf16 *g
     if (tid < C) pb[C * K + tid] = db;
 }
 
-// grad[w] = sum over blocks (in block order) of part[block][w]; the layer's
-// weights and biases are consecutive in the parameter vector.
-__global__ void k_reduce(const float *part, int nblk, int nw, float *grad) {
+// grad = sum over blocks (in a fixed order) of part[block][w], where part
+// holds one 3x3 slice [o][9][c] + biases; slice dzi of NT taps is scattered to
+// W[o][dzi * 9 + t][c] (the identity in 2D) and the biases are written by the
+// slice `bias_dzi` only.  grad points at the layer's first weight.
+__global__ void k_reduce(const float *part, int nblk, int nw, float *grad, int NT, int dzi, int bias_dzi, int CI,
+                         int CO) {
     // 32 weights per workgroup, 8 lanes per weight summing every 8th block,
     // then the 8 lane sums in lane order: a fixed order for every run
     __shared__ double red[8][32];
@@ -490,7 +550,13 @@ __global__ void k_reduce(const float *part, int nblk, int nw, float *grad) {
     if (g == 0 && i < nw) {
         double t = 0.0;
         for (int q = 0; q < 8; ++q) t += red[q][wl];
-        grad[i] = (float)t;
+        const int nwt = CO * 9 * CI;
+        if (i < nwt) {
+            const int o = i / (9 * CI), tp = (i / CI) % 9, c = i % CI;
+            grad[((int64_t)o * NT + dzi * 9 + tp) * CI + c] = (float)t;
+        } else if (dzi == bias_dzi) {
+            grad[(int64_t)CO * NT * CI + (i - nwt)] = (float)t;
+        }
     }
 }
 
@@ -528,27 +594,34 @@ int fail(int code, const char *fmt, ...) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t wbf, wT, s, rms, act, z, y, dy, dyz, dz, lpart, wpart, grad, total;
+    size_t wbf, wT, wf, s, rms, act, accb, z, y, dy, dyz, dz, lpart, wpart, grad, total;
     int64_t N, nblk_pix;
     int nblk_w;
 };
 
+int taps_of(int ndim) { return ndim == 3 ? 27 : 9; }
+int64_t planes_of(const gd_grid *g) { return g->batch * (g->ndim == 3 ? g->n[2] : 1); }
+
 int64_t wgrad_tiles(const gd_grid *g) {
-    return g->batch * ((g->n[1] + WGY - 1) / WGY) * ((g->n[0] + WGX - 1) / WGX);
+    return planes_of(g) * ((g->n[1] + WGY - 1) / WGY) * ((g->n[0] + WGX - 1) / WGX);
 }
 
 Layout layout(const gd_grid *g, bool training, bool own_grad) {
-    const Offsets off = offsets();
+    const int NT = taps_of(g->ndim), ndz = NT / 9;
+    const Offsets off = offsets(NT);
     Layout L;
     std::memset(&L, 0, sizeof L);
-    L.N = g->batch * g->n[0] * g->n[1];
+    L.N = planes_of(g) * g->n[0] * g->n[1];
     L.nblk_pix = (L.N + 255) / 256;
     L.nblk_w = (int)std::min<int64_t>(wgrad_tiles(g), 512);
+    const size_t slices = (size_t)NMID * ndz * C * K9 * 2;  // bf16 weight slices of the 32 -> 32 layers
     size_t o = 0;
     L.wbf = o;
     o = align_up(o + (size_t)off.total * 2, 256);
     L.wT = o;
-    if (training) o = align_up(o + (size_t)NMID * C * K * 2, 256);
+    if (training) o = align_up(o + slices, 256);
+    L.wf = o;
+    if (ndz > 1) o = align_up(o + slices, 256);
     L.s = o;
     o = align_up(o + (size_t)g->batch * 8, 256);
     L.rms = o;
@@ -556,6 +629,8 @@ Layout layout(const gd_grid *g, bool training, bool own_grad) {
     L.act = o;
     const size_t actb = align_up((size_t)L.N * C * 2, 256);
     o += (training ? NL - 1 : 2) * actb;
+    L.accb = o;
+    if (ndz > 1) o = align_up(o + (size_t)L.N * C * 4, 256);
     L.z = o;
     o = align_up(o + (size_t)L.N * 4, 256);
     if (training) {
@@ -582,7 +657,7 @@ Layout layout(const gd_grid *g, bool training, bool own_grad) {
 
 int check_net(const gd_cnn *net, bool training) {
     if (!net) return fail(GD_EINVAL, "network is NULL");
-    if (net->ndim != 2) return fail(GD_EINVAL, "only the 2D network is built (ndim %d)", net->ndim);
+    if (net->ndim != 2 && net->ndim != 3) return fail(GD_EINVAL, "the network is 2D or 3D (ndim %d)", net->ndim);
     if (net->channels != C || net->layers != NL)
         return fail(GD_EINVAL, "the network has %d layers of %d channels", NL, C);
     if (!net->params) return fail(GD_EINVAL, "params is NULL");
@@ -591,13 +666,15 @@ int check_net(const gd_cnn *net, bool training) {
     return GD_OK;
 }
 
-int check_grid(const gd_grid *g) {
+int check_grid(const gd_cnn *net, const gd_grid *g) {
     if (!g) return fail(GD_EINVAL, "grid is NULL");
-    if (g->ndim != 2) return fail(GD_EINVAL, "the warm start is built for 2D fields only");
+    if (g->ndim != net->ndim) return fail(GD_EINVAL, "a %dD network needs %dD fields", net->ndim, net->ndim);
     if (g->dtype != GD_F32 && g->dtype != GD_F64) return fail(GD_EINVAL, "dtype must be GD_F32 or GD_F64");
-    if (g->n[0] < 1 || g->n[1] < 1 || g->batch < 1) return fail(GD_EINVAL, "sizes must be >= 1");
-    if (g->n[0] * g->n[1] >= (int64_t(1) << 31) || g->n[0] * g->n[1] * g->batch > (int64_t(1) << 34) ||
-        g->batch > 65535)
+    if (g->n[0] < 1 || g->n[1] < 1 || g->batch < 1 || (g->ndim == 3 && g->n[2] < 1))
+        return fail(GD_EINVAL, "sizes must be >= 1");
+    const int64_t planes = planes_of(g);
+    if (g->n[0] * g->n[1] >= (int64_t(1) << 31) || g->n[0] * g->n[1] * planes > (int64_t(1) << 34) ||
+        g->batch > 65535 || planes > (int64_t(1) << 24))
         return fail(GD_EINVAL, "field too large");
     return GD_OK;
 }
@@ -609,69 +686,118 @@ int check_grid(const gd_grid *g) {
         if (e_ != hipSuccess) return fail(GD_EHIP, "launch: %s", hipGetErrorString(e_)); \
     } while (0)
 
+// One 32 -> 32 layer (forward, or its input gradient with BWD): the 2D layer
+// in one matrix-core pass; a 3D layer as three plane-shifted passes
+// accumulated in FP32, then bias and ReLU (or the mask) into bf16.
+int mid_layer(bool bwd, const gd_grid *g, const Layout &L, char *w, const bf16 *in, const bf16 *slices,
+              const float *bias, const bf16 *mask, bf16 *out, hipStream_t st) {
+    const int NT = taps_of(g->ndim), ndz = NT / 9;
+    const int H = (int)g->n[1], W = (int)g->n[0], nz = g->ndim == 3 ? (int)g->n[2] : 1;
+    const int tiles_x = (W + TX - 1) / TX, tiles_y = (H + TY - 1) / TY;
+    const unsigned cblk = (unsigned)(planes_of(g) * tiles_x * tiles_y);
+    if (ndz == 1) {
+        if (bwd)
+            GD_LAUNCH(k_conv_mid<kBwd>, dim3(cblk), dim3(256), 0, st, in, slices, (const float *)nullptr, mask, out,
+                      (float *)nullptr, 0, H, W, nz, 0, tiles_x, tiles_y);
+        else
+            GD_LAUNCH(k_conv_mid<kFwd>, dim3(cblk), dim3(256), 0, st, in, slices, bias, (const bf16 *)nullptr, out,
+                      (float *)nullptr, 0, H, W, nz, 0, tiles_x, tiles_y);
+        return GD_OK;
+    }
+    float *accb = (float *)(w + L.accb);
+    for (int dzi = 0; dzi < ndz; ++dzi)
+        GD_LAUNCH(k_conv_mid<kAcc>, dim3(cblk), dim3(256), 0, st, in, slices + (size_t)dzi * C * K9,
+                  (const float *)nullptr, (const bf16 *)nullptr, (bf16 *)nullptr, accb, dzi == 0 ? 1 : 0, H, W, nz,
+                  dzi - 1, tiles_x, tiles_y);
+    const int64_t n = L.N * C;
+    GD_LAUNCH(k_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const float *)accb, bwd ? nullptr : bias,
+              bwd ? mask : (const bf16 *)nullptr, out, n);
+    return GD_OK;
+}
+
 // forward (train = false: u0 out; train = true: keep every activation and y)
 template <typename T>
 int run_forward(const gd_cnn *net, const gd_grid *g, const Layout &L, char *w, const T *ub, T *u0, bool train,
                 hipStream_t st) {
-    const Offsets off = offsets();
-    const int H = (int)g->n[1], W = (int)g->n[0];
-    const int64_t HW = (int64_t)H * W, N = L.N;
+    const int NT = taps_of(g->ndim), ndz = NT / 9;
+    const Offsets off = offsets(NT);
+    const int H = (int)g->n[1], W = (int)g->n[0], nz = g->ndim == 3 ? (int)g->n[2] : 1;
+    const int64_t P = (int64_t)H * W * nz, N = L.N;
     bf16 *wbf = (bf16 *)(w + L.wbf);
     double *s = (double *)(w + L.s);
     const size_t actb = align_up((size_t)N * C * 2, 256);
     auto act = [&](int i) { return (bf16 *)(w + L.act + (size_t)i * actb); };
     const unsigned pblk = (unsigned)L.nblk_pix;
     GD_LAUNCH(k_cvt, dim3((unsigned)((off.total + 255) / 256)), dim3(256), 0, st, net->params, wbf, off.total);
-    GD_LAUNCH(k_rms_part<T>, dim3(RMS_CHUNKS, (unsigned)g->batch), dim3(256), 0, st, ub, HW, (double *)(w + L.rms));
+    bf16 *wf = (bf16 *)(w + L.wf);  // 3D: forward weight slices
+    if (ndz > 1)
+        GD_LAUNCH(k_repack<false>, dim3((unsigned)((NMID * ndz * C * K9 + 255) / 256)), dim3(256), 0, st,
+                  (const bf16 *)wbf, off.W[1], off.W[2] - off.W[1], NT, wf);
+    GD_LAUNCH(k_rms_part<T>, dim3(RMS_CHUNKS, (unsigned)g->batch), dim3(256), 0, st, ub, P, (double *)(w + L.rms));
     GD_LAUNCH(k_rms_fin, dim3((unsigned)((g->batch + 63) / 64)), dim3(64), 0, st, (const double *)(w + L.rms),
-              (int)g->batch, HW, s);
-    GD_LAUNCH(k_conv_in<T>, dim3(pblk), dim3(256), 0, st, ub, s, wbf + off.W[0], net->params + off.b[0], act(0), H, W,
-              N);
-    const int tiles_x = (W + TX - 1) / TX, tiles_y = (H + TY - 1) / TY;
-    const unsigned cblk = (unsigned)(g->batch * tiles_x * tiles_y);
+              (int)g->batch, P, s);
+    if (NT == 9)
+        GD_LAUNCH((k_conv_in<T, 9>), dim3(pblk), dim3(256), 0, st, ub, (const double *)s, (const bf16 *)(wbf + off.W[0]),
+                  (const float *)(net->params + off.b[0]), act(0), H, W, nz, N);
+    else
+        GD_LAUNCH((k_conv_in<T, 27>), dim3(pblk), dim3(256), 0, st, ub, (const double *)s,
+                  (const bf16 *)(wbf + off.W[0]), (const float *)(net->params + off.b[0]), act(0), H, W, nz, N);
+    int rc;
     for (int m = 0; m < NMID; ++m) {
         const int l = m + 1;
         bf16 *src = train ? act(m) : act(m & 1);
         bf16 *dst = train ? act(m + 1) : act((m + 1) & 1);
-        GD_LAUNCH(k_conv_mid<false>, dim3(cblk), dim3(256), 0, st, src, wbf + off.W[l], net->params + off.b[l],
-                  (const bf16 *)nullptr, dst, H, W, tiles_x, tiles_y);
+        const bf16 *slices = ndz > 1 ? wf + (size_t)m * ndz * C * K9 : wbf + off.W[l];
+        if ((rc = mid_layer(false, g, L, w, src, slices, net->params + off.b[l], nullptr, dst, st))) return rc;
     }
     bf16 *last = train ? act(NL - 2) : act(NMID & 1);
-    GD_LAUNCH(k_conv_out, dim3(pblk), dim3(256), 0, st, (const bf16 *)last, (const bf16 *)(wbf + off.W[NL - 1]),
-              (const float *)(net->params + off.b[NL - 1]), (float *)(w + L.z), H, W, N);
+    if (NT == 9)
+        GD_LAUNCH(k_conv_out<9>, dim3(pblk), dim3(256), 0, st, (const bf16 *)last, (const bf16 *)(wbf + off.W[NL - 1]),
+                  (const float *)(net->params + off.b[NL - 1]), (float *)(w + L.z), H, W, nz, N);
+    else
+        GD_LAUNCH(k_conv_out<27>, dim3(pblk), dim3(256), 0, st, (const bf16 *)last, (const bf16 *)(wbf + off.W[NL - 1]),
+                  (const float *)(net->params + off.b[NL - 1]), (float *)(w + L.z), H, W, nz, N);
     GD_LAUNCH(k_gfin<T>, dim3(pblk), dim3(256), 0, st, (const float *)(w + L.z), ub, (const double *)s,
-              train ? (float *)(w + L.y) : (float *)nullptr, train ? (T *)nullptr : u0, H, W, N);
+              train ? (float *)(w + L.y) : (float *)nullptr, train ? (T *)nullptr : u0, H, W, nz, N);
     return GD_OK;
 }
 
+// Weight gradient of layer (CI -> CO) into grad_layer (its first weight): one
+// pass per 3x3 slice (dz), each reduced and scattered into place.
 template <int CI, int CO, typename T>
 int wgrad_layer(const gd_grid *g, const Layout &L, char *w, const bf16 *xa, const T *ub, const double *s,
                 const bf16 *ga, const float *gf, float *grad_layer, hipStream_t st) {
     constexpr int NWL = CO * 9 * CI + CO;
-    const int H = (int)g->n[1], W = (int)g->n[0];
+    const int NT = taps_of(g->ndim), ndz = NT / 9;
+    const int H = (int)g->n[1], W = (int)g->n[0], nz = g->ndim == 3 ? (int)g->n[2] : 1;
     const int tiles_x = (W + WGX - 1) / WGX, tiles_y = (H + WGY - 1) / WGY;
     const int64_t ntiles = wgrad_tiles(g);
     float *part = (float *)(w + L.wpart);
-    if constexpr (CI == C && CO == C) {
-        GD_LAUNCH(k_wgrad_mid, dim3((unsigned)L.nblk_w), dim3(256), 0, st, xa, ga, part, H, W, tiles_x, tiles_y,
-                  ntiles);
-    } else {
-        auto kern = k_wgrad<CI, CO, T>;
-        GD_LAUNCH(kern, dim3((unsigned)L.nblk_w), dim3(256), 0, st, xa, ub, s, ga, gf, part, H, W, tiles_x, tiles_y,
-                  ntiles);
+    for (int dzi = 0; dzi < ndz; ++dzi) {
+        const int dzo = ndz > 1 ? dzi - 1 : 0;
+        if constexpr (CI == C && CO == C) {
+            GD_LAUNCH(k_wgrad_mid, dim3((unsigned)L.nblk_w), dim3(256), 0, st, xa, ga, part, H, W, nz, dzo, tiles_x,
+                      tiles_y, ntiles);
+        } else {
+            auto kern = k_wgrad<CI, CO, T>;
+            GD_LAUNCH(kern, dim3((unsigned)L.nblk_w), dim3(256), 0, st, xa, ub, s, ga, gf, part, H, W, nz, dzo,
+                      tiles_x, tiles_y, ntiles);
+        }
+        GD_LAUNCH(k_reduce, dim3((NWL + 31) / 32), dim3(256), 0, st, (const float *)part, L.nblk_w, NWL, grad_layer,
+                  NT, dzi, (ndz - 1) / 2, CI, CO);
     }
-    GD_LAUNCH(k_reduce, dim3((NWL + 31) / 32), dim3(256), 0, st, (const float *)part, L.nblk_w, NWL, grad_layer);
     return GD_OK;
 }
 
 template <typename T>
 int run_train(const gd_cnn *net, const gd_grid *g, const Layout &L, char *w, const T *ub, const T *u, double *loss,
               hipStream_t st) {
-    const Offsets off = offsets();
+    const int NT = taps_of(g->ndim), ndz = NT / 9;
+    const Offsets off = offsets(NT);
     int rc = run_forward<T>(net, g, L, w, ub, nullptr, true, st);
     if (rc) return rc;
-    const int H = (int)g->n[1], W = (int)g->n[0];
-    const int64_t HW = (int64_t)H * W, N = L.N;
+    const int H = (int)g->n[1], W = (int)g->n[0], nz = g->ndim == 3 ? (int)g->n[2] : 1;
+    const int64_t P = (int64_t)H * W * nz, N = L.N;
     bf16 *wbf = (bf16 *)(w + L.wbf);
     bf16 *wT = (bf16 *)(w + L.wT);
     const double *s = (const double *)(w + L.s);
@@ -681,28 +807,29 @@ int run_train(const gd_cnn *net, const gd_grid *g, const Layout &L, char *w, con
     float *grad = net->grad ? net->grad : (float *)(w + L.grad);
     float *dy = (float *)(w + L.dy);
     const unsigned pblk = (unsigned)L.nblk_pix;
-    GD_LAUNCH(k_transpose, dim3((unsigned)((NMID * C * K + 255) / 256)), dim3(256), 0, st, (const bf16 *)wbf, off.W[1],
-              off.W[2] - off.W[1], wT);
+    GD_LAUNCH(k_repack<true>, dim3((unsigned)((NMID * ndz * C * K9 + 255) / 256)), dim3(256), 0, st, (const bf16 *)wbf,
+              off.W[1], off.W[2] - off.W[1], NT, wT);
     GD_LAUNCH(k_loss<T>, dim3(pblk), dim3(256), 0, st, (const float *)(w + L.y), ub, u, s, dy,
-              (double *)(w + L.lpart), HW, N);
+              (double *)(w + L.lpart), P, N);
     GD_LAUNCH(k_loss_fin, dim3(1), dim3(256), 0, st, (const double *)(w + L.lpart), L.nblk_pix, N, loss);
     // through the final filter: dL/dz = G dL/dy
     float *dyz = (float *)(w + L.dyz);
-    GD_LAUNCH(k_gfilt, dim3(pblk), dim3(256), 0, st, (const float *)dy, dyz, H, W, N);
+    GD_LAUNCH(k_gfilt, dim3(pblk), dim3(256), 0, st, (const float *)dy, dyz, H, W, nz, N);
     // layer 6
     if ((rc = wgrad_layer<C, 1, T>(g, L, w, act(NL - 2), ub, s, nullptr, dyz, grad + off.W[NL - 1], st))) return rc;
-    GD_LAUNCH(k_out_bwd, dim3(pblk), dim3(256), 0, st, (const float *)dyz, (const bf16 *)(wbf + off.W[NL - 1]),
-              (const bf16 *)act(NL - 2), dz(0), H, W, N);
+    if (NT == 9)
+        GD_LAUNCH(k_out_bwd<9>, dim3(pblk), dim3(256), 0, st, (const float *)dyz, (const bf16 *)(wbf + off.W[NL - 1]),
+                  (const bf16 *)act(NL - 2), dz(0), H, W, nz, N);
+    else
+        GD_LAUNCH(k_out_bwd<27>, dim3(pblk), dim3(256), 0, st, (const float *)dyz, (const bf16 *)(wbf + off.W[NL - 1]),
+                  (const bf16 *)act(NL - 2), dz(0), H, W, nz, N);
     // layers 5 .. 2: dz(k) holds the gradient at the output of layer l
-    const int tiles_x = (W + TX - 1) / TX, tiles_y = (H + TY - 1) / TY;
-    const unsigned cblk = (unsigned)(g->batch * tiles_x * tiles_y);
     int k = 0;
     for (int l = NL - 2; l >= 1; --l, ++k) {
         const bf16 *xin = act(l - 1);  // input activation of layer l
         if ((rc = wgrad_layer<C, C, T>(g, L, w, xin, ub, s, dz(k), nullptr, grad + off.W[l], st))) return rc;
-        GD_LAUNCH(k_conv_mid<true>, dim3(cblk), dim3(256), 0, st, (const bf16 *)dz(k),
-                  (const bf16 *)(wT + (size_t)(l - 1) * C * K), (const float *)nullptr, xin, dz(k + 1), H, W, tiles_x,
-                  tiles_y);
+        if ((rc = mid_layer(true, g, L, w, dz(k), wT + (size_t)(l - 1) * ndz * C * K9, nullptr, xin, dz(k + 1), st)))
+            return rc;
     }
     // layer 1 (input x0 = ubar / s)
     if ((rc = wgrad_layer<1, C, T>(g, L, w, nullptr, ub, s, dz(k), nullptr, grad + off.W[0], st))) return rc;
@@ -720,12 +847,12 @@ using namespace gdcnn;
 extern "C" {
 
 int64_t warmstart_param_count(const gd_cnn *net) {
-    if (!net || net->ndim != 2 || net->channels != C || net->layers != NL) return 0;
-    return offsets().total;
+    if (!net || (net->ndim != 2 && net->ndim != 3) || net->channels != C || net->layers != NL) return 0;
+    return offsets(taps_of(net->ndim)).total;
 }
 
 size_t warmstart_workspace_bytes(const gd_cnn *net, const gd_grid *g, int32_t training) {
-    if (check_net(net, false) || check_grid(g)) return 0;
+    if (check_net(net, false) || check_grid(net, g)) return 0;
     return layout(g, training != 0, !net->grad).total;
 }
 
@@ -733,7 +860,7 @@ int warmstart_forward(const gd_cnn *net, const gd_grid *g, const void *ubar, voi
                       void *stream) {
     int rc = check_net(net, false);
     if (rc) return rc;
-    if ((rc = check_grid(g))) return rc;
+    if ((rc = check_grid(net, g))) return rc;
     if (!ubar || !u0) return fail(GD_EINVAL, "ubar and u0 must be non-NULL");
     if (ubar == u0) return fail(GD_EINVAL, "ubar and u0 must differ");
     if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
@@ -750,7 +877,7 @@ int warmstart_train_step(const gd_cnn *net, const gd_grid *g, const void *ubar, 
                          size_t work_bytes, double *loss, void *stream) {
     int rc = check_net(net, true);
     if (rc) return rc;
-    if ((rc = check_grid(g))) return rc;
+    if ((rc = check_grid(net, g))) return rc;
     if (!ubar || !u || !loss) return fail(GD_EINVAL, "ubar, u and loss must be non-NULL");
     if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
     if ((uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be 256-byte aligned");

@@ -441,19 +441,22 @@ def deconvolve_batch(solver: str, ubars, max_iter: int, tol: float = 0.0, init: 
 
 class WarmStart:
     """The learned warm start (warmstart_forward / warmstart_train_step): a
-    2D periodic CNN whose output u0 = ubar + s * f(ubar / s) starts a solve with
-    init='given'.  Owns its FP32 parameters, Adam moments and step counter on
-    the device.  ``params``: initial flat FP32/FP64 vector (for example
-    synth.cnn_init_params(seed))."""
+    periodic CNN (3x3 taps for ndim=2, 3x3x3 for ndim=3) whose output
+    u0 = ubar + s * G f(ubar / s) starts a solve with init='given'.  Owns its
+    FP32 parameters, Adam moments and step counter on the device.  ``params``:
+    initial flat FP32/FP64 vector (for example synth.cnn_init_params(seed,
+    ndim=ndim)).  Fields: (ny, nx) / (batch, ny, nx) in 2D, (nz, ny, nx) /
+    (batch, nz, ny, nx) in 3D."""
 
     CHANNELS, LAYERS = 32, 6
 
     def __init__(self, params, device=None, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
-                 eps: float = 1e-8):
+                 eps: float = 1e-8, ndim: int = 2):
         self.lib = load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.ndim = ndim
         self.net = Cnn()
-        self.net.ndim, self.net.channels, self.net.layers = 2, self.CHANNELS, self.LAYERS
+        self.net.ndim, self.net.channels, self.net.layers = ndim, self.CHANNELS, self.LAYERS
         self.net.lr, self.net.beta1, self.net.beta2, self.net.eps = lr, beta1, beta2, eps
         n = int(self.lib.warmstart_param_count(ctypes.byref(self.net)))
         p = torch.as_tensor(np.asarray(params), dtype=torch.float32).reshape(-1)
@@ -474,9 +477,9 @@ class WarmStart:
         self.net.lr = float(lr)
 
     def _grid(self, x: torch.Tensor) -> Grid:
-        if x.dim() not in (2, 3):
-            raise ValueError("fields are (ny, nx) or (batch, ny, nx)")
-        return make_grid(x.shape, 2, x.dtype)
+        if x.dim() not in (self.ndim, self.ndim + 1):
+            raise ValueError(f"{self.ndim}D fields, with an optional leading batch dimension")
+        return make_grid(x.shape, self.ndim, x.dtype)
 
     def _workspace(self, g: Grid, training: bool) -> torch.Tensor:
         key = (int(g.n[0]), int(g.n[1]), int(g.batch), int(g.dtype), training)

@@ -126,12 +126,86 @@ def test_training_lowers_loss_and_warm_start_solves():
     assert infos_w[0]["r_true"] <= 2e-6 * infos_w[0]["r_ref"]
 
 
-def test_rejects_3d_and_bad_shapes():
+def test_rejects_mismatched_dimensions():
     ws = gdecon.WarmStart(synth.cnn_init_params(0))
-    g = gdecon.make_grid((4, 8, 8), 3, torch.float32)
+    g = gdecon.make_grid((4, 8, 8), 3, torch.float32)     # 3D fields for the 2D network
     lib = gdecon.load()
     assert lib.warmstart_workspace_bytes(ws.net, g, 0) == 0
     x = torch.zeros((4, 8, 8), device="cuda")
     assert lib.warmstart_forward(ws.net, g, x.data_ptr(), torch.zeros_like(x).data_ptr(), x.data_ptr(), 1 << 20,
                                  None) == -1
     assert "2D" in lib.gd_last_error().decode()
+    assert lib.warmstart_param_count(gdecon.WarmStart(synth.cnn_init_params(0, ndim=3), ndim=3).net) == 112481
+
+
+# ------------------------------------------------------------------ 3D network
+def fields3(shape, B, seed):
+    u = np.stack([oracle.filter(np.random.default_rng(seed + i).standard_normal(shape), 3) for i in range(B)])
+    ub = np.stack([oracle.filter(x, 3) for x in u])
+    return ub.astype(np.float32).astype(np.float64), u.astype(np.float32).astype(np.float64)
+
+
+def params3_with_bias(seed):
+    p = synth.cnn_init_params(seed, ndim=3)
+    r = np.random.default_rng(seed + 200)
+    for W, b in cnn.unpack(p, ndim=3):
+        b[:] = 0.05 * r.standard_normal(b.shape)
+    return p
+
+
+@pytest.mark.parametrize("shape", [(6, 10, 40), (1, 3, 5), (3, 9, 33), (16, 16, 16)])
+def test_forward_3d_matches_reference(shape):
+    p = params3_with_bias(1)
+    ub, _ = fields3(shape, 2, 60)
+    ws = gdecon.WarmStart(p, ndim=3)
+    u0 = ws.forward(to_dev(ub, torch.float32))
+    torch.cuda.synchronize()
+    got = u0.double().cpu().numpy()
+    ref = cnn.forward(p, ub, emulate_bf16=True, ndim=3)
+    s = ref["s"][:, None, None, None]
+    y_got = (got - ub) / s
+    assert rel_l2(y_got, ref["y"]) <= 3e-3, rel_l2(y_got, ref["y"])
+    assert rel_l2(y_got, cnn.forward(p, ub, ndim=3)["y"]) <= 2e-2
+    u1 = ws.forward(to_dev(ub, torch.float32))
+    torch.cuda.synchronize()
+    assert torch.equal(u0, u1)
+
+
+def test_gradients_and_adam_3d_match_reference():
+    p = params3_with_bias(2)
+    ub, u = fields3((6, 12, 36), 2, 70)
+    ws = gdecon.WarmStart(p, lr=1e-3, ndim=3)
+    loss = ws.train_step(to_dev(ub, torch.float32), to_dev(u, torch.float32))
+    torch.cuda.synchronize()
+    g_gpu = ws.grad.double().cpu().numpy()
+    l_ref, g_ref = cnn.loss_and_grad(p, ub, u, emulate_bf16=True, ndim=3)
+    assert abs(loss.item() - l_ref) <= 3e-3 * l_ref
+    off = 0
+    for li, (W, b) in enumerate(cnn.unpack(p, ndim=3)):
+        n = W.size + b.size
+        e = rel_l2(g_gpu[off:off + n], g_ref[off:off + n])
+        assert e <= 2e-2, (li, e)
+        off += n
+    p32 = p.astype(np.float32).astype(np.float64)
+    want, _, _ = cnn.adam_step(p32, np.zeros_like(p32), np.zeros_like(p32), g_gpu, 1, lr=1e-3)
+    np.testing.assert_allclose(ws.params.double().cpu().numpy(), want, rtol=1e-5, atol=1e-7)
+
+
+def test_training_3d_lowers_loss_and_warm_start_solves():
+    """Empirical: a short 3D training run lowers the loss, and the trained
+    network's u0 starts a 3D BiCGSTAB solve that converges."""
+    fields = synth.training_pairs_3d(4, n=32)
+    u = torch.from_numpy(np.stack(fields)).cuda()
+    ub = gdecon.filter_apply(u, ndim=3)
+    ws = gdecon.WarmStart(synth.cnn_init_params(0, ndim=3), lr=2e-3, ndim=3)
+    first = ws.train_step(ub, u).item()
+    for _ in range(80):
+        ws.train_step(ub, u)
+    last = ws.train_step(ub, u).item()
+    assert last < 0.7 * first, (first, last)
+    test = torch.from_numpy(synth.training_pairs_3d(1, n=32, seed0=50)[0]).cuda()[None]
+    tub = gdecon.filter_apply(test, ndim=3)
+    u0 = ws.forward(tub)
+    _, infos, _ = gdecon.deconvolve("bicgstab", tub, 100, tol=1e-6, ndim=3, init="given", u0=u0)
+    assert infos[0]["status_name"] == "CONVERGED"
+    assert infos[0]["r_true"] <= 2e-6 * infos[0]["r_ref"]
