@@ -72,13 +72,14 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_solve_kernel_bicgstab
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the kernel sources, the build script and the C header."""
+    """sha256 over the solve kernel's sources (every library source except the
+    warm-start network's), the build script and the C header."""
     import glob
     import hashlib
     csrc = os.path.join(ROOT, "paper_1707_09177_amd", "csrc")
-    files = sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))
-                   + glob.glob(os.path.join(csrc, "*.inc")) + [os.path.join(csrc, "build.py"),
-                                                               os.path.join(ROOT, "include", "gdecon.h")])
+    files = sorted(f for f in glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))
+                   + glob.glob(os.path.join(csrc, "*.inc")) if os.path.basename(f) != "gd_cnn.hip")
+    files += [os.path.join(csrc, "build.py"), os.path.join(ROOT, "include", "gdecon.h")]
     h = hashlib.sha256()
     for f in files:
         h.update(os.path.relpath(f, ROOT).encode())
@@ -274,6 +275,7 @@ def main_warm(args, w, torch, gd, dev):
                       worst_true_rel_residual=max(i["r_true"] / i["r_ref"] for i in inf),
                       r0_over_ref_mean=float(np.mean([i["r0"] / i["r_ref"] for i in inf])))
     m = res["cnn"]
+    res3 = warm_3d(gd, torch, dev, synth, timed, args)
     out_line = {
         "metric": METRIC, "value": npts / (m["ms"] * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": 1, "ms_per_step": m["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -282,8 +284,58 @@ def main_warm(args, w, torch, gd, dev):
                    "solver": "bicgstab", "tol": 1e-6, "train_steps": steps_train, "train_batch": batch},
         "warmstart": {"train_seconds": train_s, "loss_first": first, "loss_last": last, "starts": res,
                       "cnn_vs_ubar_time": res["ubar"]["ms"] / m["ms"]},
+        "warmstart_3d": res3,
     }
     print(json.dumps(out_line))
+
+
+def warm_3d(gd, torch, dev, synth, timed, args, n_train=64, n_eval=128, count_eval=8):
+    """3D network: trained on 64^3 k^-5/3 fields (batches of 4), evaluated on
+    held-out 128^3 fields (k^-5/3 on 2 <= k <= 40): BiCGSTAB passes and time
+    from the ubar, zero and CNN starts."""
+    fields = synth.training_pairs_3d(16, n=n_train)
+    ut = torch.from_numpy(np.stack(fields)).to(dev)
+    ubt = gd.filter_apply(ut, ndim=3)
+    net = gd.WarmStart(synth.cnn_init_params(0, ndim=3), lr=1e-3, ndim=3)
+    steps = max(1, args.train_steps // 3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    first = None
+    for k in range(steps):
+        lo = (k * 4) % len(fields)
+        loss = net.train_step(ubt[lo:lo + 4], ut[lo:lo + 4])
+        if k == 0:
+            first = loss.item()
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    last = loss.item()
+    ev = np.stack([synth.scalar_3d(n_eval, synth.spectrum_kolmogorov, 2.0, 0.3125 * n_eval,
+                                   synth.rng_for(6, 60000 + i), np.float32) for i in range(count_eval)])
+    ubar = gd.filter_apply(torch.from_numpy(ev).to(dev), ndim=3)
+    d = gd.Deconvolver(ubar.shape, 3, ubar.dtype, "bicgstab")
+    out = torch.empty_like(ubar)
+    res = {}
+    for start in ("ubar", "zero"):
+        ms = timed(lambda: d.solve(ubar, 500, 1e-6, init=start, out=out), args.steps)
+        inf = d.solve(ubar, 500, 1e-6, init=start, out=out).info()
+        res[start] = dict(ms=ms, iters_mean=float(np.mean([i["iters"] for i in inf])),
+                          status=sorted({i["status_name"] for i in inf}))
+    u0 = torch.empty_like(ubar)
+
+    def cnn_solve():
+        net.forward(ubar, out=u0)
+        out.copy_(u0)
+        d.solve(ubar, 500, 1e-6, init="given", out=out)
+
+    ms_fwd = timed(lambda: net.forward(ubar, out=u0), args.steps)
+    ms_total = timed(cnn_solve, args.steps)
+    net.forward(ubar, out=out)
+    inf = d.solve(ubar, 500, 1e-6, init="given", out=out).info()
+    res["cnn"] = dict(ms=ms_total, ms_forward=ms_fwd, iters_mean=float(np.mean([i["iters"] for i in inf])),
+                      status=sorted({i["status_name"] for i in inf}),
+                      r0_over_ref_mean=float(np.mean([i["r0"] / i["r_ref"] for i in inf])))
+    return {"train_steps": steps, "train_seconds": train_s, "loss_first": first, "loss_last": last,
+            "eval": f"{count_eval} x {n_eval}^3", "starts": res}
 
 
 def time_solver(gd, torch, ubar, w, solver, steps, warmup, tol=1e-6, max_iter=500, tune=True):
