@@ -6,7 +6,7 @@ shares no code with it.
 
 ``gd_oracle.c`` holds the filter and the four solvers (Algorithms 1-4 of the
 paper) as plain scalar loops; this module loads it with ctypes and marshals
-numpy arrays.  ``cnn.py`` holds the FP64 reference for the warm-start network.
+numpy arrays, and writes the closure stress out from its definition.  ``cnn.py`` holds the FP64 reference for the warm-start network.
 """
 from __future__ import annotations
 
@@ -102,6 +102,32 @@ def filter(x: np.ndarray, ndim: int) -> np.ndarray:
         lib.or_filter(ndim, nx, ny, nz, _ptr(xb), _ptr(yb))
         out[b] = yb
     return out.reshape(x.shape)
+
+
+def stress_pairs(ndim: int):
+    """The independent pairs (i, j), i <= j, in output order."""
+    return [(i, j) for i in range(ndim) for j in range(i, ndim)]
+
+
+def closure_stress(ubar: np.ndarray, ustar: np.ndarray, ndim: int) -> np.ndarray:
+    """tau_ij = ubar_i ubar_j - G(u*_i u*_j) for i <= j.
+
+    The sub-filter stress of the filtered momentum equation (Sec. 2,
+    Eq. fge3) with the unfiltered velocity replaced by its deconvolved
+    approximation u* (Sec. 3: u* = ubar gives Eq. tau2, two van Cittert
+    steps give the second-order Eq. tau3).  ubar and ustar are
+    (..., ndim, [nz,] ny, nx); the result is (..., npairs, [nz,] ny, nx)
+    with the pairs of `stress_pairs`.
+    """
+    ubar = np.asarray(ubar, dtype=np.float64)
+    ustar = np.asarray(ustar, dtype=np.float64)
+    assert ubar.shape == ustar.shape and ubar.shape[-ndim - 1] == ndim
+    ax = -ndim - 1                       # the component axis
+    out = []
+    for i, j in stress_pairs(ndim):
+        resolved = np.take(ubar, i, axis=ax) * np.take(ubar, j, axis=ax)
+        out.append(resolved - filter(np.take(ustar, i, axis=ax) * np.take(ustar, j, axis=ax), ndim))
+    return np.stack(out, axis=-ndim - 1)
 
 
 def dot(a: np.ndarray, b: np.ndarray, hw: float, sum_mode: int = 0) -> float:
