@@ -65,6 +65,14 @@ WORKLOADS = {
     "c3": dict(desc="3D periodic 256^3 x 3 velocity components, E(k)~k^-5/3 on 2<=k<=80, divergence-free, "
                     "BiCGSTAB per component to rel. residual 1e-6 (FP32 storage, FP64 dots/scalars)",
                cfg=3, ndim=3, n=256, count=3, key="256cube_x3"),
+    "closure3d": dict(desc="approximate-deconvolution closure stress tau_ij = ubar_i ubar_j - G(u*_i u*_j), 6 pairs, "
+                           "from one 3D 256^3 divergence-free velocity (E(k)~k^-5/3 on 2<=k<=80), u* = BiCGSTAB "
+                           "deconvolution of ubar to rel. residual 1e-6 (FP32)",
+                      cfg=3, ndim=3, n=256, count=3, key="closure_256cube", closure=True),
+    "closure2d": dict(desc="approximate-deconvolution closure stress, 3 pairs, from eight 2D 2048^2 velocities "
+                           "(16 k^-3 fields on 4<=k<=512 as components), u* = BiCGSTAB deconvolution to rel. "
+                           "residual 1e-6 (FP32)",
+                      cfg=2, ndim=2, n=2048, count=16, key="closure_2048sq_x8", closure=True),
 }
 
 
@@ -208,6 +216,77 @@ def main_batch(args, w, torch, gd, dev):
         out["vs_vancittert"] = results["vc"]["ms"] / m["ms"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_batch(sizes, us)
+    print(json.dumps(out))
+
+
+def closure_accesses(ndim: int) -> int:
+    """Field accesses per point of the closure kernel: read ndim components of
+    ubar and of u*, write ndim (ndim + 1) / 2 stress components."""
+    return 2 * ndim + ndim * (ndim + 1) // 2
+
+
+def main_closure(args, w, torch, gd, dev):
+    """Deconvolve the filtered velocity, then time the closure stress kernel
+    (and the whole chain: solve of every component + closure)."""
+    nd = w["ndim"]
+    u32, ubar = make_inputs(w, torch, gd, dev)
+    vel = ubar.view(-1, nd, *ubar.shape[1:])                 # (fields, components, grid)
+    d = gd.Deconvolver(ubar.shape, nd, ubar.dtype, "bicgstab")
+    ustar = torch.empty_like(ubar)
+    if not args.no_tune:
+        gd.autotune("bicgstab", ubar, ndim=nd, out=ustar)
+    info = d.solve(ubar, 500, 1e-6, out=ustar).info()
+    us = ustar.view_as(vel)
+    tau = gd.closure_stress(vel, us, nd)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = [a.elapsed_time(b) for a, b in evs]
+        return float(np.mean(ms)), float(np.min(ms))
+
+    ms_cl, ms_cl_min = timed(lambda: gd.closure_stress(vel, us, nd, out=tau), args.steps)
+    ms_chain, _ = timed(lambda: (d.solve(ubar, 500, 1e-6, out=ustar), gd.closure_stress(vel, us, nd, out=tau)),
+                        max(3, args.steps // 4))
+    npts = int(np.prod(vel.shape[2:])) * vel.shape[0]             # grid points of the velocity batch
+    itemsize = ubar.element_size()
+    algo = npts * itemsize * closure_accesses(nd)
+    gbs = algo / (ms_cl * 1e-3) / 1e9
+    out = {
+        "metric": "closure-stress grid points/s (all tau_ij pairs); % HBM roofline", "value": npts / (ms_cl * 1e-3),
+        "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_cl,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w["desc"], "velocity_fields": vel.shape[0], "grid": [w["n"]] * nd, "points": npts,
+                   "pairs": nd * (nd + 1) // 2},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(w["key"]), "kernel": f"k_closure<float,{nd}>",
+                     "bytes_per_launch": algo},
+        "closure_ms_min": ms_cl_min,
+        "chain": {"ms": ms_chain, "points_per_s": npts / (ms_chain * 1e-3),
+                  "solve_iters": sorted({i["iters"] for i in info}),
+                  "status": sorted({i["status_name"] for i in info}),
+                  "closure_share": ms_cl / ms_chain},
+    }
+    if not args.no_cpu:
+        import oracle
+        ub64 = vel.double().cpu().numpy()
+        us64 = us.double().cpu().numpy()
+        k = 1 if nd == 3 else 2                                  # velocity fields in the sample
+        t0 = time.perf_counter()
+        oracle.closure_stress(ub64[:k], us64[:k], nd)
+        dt = time.perf_counter() - t0
+        pts = int(np.prod(vel.shape[2:])) * k
+        out["cpu_baseline"] = dict(value=pts / dt, unit="points/s", cores=1, kind="oracle",
+                                   sample=f"{k} of {vel.shape[0]} velocity fields, FP64 oracle closure stress "
+                                          f"(numpy products + C filter), single thread, {dt:.2f} s")
     print(json.dumps(out))
 
 
@@ -418,6 +497,8 @@ def main():
         return main_batch(args, w, torch, gd, dev)
     if w.get("warm"):
         return main_warm(args, w, torch, gd, dev)
+    if w.get("closure"):
+        return main_closure(args, w, torch, gd, dev)
     u32, ubar = make_inputs(w, torch, gd, dev)
     if args.tune_only:
         for s in args.solvers.split(","):

@@ -302,6 +302,24 @@ int warmstart_forward(const gd_cnn *net, const gd_grid *grid, const void *ubar, 
 int warmstart_train_step(const gd_cnn *net, const gd_grid *grid, const void *ubar, const void *u, void *work,
                          size_t work_bytes, double *loss, void *stream);
 
+/*
+ * ---- Closure stress ----------------------------------------------------------
+ *
+ * The sub-filter stress of the filtered equations, tau_ij = ubar_i ubar_j -
+ * G(u_i u_j) (Sec. 2, Eq. fge3), closed by approximate deconvolution with the
+ * deconvolved velocity u* in place of u (Sec. 3, Eq. tau3):
+ *     tau_ij = ubar_i ubar_j - G(u*_i u*_j),   i <= j.
+ * A velocity field has grid->ndim components; grid->batch is the number of
+ * velocity fields.
+ *   ubar, ustar  device, [batch][ndim][points] (component c of field b at
+ *                offset (b * ndim + c) * points)
+ *   tau          device, output, [batch][npairs][points], pairs in the order
+ *                11, 12, 22 (2D) or 11, 12, 13, 22, 23, 33 (3D)
+ * One fused pass; stream-ordered.  Errors: GD_EINVAL (bad grid, NULL, tau
+ * overlapping an input), GD_EHIP.
+ */
+int closure_stress(const gd_grid *grid, const void *ubar, const void *ustar, void *tau, void *stream);
+
 /* Human-readable name of a return code (< 0) or of a gd_info status (>= 0). */
 const char *gd_status_string(int32_t code);
 

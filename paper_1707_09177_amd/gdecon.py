@@ -80,7 +80,7 @@ EXPORTS = ["filter_apply", "deconvolve_workspace_bytes", "deconvolve_vancittert"
            "deconvolve_bicgstab", "deconvolve_steepest_descent", "gd_status_string", "gd_last_error",
            "gd_last_launch", "gd_set_trace", "deconvolve_batch_workspace_bytes", "deconvolve_batch",
            "deconvolve_autotune", "deconvolve_batch_autotune", "gd_tune_reset", "gd_tune_set", "gd_tune_set_batch", "warmstart_param_count",
-           "warmstart_workspace_bytes", "warmstart_forward", "warmstart_train_step"]
+           "warmstart_workspace_bytes", "warmstart_forward", "warmstart_train_step", "closure_stress"]
 
 _lib = None
 
@@ -126,6 +126,8 @@ def load(path: str = LIB_PATH):
     lib.gd_tune_set.restype = ctypes.c_int
     lib.gd_tune_set_batch.argtypes = [i32, i32, ip, i32, tp]
     lib.gd_tune_set_batch.restype = ctypes.c_int
+    lib.closure_stress.argtypes = [gp, vp, vp, vp, vp]
+    lib.closure_stress.restype = ctypes.c_int
     cp = ctypes.POINTER(Cnn)
     lib.warmstart_param_count.argtypes = [cp]
     lib.warmstart_param_count.restype = ctypes.c_int64
@@ -511,6 +513,26 @@ class WarmStart:
         _check(self.lib.warmstart_train_step(ctypes.byref(self.net), ctypes.byref(g), _dev_ptr(ubar), _dev_ptr(u),
                                              w.data_ptr(), w.numel(), self.loss.data_ptr(), _stream_handle(stream)))
         return self.loss
+
+
+def closure_stress(ubar: torch.Tensor, ustar: torch.Tensor, ndim: int, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """tau_ij = ubar_i ubar_j - G(u*_i u*_j) for i <= j (closure_stress).
+    ubar, ustar: (..., ndim, [nz,] ny, nx) velocity fields (components in the
+    dimension before the grid).  Returns (..., npairs, [nz,] ny, nx) with the
+    pairs 11, 12, 22 (2D) or 11, 12, 13, 22, 23, 33 (3D).  Launch only."""
+    if ubar.shape != ustar.shape or ubar.dtype != ustar.dtype:
+        raise ValueError("ubar and ustar must match")
+    if ubar.dim() < ndim + 1 or ubar.shape[-ndim - 1] != ndim:
+        raise ValueError(f"the component dimension (before the grid) must have size {ndim}")
+    lead = tuple(ubar.shape[:-ndim - 1])
+    g = make_grid(lead + (1,) + tuple(ubar.shape[-ndim:]), ndim, ubar.dtype)
+    np_ = ndim * (ndim + 1) // 2
+    tau = torch.empty(lead + (np_,) + tuple(ubar.shape[-ndim:]), dtype=ubar.dtype, device=ubar.device) \
+        if out is None else out
+    _check(load().closure_stress(ctypes.byref(g), _dev_ptr(ubar), _dev_ptr(ustar), _dev_ptr(tau),
+                                 _stream_handle(stream)))
+    return tau
 
 
 def deconvolve(solver: str, ubar: torch.Tensor, max_iter: int, tol: float = 0.0, ndim: int = 2, init: str = "ubar",

@@ -132,3 +132,27 @@ def test_tune_set_validates_choices():
     bad = gdecon._choice(wave_claims=2)
     assert lib.gd_tune_set(2, ctypes.byref(g), 256, 512, ctypes.byref(bad)) == -1
     assert lib.gd_tune_set(7, ctypes.byref(g), 256, 512, ctypes.byref(gdecon._choice())) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgdecon.so not built")
+def test_closure_stress_host_side_validation():
+    """closure_stress rejects bad grids, NULL pointers and an output that
+    overlaps an input before any launch."""
+    from paper_1707_09177_amd import gdecon
+    lib = gdecon.load()
+    g = gdecon.Grid()
+    g.ndim, g.dtype, g.batch = 4, 1, 1
+    g.n[0], g.n[1], g.n[2] = 8, 8, 8
+    assert lib.closure_stress(ctypes.byref(g), 4096, 8192, 1 << 20, None) == -1
+    assert "ndim" in lib.gd_last_error().decode()
+    g.ndim = 3
+    assert lib.closure_stress(ctypes.byref(g), None, 8192, 1 << 20, None) == -1
+    assert "NULL" in lib.gd_last_error().decode()
+    g.n[1] = 0
+    assert lib.closure_stress(ctypes.byref(g), 4096, 8192, 1 << 20, None) == -1
+    g.n[1] = 8
+    # 3 components of 512 FP32 points = 6 KiB per input; 6 pairs = 12 KiB out
+    ub, us = 1 << 20, 2 << 20
+    assert lib.closure_stress(ctypes.byref(g), ub, us, us + 4096, None) == -1
+    assert "overlaps" in lib.gd_last_error().decode()
+    assert lib.closure_stress(ctypes.byref(g), ub, us, us - 12288 + 4, None) == -1
