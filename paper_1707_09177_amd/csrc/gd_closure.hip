@@ -7,12 +7,15 @@
 //     tau_ij = ubar_i ubar_j - G(u*_i u*_j),   i <= j,
 // 3 pairs in 2D (11, 12, 22), 6 in 3D (11, 12, 13, 22, 23, 33).
 //
-// One fused pass: a workgroup owns a 32 x 8 column of the field and marches
-// along z.  For every plane it stages the products u*_i u*_j of the tile and
-// its one-point halo in LDS, filters them in x and y there, keeps three
-// filtered planes in registers for the z pass, and writes every tau_ij of the
-// plane behind.  HBM traffic: the u* components (with the halo of the tile),
-// the ubar components and the tau outputs, each once.
+// One fused pass that marches along the slowest axis (z in 3D, y in 2D).  A
+// workgroup owns an in-plane tile (3D: 64 x 8 points, each thread two
+// consecutive rows; 2D: a row segment of 256) and a run of planes.  For every
+// plane it stages the products u*_i u*_j of the tile and its one-point halo in
+// LDS, filters them in-plane there, keeps three filtered planes per pair in
+// registers for the march-axis pass, and writes every tau_ij of the plane
+// behind.  The next plane's u* loads are issued before the current plane is
+// filtered.  HBM traffic: u* (halo re-reads mostly hit L2), ubar and tau, each
+// once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,10 +31,6 @@ void set_error_text(const char *msg);
 
 namespace gdclosure {
 
-constexpr int TXC = 32, TYC = 8;                // tile of one workgroup (one thread per column)
-constexpr int HXC = TXC + 2, HYC = TYC + 2;     // tile with its halo
-constexpr int kZSeg = 32;                       // planes per workgroup along z
-
 // Periodic index for v in [-1, n].
 __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
@@ -40,95 +39,152 @@ __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >=
 // to stay in bounds.
 __device__ __forceinline__ int wrap_halo(int v, int n) { return v < 0 ? v + n : (v == n ? 0 : (v > n ? n - 1 : v)); }
 
+template <int NDIM>
+struct Shape;
+template <>
+struct Shape<3> {
+    static constexpr int TX = 64, RPT = 2;  // tile width; rows per thread
+    static constexpr bool XCD = true;       // x/y neighbour tiles on one XCD share halo lines in its L2
+};
+template <>
+struct Shape<2> {
+    static constexpr int TX = 256, RPT = 1;
+    static constexpr bool XCD = false;      // only two halo points per row: nothing to share
+};
+
 template <typename T, int NDIM>
 __global__ __launch_bounds__(256) void k_closure(const T *ubar, const T *ustar, T *tau, int nx, int ny, int nz,
-                                                 int tiles_x, int tiles_y, int zsegs) {
-    constexpr int NC = NDIM;                    // velocity components
-    constexpr int NP = NDIM * (NDIM + 1) / 2;   // stress components
-    __shared__ T prod[NP][HYC * HXC];
+                                                 int tiles_x, int tiles_y, int segs, int seg, int nblocks) {
+    using S = Shape<NDIM>;
+    constexpr int NC = NDIM, NP = NDIM * (NDIM + 1) / 2;  // velocity / stress components
+    constexpr int TX = S::TX, RPT = S::RPT;
+    constexpr int TYW = 256 / TX;                         // thread rows
+    constexpr int TY = TYW * RPT;                         // tile rows (3D)
+    constexpr int HX = TX + 2, HY = NDIM == 3 ? TY + 2 : 1;
+    constexpr int NS = HX * HY, SPT = (NS + 255) / 256;   // staged points per plane; per thread
+    static_assert(NDIM == 3 || (TYW == 1 && RPT == 1), "2D tiles are row segments");
+    __shared__ T prod[NP][NS];
     const int tid = threadIdx.x;
-    const int lx = tid % TXC, ly = tid / TXC;
-    int blk = blockIdx.x;
-    const int tx = blk % tiles_x;
-    blk /= tiles_x;
-    const int ty = blk % tiles_y;
-    blk /= tiles_y;
-    const int zs = blk % zsegs;
-    const int64_t f = blk / zsegs;              // field of the batch
-    const int x0 = tx * TXC, y0 = ty * TYC;
-    const int x = x0 + lx, y = y0 + ly;
-    const bool act = x < nx && y < ny;
-    const int64_t plane = (int64_t)nx * ny, npts = plane * nz;
+    int lin = blockIdx.x;
+    if (S::XCD) {  // workgroups are dealt round-robin over the 8 XCDs: give each a contiguous range
+        const int per = nblocks / 8, rem = nblocks % 8, xcd = lin % 8, k = lin / 8;
+        lin = xcd * per + min(xcd, rem) + k;
+    }
+    const int tx = lin % tiles_x;
+    lin /= tiles_x;
+    const int ty = lin % tiles_y;
+    lin /= tiles_y;
+    const int sg = lin % segs;
+    const int64_t f = lin / segs;                         // velocity field of the batch
+    const int lx = tid % TX, ly = tid / TX;
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int x = x0 + lx, yb = NDIM == 3 ? y0 + ly * RPT : 0;
+    const int nm = NDIM == 3 ? nz : ny;                   // march extent
+    const int64_t pstride = NDIM == 3 ? (int64_t)nx * ny : nx;
+    const int64_t npts = pstride * nm;
     const T *us = ustar + f * NC * npts;
     const T *ub = ubar + f * NC * npts;
     T *tf = tau + f * NP * npts;
-    const int z0 = NDIM == 3 ? zs * kZSeg : 0;
-    const int z1 = NDIM == 3 ? std::min(nz, z0 + kZSeg) : 1;
-    T h0[NP], h1[NP], h2[NP];
+    int64_t soff[SPT];                                    // in-plane offsets of this thread's staged points
 #pragma unroll
-    for (int k = 0; k < NP; ++k) h0[k] = h1[k] = h2[k] = T(0);
-    const int mlo = NDIM == 3 ? z0 - 1 : 0, mhi = NDIM == 3 ? z1 : 0;
-    for (int m = mlo; m <= mhi; ++m) {
-        const int mw = NDIM == 3 ? wrap(m, nz) : 0;
+    for (int k = 0; k < SPT; ++k) {
+        const int s = tid + 256 * k;
+        const int gx = wrap_halo(x0 + s % HX - 1, nx);
+        const int gy = NDIM == 3 ? wrap_halo(y0 + s / HX - 1, ny) : 0;
+        soff[k] = (int64_t)gy * nx + gx;
+    }
+    const int m0 = sg * seg, m1 = min(nm, m0 + seg);
+    T st[SPT][NC];
+    auto stage = [&](int m) {
+        const int64_t base = (int64_t)wrap(m, nm) * pstride;
+#pragma unroll
+        for (int k = 0; k < SPT; ++k)
+            if (k + 1 < SPT || tid + 256 * k < NS)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) st[k][c] = us[c * npts + base + soff[k]];
+    };
+    stage(m0 - 1);
+    T h0[RPT][NP], h1[RPT][NP], h2[RPT][NP];              // in-plane filtered products of planes m-2, m-1, m
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int k = 0; k < NP; ++k) h0[r][k] = h1[r][k] = h2[r][k] = T(0);
+    for (int m = m0 - 1; m <= m1; ++m) {
         __syncthreads();  // the previous plane's products have been read
-        for (int q = tid; q < HYC * HXC; q += 256) {
-            const int hy = q / HXC, hx = q % HXC;
-            const int gy = wrap_halo(y0 + hy - 1, ny), gx = wrap_halo(x0 + hx - 1, nx);
-            const int64_t i = (int64_t)mw * plane + (int64_t)gy * nx + gx;
-            T v[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) v[c] = us[c * npts + i];
-            int k = 0;
+        for (int k = 0; k < SPT; ++k)
+            if (k + 1 < SPT || tid + 256 * k < NS) {
+                int q = 0;
 #pragma unroll
-            for (int a = 0; a < NC; ++a)
+                for (int a = 0; a < NC; ++a)
 #pragma unroll
-                for (int b = a; b < NC; ++b) prod[k++][q] = v[a] * v[b];
-        }
+                    for (int b = a; b < NC; ++b) prod[q++][tid + 256 * k] = st[k][a] * st[k][b];
+            }
         __syncthreads();
-        // x and y passes of the filter at this thread's point
-        T hn[NP];
+        if (m < m1) stage(m + 1);
+        const bool outm = m > m0 && x < nx;               // plane m-1 has both march neighbours now
+        T v[RPT][NC];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            if (outm && (NDIM == 2 || yb + r < ny))
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    v[r][c] = ub[c * npts + (int64_t)(m - 1) * pstride + (int64_t)(yb + r) * nx + x];
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            auto row = [&](int r) {
-                const T *p = &prod[k][(ly + r) * HXC + lx];
-                return T(0.5) * p[1] + T(0.25) * (p[0] + p[2]);
-            };
-            hn[k] = T(0.5) * row(1) + T(0.25) * (row(0) + row(2));
-        }
-        if constexpr (NDIM == 2) {
-            if (act) {
-                const int64_t i = (int64_t)y * nx + x;
-                T v[NC];
+            T xr[RPT + 2];                                // x pass of rows yb-1 .. yb+RPT
 #pragma unroll
-                for (int c = 0; c < NC; ++c) v[c] = ub[c * npts + i];
+            for (int j = 0; j < (NDIM == 3 ? RPT + 2 : 1); ++j) {
+                const T *p = &prod[k][(ly * RPT + j) * HX + lx];
+                xr[j] = T(0.5) * p[1] + T(0.25) * (p[0] + p[2]);
+            }
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const T hn = NDIM == 3 ? T(0.5) * xr[r + 1] + T(0.25) * (xr[r] + xr[r + 2]) : xr[0];
+                h0[r][k] = h1[r][k];
+                h1[r][k] = h2[r][k];
+                h2[r][k] = hn;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            if (outm && (NDIM == 2 || yb + r < ny)) {
+                const int64_t i = (int64_t)(m - 1) * pstride + (int64_t)(yb + r) * nx + x;
                 int k = 0;
 #pragma unroll
                 for (int a = 0; a < NC; ++a)
 #pragma unroll
-                    for (int b = a; b < NC; ++b, ++k) tf[k * npts + i] = v[a] * v[b] - hn[k];
+                    for (int b = a; b < NC; ++b, ++k)  // tau is written once and not re-read here
+                        __builtin_nontemporal_store(
+                            v[r][a] * v[r][b] - (T(0.5) * h1[r][k] + T(0.25) * (h0[r][k] + h2[r][k])),
+                            &tf[k * npts + i]);
             }
-        } else {
-#pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                h0[k] = h1[k];
-                h1[k] = h2[k];
-                h2[k] = hn[k];
-            }
-            // z pass: plane m-1 has both of its neighbours now
-            if (m > z0 && act) {
-                const int64_t i = (int64_t)(m - 1) * plane + (int64_t)y * nx + x;
-                T v[NC];
-#pragma unroll
-                for (int c = 0; c < NC; ++c) v[c] = ub[c * npts + i];
-                int k = 0;
-#pragma unroll
-                for (int a = 0; a < NC; ++a)
-#pragma unroll
-                    for (int b = a; b < NC; ++b, ++k)
-                        tf[k * npts + i] = v[a] * v[b] - (T(0.5) * h1[k] + T(0.25) * (h0[k] + h2[k]));
-            }
-        }
     }
+}
+
+// Planes per workgroup: the longest run (64 in 2D, 32 in 3D, at least 4) that
+// still gives the launch enough workgroups (2048 in 2D; 512 in 3D, where the
+// tiles are larger and a long march amortises the halo planes).
+template <int NDIM>
+int choose_seg(int64_t tiles, int nm) {
+    int seg = NDIM == 3 ? 32 : 64;
+    const int64_t want = NDIM == 3 ? 512 : 2048;
+    while (seg > 4 && tiles * ((nm + seg - 1) / seg) < want) seg /= 2;
+    return seg;
+}
+
+template <typename T, int NDIM>
+int launch(const T *ub, const T *us, T *tau, int64_t nx, int64_t ny, int64_t nz, int64_t batch, hipStream_t st) {
+    constexpr int TX = Shape<NDIM>::TX, TY = 256 / TX * Shape<NDIM>::RPT;
+    const int64_t tiles_x = (nx + TX - 1) / TX, tiles_y = NDIM == 3 ? (ny + TY - 1) / TY : 1;
+    const int nm = (int)(NDIM == 3 ? nz : ny);
+    const int seg = choose_seg<NDIM>(tiles_x * tiles_y * batch, nm);
+    const int64_t segs = (nm + seg - 1) / seg;
+    const int64_t blocks = tiles_x * tiles_y * segs * batch;
+    if (blocks > 0x7fffffff) return -1;
+    hipLaunchKernelGGL((k_closure<T, NDIM>), dim3((unsigned)blocks), dim3(256), 0, st, ub, us, tau, (int)nx, (int)ny,
+                       (int)nz, (int)tiles_x, (int)tiles_y, (int)segs, seg, (int)blocks);
+    return 0;
 }
 
 int fail(int code, const char *fmt, ...) {
@@ -166,27 +222,16 @@ int closure_stress(const gd_grid *g, const void *ubar, const void *ustar, void *
     const size_t in_bytes = (size_t)g->batch * nc * nx * ny * nz * ts, out_bytes = (size_t)g->batch * np * nx * ny * nz * ts;
     if (overlap(tau, out_bytes, ubar, in_bytes) || overlap(tau, out_bytes, ustar, in_bytes))
         return fail(GD_EINVAL, "tau overlaps an input");
-    const int tiles_x = (int)((nx + TXC - 1) / TXC), tiles_y = (int)((ny + TYC - 1) / TYC);
-    const int zsegs = g->ndim == 3 ? (int)((nz + kZSeg - 1) / kZSeg) : 1;
-    const int64_t blocks = (int64_t)tiles_x * tiles_y * zsegs * g->batch;
-    if (blocks > 0x7fffffff) return fail(GD_EINVAL, "grid too large");
     hipStream_t st = (hipStream_t)stream;
-    const dim3 grid((unsigned)blocks), block(256);
-    if (g->dtype == GD_F32) {
-        if (g->ndim == 2)
-            hipLaunchKernelGGL((k_closure<float, 2>), grid, block, 0, st, (const float *)ubar, (const float *)ustar,
-                               (float *)tau, (int)nx, (int)ny, (int)nz, tiles_x, tiles_y, zsegs);
-        else
-            hipLaunchKernelGGL((k_closure<float, 3>), grid, block, 0, st, (const float *)ubar, (const float *)ustar,
-                               (float *)tau, (int)nx, (int)ny, (int)nz, tiles_x, tiles_y, zsegs);
-    } else {
-        if (g->ndim == 2)
-            hipLaunchKernelGGL((k_closure<double, 2>), grid, block, 0, st, (const double *)ubar,
-                               (const double *)ustar, (double *)tau, (int)nx, (int)ny, (int)nz, tiles_x, tiles_y, zsegs);
-        else
-            hipLaunchKernelGGL((k_closure<double, 3>), grid, block, 0, st, (const double *)ubar,
-                               (const double *)ustar, (double *)tau, (int)nx, (int)ny, (int)nz, tiles_x, tiles_y, zsegs);
-    }
+    int rc;
+    if (g->dtype == GD_F32)
+        rc = g->ndim == 2 ? launch<float, 2>((const float *)ubar, (const float *)ustar, (float *)tau, nx, ny, nz, g->batch, st)
+                          : launch<float, 3>((const float *)ubar, (const float *)ustar, (float *)tau, nx, ny, nz, g->batch, st);
+    else
+        rc = g->ndim == 2
+                 ? launch<double, 2>((const double *)ubar, (const double *)ustar, (double *)tau, nx, ny, nz, g->batch, st)
+                 : launch<double, 3>((const double *)ubar, (const double *)ustar, (double *)tau, nx, ny, nz, g->batch, st);
+    if (rc != 0) return fail(GD_EINVAL, "grid too large");
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(GD_EHIP, "closure launch: %s", hipGetErrorString(e));
     return GD_OK;
