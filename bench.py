@@ -77,6 +77,7 @@ WORKLOADS = {
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_solve_kernel_bicgstab.txt")
+CLOSURE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_closure_kernel.txt")
 
 
 def kernel_source_hash() -> str:
@@ -96,12 +97,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(key: str):
-    """HBM bytes per launch of the BiCGSTAB solve kernel from the committed
-    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources have
-    changed since those counters were taken (or no figure exists)."""
+def measured_traffic(key: str, path: str = TRAFFIC_FILE):
+    """HBM bytes per launch of a kernel (the BiCGSTAB solve kernel by default)
+    from a committed FETCH_SIZE / WRITE_SIZE summary, or None when the kernel
+    sources have changed since those counters were taken (or no figure exists)."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             kv = dict(line.split(" = ", 1) for line in fh.read().splitlines() if " = " in line)
     except OSError:
         return None
@@ -267,7 +268,7 @@ def main_closure(args, w, torch, gd, dev):
         "config": {"workload": w["desc"], "velocity_fields": vel.shape[0], "grid": [w["n"]] * nd, "points": npts,
                    "pairs": nd * (nd + 1) // 2},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(w["key"]), "kernel": f"k_closure<float,{nd}>",
+                     "traffic": measured_traffic(w["key"], CLOSURE_TRAFFIC_FILE), "kernel": f"k_closure<float,{nd}>",
                      "bytes_per_launch": algo},
         "closure_ms_min": ms_cl_min,
         "chain": {"ms": ms_chain, "points_per_s": npts / (ms_chain * 1e-3),

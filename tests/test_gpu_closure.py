@@ -113,3 +113,23 @@ def test_closure_rejects_mismatch():
         gdecon.closure_stress(x, x, 3)
     with pytest.raises(ValueError):
         gdecon.closure_stress(x, x.double(), 2)
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_bardina_and_layton_forms(nd):
+    """The scale-similarity models are closure_stress calls with particular
+    inputs: u* = ubar gives Eq. tau2; ubar := G ubar, u* = ubar gives the
+    Bardina model of Eq. tau1."""
+    shape = (40, 56) if nd == 2 else (12, 20, 24)
+    ub = oracle.filter(np.random.default_rng(50 + nd).standard_normal((1, nd) + shape), nd)
+    ubb = oracle.filter(ub, nd)
+    d_ub, d_ubb = to_dev(ub, torch.float64), to_dev(ubb, torch.float64)
+    lay = gdecon.closure_stress(d_ub, d_ub, nd)
+    bar = gdecon.closure_stress(d_ubb, d_ub, nd)
+    torch.cuda.synchronize()
+    for q, (i, j) in enumerate(oracle.stress_pairs(nd)):
+        prod = ub[0, i] * ub[0, j]
+        want_l = prod - oracle.filter(prod, nd)
+        want_b = ubb[0, i] * ubb[0, j] - oracle.filter(prod, nd)
+        np.testing.assert_allclose(lay[0, q].cpu().numpy(), want_l, rtol=0, atol=1e-14)
+        np.testing.assert_allclose(bar[0, q].cpu().numpy(), want_b, rtol=0, atol=1e-14)
