@@ -27,6 +27,9 @@ NORM_REFS = {"r0ubar": 0, "ubar": 1}
 STATUS = {0: "CONVERGED", 1: "MAXITER", 2: "BREAKDOWN_RHO", 3: "BREAKDOWN_OMEGA", 4: "NONFINITE", 5: "ZERO_REF"}
 
 
+_APPLY = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (-O2, no FP contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -58,6 +61,8 @@ def _load():
                                  ctypes.c_double, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, dp, ctypes.POINTER(_Info)]
         lib.or_solve.restype = ctypes.c_int
+        lib.or_solve_with.argtypes = lib.or_solve.argtypes + [_APPLY]
+        lib.or_solve_with.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -104,6 +109,28 @@ def filter(x: np.ndarray, ndim: int) -> np.ndarray:
     return out.reshape(x.shape)
 
 
+def germano_hat(shape, ndim: int, gamma: float) -> np.ndarray:
+    """Transfer function of the differential filter G = (I - delta^2 lap)^-1
+    on the half spectrum of numpy's rfftn over the last ndim axes (Sec. 4,
+    Eqs. df and df2): G_hat(k) = 1 / (1 + (|k| / k_c)^2), delta = 1 / k_c,
+    k_c = gamma k_m.  The domain is 2 pi periodic, so wavenumbers are
+    integers; k_m, the highest wavenumber the grid resolves, is min_d n_d / 2."""
+    shape = tuple(shape[-ndim:])
+    ks = [np.fft.fftfreq(n, 1.0 / n) for n in shape[:-1]] + [np.fft.rfftfreq(shape[-1], 1.0 / shape[-1])]
+    grids = np.meshgrid(*ks, indexing="ij")
+    k2 = sum(g * g for g in grids)
+    kc = gamma * min(shape) / 2.0
+    return 1.0 / (1.0 + k2 / (kc * kc))
+
+
+def germano_filter(x: np.ndarray, ndim: int, gamma: float) -> np.ndarray:
+    """y = G x with the differential filter, applied through the FFT (Sec. 4)."""
+    x = np.asarray(x, dtype=np.float64)
+    axes = tuple(range(x.ndim - ndim, x.ndim))
+    gh = germano_hat(x.shape, ndim, gamma)
+    return np.fft.irfftn(np.fft.rfftn(x, axes=axes) * gh, s=x.shape[-ndim:], axes=axes)
+
+
 def stress_pairs(ndim: int):
     """The independent pairs (i, j), i <= j, in output order."""
     return [(i, j) for i in range(ndim) for j in range(i, ndim)]
@@ -138,9 +165,11 @@ def dot(a: np.ndarray, b: np.ndarray, hw: float, sum_mode: int = 0) -> float:
 
 
 def solve(solver: str, ubar: np.ndarray, ndim: int, max_iter: int, tol: float = 0.0, init: str = "ubar",
-          u0: np.ndarray | None = None, norm_ref: str = "r0ubar", h=None, sum_mode: int = 0):
+          u0: np.ndarray | None = None, norm_ref: str = "r0ubar", h=None, sum_mode: int = 0, gamma=None):
     """Run one of Algorithms 1-4 on every field of ``ubar`` (leading dims = batch).
 
+    G is the trapezoidal stencil, or with ``gamma`` set the differential
+    filter of Sec. 4 (``germano_filter``).
     Returns (u, infos, hist): u like ubar; infos a list of dicts; hist an array
     (batch, max_iter+1) of ||r_k|| with NaN past the last pass.
     """
@@ -163,8 +192,19 @@ def solve(solver: str, ubar: np.ndarray, ndim: int, max_iter: int, tol: float = 
         uo = np.ascontiguousarray(u[b])
         hb = np.full(max_iter + 1, np.nan)
         info = _Info()
-        rc = lib.or_solve(SOLVERS[solver], ndim, nx, ny, nz, hw, _ptr(ub), _ptr(uo), int(max_iter), float(tol),
-                          INITS[init], NORM_REFS[norm_ref], int(sum_mode), _ptr(hb), ctypes.byref(info))
+        args = (SOLVERS[solver], ndim, nx, ny, nz, hw, _ptr(ub), _ptr(uo), int(max_iter), float(tol),
+                INITS[init], NORM_REFS[norm_ref], int(sum_mode), _ptr(hb), ctypes.byref(info))
+        if gamma is None:
+            rc = lib.or_solve(*args)
+        else:
+            fshape = ubar.shape[-ndim:]
+
+            def apply(xp, yp):
+                xv = np.ctypeslib.as_array(xp, shape=(npts,))
+                np.ctypeslib.as_array(yp, shape=(npts,))[:] = germano_filter(xv.reshape(fshape), ndim,
+                                                                              gamma).ravel()
+            cb = _APPLY(apply)
+            rc = lib.or_solve_with(*args, cb)
         if rc != 0:
             raise ValueError("oracle rejected the arguments")
         u[b] = uo

@@ -9,10 +9,12 @@
  * What it computes (San & Vedula, "Generalized deconvolution procedure for
  * structural modeling of turbulence"):
  *   - the approximate-deconvolution problem G u = ubar, Eq. (tau3) of Sec. 3;
- *   - G: the separable periodic 3-point trapezoidal filter, weights
- *     (1/4, 1/2, 1/4) per axis, written as the direct 9-point (2D) or 27-point
- *     (3D) sum.  The paper leaves G free (Sec. 4 opening) and uses a spectral
- *     differential filter; this build fixes the trapezoidal stencil instead.
+ *   - G: by default the separable periodic 3-point trapezoidal filter,
+ *     weights (1/4, 1/2, 1/4) per axis, written as the direct 9-point (2D) or
+ *     27-point (3D) sum.  The paper leaves G free (Sec. 4 opening) and uses a
+ *     spectral differential filter (Sec. 4, Eq. df); or_solve_with takes any
+ *     filter as a callback, and the Python side passes that one, applied
+ *     through the FFT as the paper does.
  *   - Van Cittert / Richardson iteration, Algorithm 1 (Eqs. adm2, res, ric);
  *   - steepest descent, Algorithm 2 (Eqs. sd, sd-a);
  *   - conjugate gradient, Algorithm 3 (Eqs. cg1 - cg-b);
@@ -133,14 +135,22 @@ double or_dot(const double *a, const double *b, int64_t n, double hw, int sum_mo
     return hw * s;
 }
 
+/* A filter given by the caller: y = G x over one field of n points. */
+typedef void (*or_apply_fn)(const double *x, double *y);
+
 typedef struct {
     int ndim;
     int64_t nx, ny, nz, n;
     double hw;
     int sum_mode;
+    or_apply_fn apply;  /* NULL: the trapezoidal stencil */
 } grid_t;
 
-static void G(const grid_t *g, const double *x, double *y) { or_filter(g->ndim, g->nx, g->ny, g->nz, x, y); }
+static void G(const grid_t *g, const double *x, double *y)
+{
+    if (g->apply) g->apply(x, y);
+    else or_filter(g->ndim, g->nx, g->ny, g->nz, x, y);
+}
 static double dot(const grid_t *g, const double *a, const double *b) { return or_dot(a, b, g->n, g->hw, g->sum_mode); }
 
 /* ||ubar - G x|| */
@@ -167,13 +177,13 @@ static int stop_check(double rn, double tol, double r_ref, int n, int max_iter, 
  *   hist: NULL or max_iter+1 doubles; hist[k] = ||r_k|| for k <= iters.
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
-int or_solve(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, double hw,
-             const double *ubar, double *u, int max_iter, double tol, int init,
-             int norm_ref, int sum_mode, double *hist, or_info *info)
+int or_solve_with(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, double hw,
+                  const double *ubar, double *u, int max_iter, double tol, int init,
+                  int norm_ref, int sum_mode, double *hist, or_info *info, or_apply_fn apply)
 {
     if ((ndim != 2 && ndim != 3) || nx < 1 || ny < 1 || (ndim == 3 && nz < 1) || max_iter < 0)
         return -1;
-    grid_t g = {ndim, nx, ny, ndim == 3 ? nz : 1, 0, hw, sum_mode};
+    grid_t g = {ndim, nx, ny, ndim == 3 ? nz : 1, 0, hw, sum_mode, apply};
     g.n = g.nx * g.ny * g.nz;
     const int64_t n = g.n;
     double *r = calloc(n, sizeof(double)), *d = calloc(n, sizeof(double));
@@ -302,4 +312,13 @@ int or_solve(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, double hw
     }
     free(r); free(d); free(p); free(q); free(f0); free(s); free(t);
     return 0;
+}
+
+/* Algorithms 1-4 with the trapezoidal stencil as G. */
+int or_solve(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, double hw,
+             const double *ubar, double *u, int max_iter, double tol, int init,
+             int norm_ref, int sum_mode, double *hist, or_info *info)
+{
+    return or_solve_with(solver, ndim, nx, ny, nz, hw, ubar, u, max_iter, tol, init, norm_ref, sum_mode, hist,
+                         info, NULL);
 }
