@@ -303,6 +303,40 @@ int warmstart_train_step(const gd_cnn *net, const gd_grid *grid, const void *uba
                          size_t work_bytes, double *loss, void *stream);
 
 /*
+ * ---- The paper's differential filter ----------------------------------------
+ *
+ * The results section filters with G = (I - delta^2 lap)^-1 (Sec. 4, Eq. df),
+ * applied through the FFT, with transfer function
+ *     G_hat(k) = 1 / (1 + (|k| / k_c)^2),  delta = 1 / k_c,  k_c = gamma k_m
+ * (Eq. df2); the domain is 2 pi periodic, so k is the integer wavenumber
+ * vector, and k_m = min_d n_d / 2.  Sizes must be powers of two in [2, 4096]
+ * (GD_F32) or [2, 2048] (GD_F64).  grid->h is used as in deconvolve_* (the
+ * weight of the inner products).
+ *
+ * germano_workspace_bytes(grid, solver): bytes for deconvolve_germano with
+ *   that solver, or with solver = -1 for germano_filter_apply; 0 if the grid
+ *   is not supported.
+ * germano_filter_apply(grid, gamma, x, y, work, work_bytes, stream):
+ *   y = G x for every field of the batch (x, y device, same layout as
+ *   filter_apply; they may be the same buffer).
+ * deconvolve_germano(solver, grid, gamma, ubar, u, opts, work, work_bytes,
+ *   info, stream): Algorithm 1, 2, 3 or 4 (solver = GD_VANCITTERT ...
+ *   GD_STEEPEST_DESCENT) with this G, same arguments, options, results and
+ *   info records as deconvolve_*.  The iteration runs on the Fourier
+ *   coefficients (G diagonal there; inner products by Parseval's identity),
+ *   between one forward FFT of ubar (and of u when opts->init is
+ *   GD_INIT_GIVEN) and one inverse FFT of the result; r_true is evaluated
+ *   there too.  Stream-ordered.
+ * Errors: GD_EINVAL (unsupported size, gamma <= 0, NULL, overlaps),
+ * GD_EWORKSPACE, GD_EALIGN (workspace not 256-byte aligned), GD_EHIP.
+ */
+size_t germano_workspace_bytes(const gd_grid *grid, int32_t solver);
+int germano_filter_apply(const gd_grid *grid, double gamma, const void *x, void *y, void *work, size_t work_bytes,
+                         void *stream);
+int deconvolve_germano(int32_t solver, const gd_grid *grid, double gamma, const void *ubar, void *u,
+                       const gd_opts *opts, void *work, size_t work_bytes, gd_info *info, void *stream);
+
+/*
  * ---- Closure stress ----------------------------------------------------------
  *
  * The sub-filter stress of the filtered equations, tau_ij = ubar_i ubar_j -

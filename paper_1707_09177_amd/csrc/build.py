@@ -22,6 +22,8 @@ FLAGS = [
     # no packed-FP32 instructions (v_pk_*_f32) anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", HERE,
+    # the FFT twiddle table is evaluated at compile time
+    "-fconstexpr-steps=50000000",
 ]
 
 

@@ -317,17 +317,6 @@ bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
 
 // ---- tuning choices ----------------------------------------------------------
 
-// Launch configuration the autotuner chooses between: target tiles per
-// resident wave (tile granularity) and, for 3D fields in the uniform kernels,
-// rows per tile (0 = the default rule).
-struct TuneCfg {
-    int tpw = kTilesPerWave;
-    int rows = 0;
-    int tail = kTailPct;
-    int ilv = 0;  // interleaved tile pools
-    int wc = 0;   // per-wave tile claims
-};
-
 std::mutex g_tune_mu;
 std::map<std::string, TuneCfg> g_tune;
 bool g_tune_loaded = false;
@@ -403,7 +392,7 @@ std::string key_uniform(int solver, const gd_grid *g, bool aligned) {
 // ---- uniform batches -----------------------------------------------------------
 
 int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work,
-                  size_t work_bytes, gd_info *info, void *stream, const TuneCfg *force) {
+                  size_t work_bytes, gd_info *info, void *stream, const TuneCfg *force, const SpecParams *spec) {
     int rc = validate_grid(g);
     if (rc) return rc;
     rc = validate_opts(o);
@@ -429,7 +418,11 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
     TileShape ts = choose_tiles(g->ndim, nx, ny, nz, g->batch, (int)tsize, aligned, solver, false);
     if (g->ndim == 3 && cfg.rows > 0 && variant_ok((int)tsize, 3, ts.vw, cfg.rows) && (cfg.rows == 1 || ny >= cfg.rows))
         ts.R = cfg.rows;
-    const int variant = var_code(g->ndim, ts.vw, ts.R);
+    if (spec) {  // pointwise sweeps over a spectrum: whole 16-byte lanes, one row per tile
+        ts.vw = 16 / (int)tsize;
+        ts.R = 1;
+    }
+    const int variant = (spec ? kSpecBit : 0) + var_code(g->ndim, ts.vw, ts.R);
     const void *kern = nullptr;
     int64_t blocks_cap = 0;
     rc = solve_grid(g->dtype, solver, variant, ts.blocks_per_cu, &kern, &blocks_cap);
@@ -458,6 +451,10 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
     I.ndim = g->ndim;
     I.vw = ts.vw;
     I.R = ts.R;
+    if (spec) {
+        I.inv_kc2 = spec->inv_kc2;
+        I.nxc = spec->nxc;
+    }
     P.table = nullptr;
     P.st = (State *)(w + off_st);
     P.sync = (Sync *)w;
@@ -847,22 +844,22 @@ size_t deconvolve_workspace_bytes(const gd_grid *g, int32_t solver) {
 
 int deconvolve_vancittert(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work, size_t wb,
                           gd_info *info, void *stream) {
-    return solve_uniform(GD_VANCITTERT, g, ubar, u, o, work, wb, info, stream, nullptr);
+    return solve_uniform(GD_VANCITTERT, g, ubar, u, o, work, wb, info, stream, nullptr, nullptr);
 }
 
 int deconvolve_cg(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work, size_t wb,
                   gd_info *info, void *stream) {
-    return solve_uniform(GD_CG, g, ubar, u, o, work, wb, info, stream, nullptr);
+    return solve_uniform(GD_CG, g, ubar, u, o, work, wb, info, stream, nullptr, nullptr);
 }
 
 int deconvolve_bicgstab(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work, size_t wb,
                         gd_info *info, void *stream) {
-    return solve_uniform(GD_BICGSTAB, g, ubar, u, o, work, wb, info, stream, nullptr);
+    return solve_uniform(GD_BICGSTAB, g, ubar, u, o, work, wb, info, stream, nullptr, nullptr);
 }
 
 int deconvolve_steepest_descent(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work, size_t wb,
                                 gd_info *info, void *stream) {
-    return solve_uniform(GD_STEEPEST_DESCENT, g, ubar, u, o, work, wb, info, stream, nullptr);
+    return solve_uniform(GD_STEEPEST_DESCENT, g, ubar, u, o, work, wb, info, stream, nullptr, nullptr);
 }
 
 size_t deconvolve_batch_workspace_bytes(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count) {
@@ -902,7 +899,7 @@ int deconvolve_autotune(int32_t solver, const gd_grid *g, const void *ubar, void
                     }
     // every candidate must launch; a shape the field cannot use falls back to
     // the default rule inside solve_uniform, so duplicates are harmless
-    auto launch = [&](const TuneCfg &c) { return solve_uniform(solver, g, ubar, u, &o, work, wb, info, stream, &c); };
+    auto launch = [&](const TuneCfg &c) { return solve_uniform(solver, g, ubar, u, &o, work, wb, info, stream, &c, nullptr); };
     const int best = time_candidates(cands, launch, (hipStream_t)stream, out);
     if (best < 0) return best;
     const bool aligned = ((uintptr_t)ubar % 16 == 0) && ((uintptr_t)u % 16 == 0);

@@ -291,4 +291,56 @@ __device__ __forceinline__ void point_tile(const Geo &g, int64_t lt, const Op &o
             }
 }
 
+// Pointwise pass over a tile of a stored half spectrum (the differential
+// filter): G S = G_hat(k) S at every point, G_hat = 1 / (1 + |k|^2 / k_c^2).
+// A row holds complex values as (re, im) pairs, so element x has k_x = x / 2;
+// k_x >= nxc marks the zero padding of a row, where G_hat is taken as 0.
+// Rows are k_y (3D) and planes k_z (3D) or k_y (2D), in FFT order.
+template <int NDIM, int VW, int R, typename T, typename C, class Op>
+__device__ __forceinline__ void spectral_tile(const Geo &g, double inv_kc2, int64_t nxc, int64_t lt, const Op &op,
+                                              double (&acc)[NACC], int lane) {
+    constexpr int NI = Arr<Op::NI>::n;
+    constexpr int NO = Arr<Op::NO>::n;
+    const TilePos p = tile_pos<VW, R>(g, lt, lane);
+    if (!p.act) return;
+    C kx2[VW];
+    bool pad[VW];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+        const int64_t kx = (p.x0 + k) >> 1;
+        kx2[k] = C(kx * kx);
+        pad[k] = kx >= nxc;
+    }
+    const C ikc2 = C(inv_kc2);
+    auto sk = [](int64_t k, int64_t n) -> int64_t { return 2 * k <= n ? k : k - n; };
+#pragma unroll 2
+    for (int64_t m = p.m0; m < p.m1; ++m) {
+        const int64_t km = sk(m, g.nmarch);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t row = p.row0 + r;
+            if (NDIM == 3 && row >= g.nrows) continue;
+            const int64_t kr = NDIM == 3 ? sk(row, g.nrows) : 0;
+            const C kyz2 = C(km * km + kr * kr);
+            const int64_t i = m * g.plane + row * g.nx + p.x0;
+            T v[NI][VW], o[NO][VW];
+#pragma unroll
+            for (int f = 0; f < Op::NI; ++f) vld<T, VW>(op.in[f] + i, v[f]);
+#pragma unroll
+            for (int f = 0; f < Op::NO; ++f) vld<T, VW>(op.oin[f] + i, o[f]);
+            C s[VW], gv[VW];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) {
+                T a[NI];
+#pragma unroll
+                for (int f = 0; f < NI; ++f) a[f] = v[f][k];
+                s[k] = op.mix(a);
+                const C gh = pad[k] ? C(0) : C(1) / (C(1) + (kx2[k] + kyz2) * ikc2);
+                gv[k] = gh * s[k];
+            }
+            op.out(i, s, gv, o, acc);
+        }
+    }
+}
+
 }  // namespace gd

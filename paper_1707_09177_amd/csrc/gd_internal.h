@@ -16,10 +16,14 @@ namespace gd {
 // batch finds instance i by offsetting instance 0; kTableBit + shape is the
 // same shape reading per-instance descriptors from a table (uneven batches
 // whose instances share one shape); VAR_ALL always reads the table.
+// kSpecBit + shape is the same shape run on a stored Fourier spectrum, with G
+// the pointwise transfer function of the differential filter.
 constexpr int VAR_ALL = 0;
 constexpr int kTableBit = 1000;
+constexpr int kSpecBit = 5000;
 __host__ __device__ constexpr int var_code(int ndim, int vw, int R) { return ndim * 100 + vw * 10 + R; }
-__host__ __device__ constexpr bool var_table(int c) { return c == VAR_ALL || c >= kTableBit; }
+__host__ __device__ constexpr bool var_table(int c) { return c == VAR_ALL || (c % kSpecBit) >= kTableBit; }
+__host__ __device__ constexpr bool var_spec(int c) { return c >= kSpecBit; }
 __host__ __device__ constexpr int var_ndim(int c) { return (c % kTableBit) / 100; }
 __host__ __device__ constexpr int var_vw(int c) { return (c / 10) % 10; }
 __host__ __device__ constexpr int var_r(int c) { return c % 10; }
@@ -57,6 +61,10 @@ struct Inst {
     int64_t b0, s0;         // first long / short tile in the claim order (table mode)
     double hw;              // h^d of the inner product
     int32_t ndim, vw, R, pad;
+    // spectral solves: 1 / k_c^2 of the differential filter and the number of
+    // complex columns (n_x / 2 + 1) of the stored half spectrum
+    double inv_kc2;
+    int64_t nxc;
 };
 
 // FP64 scalars of one instance; written only by the barrier's last arriver.
@@ -134,6 +142,23 @@ struct Params {
     int32_t wave_claims; // 1: every wave claims its own tiles; 0: a workgroup claims for its waves
 };
 
+// Launch configuration the autotuner chooses between: target tiles per
+// resident wave (tile granularity) and, for 3D fields in the uniform kernels,
+// rows per tile (0 = the default rule).
+struct TuneCfg {
+    int tpw = kTilesPerWave;
+    int rows = 0;
+    int tail = kTailPct;
+    int ilv = 0;  // interleaved tile pools
+    int wc = 0;   // per-wave tile claims
+};
+
+// A solve on a stored Fourier spectrum (the differential filter).
+struct SpecParams {
+    double inv_kc2;
+    int64_t nxc;
+};
+
 // Tile shape of a field: lanes hold vw consecutive x values, a 3D tile spans
 // R rows, and a tile marches L planes.
 struct TileShape {
@@ -171,6 +196,11 @@ __host__ __device__ constexpr bool mixed_variant_ok(int tsize, int ndim, int vw,
 const void *solve_kernel_ptr(int dtype, int solver, int variant);
 const void *filter_kernel_ptr(int dtype, int variant);
 Geo make_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int vw, int R, int64_t L, int tail_pct);
+int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work,
+                  size_t work_bytes, gd_info *info, void *stream, const TuneCfg *force, const SpecParams *spec);
+int validate_grid(const gd_grid *g);
+int validate_opts(const gd_opts *o);
+void set_error_text(const char *msg);
 int64_t geo_tiles(const Geo &g);
 
 }  // namespace gd

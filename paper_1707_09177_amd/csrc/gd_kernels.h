@@ -107,6 +107,14 @@ template <> struct PhaseNacc<PH_BIC> { static constexpr int v = 2; };
 
 __host__ __device__ constexpr inline int phase_nacc(int ph) { return ph == PH_BIB ? 3 : (ph == PH_BIC ? 2 : 1); }
 
+// One tile of a sweep that applies G: the stencil march, or on a stored
+// spectrum the pointwise transfer function.
+template <int VS, int NDIM, int VW, int R, typename T, typename C, class Op>
+__device__ __forceinline__ void g_tile(const Inst &I, int64_t lt, const Op &op, double (&acc)[NACC], int lane) {
+    if constexpr (var_spec(VS)) spectral_tile<NDIM, VW, R, T, C>(I.geo, I.inv_kc2, I.nxc, lt, op, acc, lane);
+    else march_tile<NDIM, VW, R, T, C>(I.geo, lt, op, acc, lane);
+}
+
 // One tile of one sweep.
 template <typename T, int VS, int PH>
 __device__ __forceinline__ void tile_body(const Inst &I, const State *S, int it, int64_t lt, double (&acc)[NACC],
@@ -135,53 +143,53 @@ __device__ __forceinline__ void tile_body(const Inst &I, const State *S, int it,
             point_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_RREF_RES) {
             OpResNorm<T, T, VW> op{{ub}, {ub}};
-            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
         } else if constexpr (PH == PH_TRUE) {
             OpResNorm<T, double, VW> op{{u}, {ub}};
-            march_tile<NDIM, VW, R, T, double>(g, lt, op, acc, lane);
+            g_tile<VS, NDIM, VW, R, T, double>(I, lt, op, acc, lane);
         } else if constexpr (PH == PH_INIT_UBAR) {
             OpInitUbar<T, T, VW> op{{ub}, {nullptr}, u, V[V_R0], V[V_F0]};
-            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
         } else if constexpr (PH == PH_INIT_ZERO) {
             OpInitZero<T, T, VW> op{{nullptr}, {ub}, u, V[V_R0], V[V_F0]};
             point_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
         } else if constexpr (PH == PH_INIT_GIVEN) {
             OpInitGiven<T, T, VW> op{{u}, {ub}, V[V_R0], V[V_F0]};
-            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
         } else if constexpr (PH == PH_VC) {
             OpVC<T, T, VW> op{{X(V_R0)}, {u}, Y(V_R0), u};
-            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
         } else if constexpr (PH == PH_CG1) {
             if (it == 0) {
                 OpCG1First<T, T, VW> op{{V[V_R0]}, {nullptr}, Y(V_P0)};
-                march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+                g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
             } else {
                 OpCG1<T, T, VW> op{{V[V_R0], X(V_P0)}, {nullptr}, Y(V_P0), beta};
-                march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+                g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
             }
         } else if constexpr (PH == PH_CG2) {
             OpCG2<T, T, VW> op{{Y(V_P0)}, {u, V[V_R0]}, u, V[V_R0], alpha};
-            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
         } else if constexpr (PH == PH_BIA) {
             if (it == 0) {
                 OpBiAFirst<T, T, VW> op{{X(V_R0)}, {V[V_F0]}, Y(V_P0), Y(V_Q0)};
-                march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+                g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
             } else {
                 OpBiA<T, T, VW> op{{X(V_R0), X(V_P0), X(V_Q0)}, {V[V_F0]}, Y(V_P0), Y(V_Q0), beta, omega};
-                march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+                g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
             }
         } else if constexpr (PH == PH_BIB) {
             OpBiB<T, T, VW> op{{X(V_R0), Y(V_Q0)}, {nullptr}, alpha};
-            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
         } else if constexpr (PH == PH_BIC) {
             OpBiC<T, T, VW> op{{X(V_R0), Y(V_Q0)}, {u, Y(V_P0), V[V_F0]}, u, Y(V_R0), alpha, omega};
-            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
         } else if constexpr (PH == PH_SD1) {
             OpSD1<T, T, VW> op{{X(V_R0)}, {nullptr}};
-            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
         } else if constexpr (PH == PH_SD2) {
             OpSD2<T, T, VW> op{{X(V_R0)}, {u}, Y(V_R0), u, alpha};
-            march_tile<NDIM, VW, R, T, T>(g, lt, op, acc, lane);
+            g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
         }
     });
 }

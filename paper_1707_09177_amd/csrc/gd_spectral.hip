@@ -1,0 +1,480 @@
+// gd_spectral.hip -- the paper's differential filter and the solve with it.
+//
+// The results section filters with G = (I - delta^2 lap)^-1, applied through
+// the FFT, whose transfer function is G_hat(k) = 1 / (1 + (|k| / k_c)^2),
+// delta = 1 / k_c, k_c = gamma k_m (Sec. 4, Eqs. df and df2; k_m, the highest
+// wavenumber the grid resolves, is taken as min_d n_d / 2, the domain is
+// 2 pi periodic so wavenumbers are integers).
+//
+// G is diagonal in Fourier space, and Algorithms 1-4 use G only through
+// products G x, linear combinations and inner products.  So the solve runs on
+// Fourier coefficients: one forward FFT of ubar (and of a given u0), every
+// pass of the persistent solve kernel with G x = G_hat(k) x(k) evaluated
+// pointwise, and one inverse FFT of u.  Inner products carry over through
+// Parseval's identity: the half spectrum of a real field is stored scaled by
+// c(k) = sqrt(w(k_x) / N) (w = 1 on the k_x = 0 and k_x = n_x / 2 columns,
+// 2 elsewhere, N the point count), so the plain dot product of two stored
+// spectra, real and imaginary parts taken as separate reals, equals
+// sum_x a(x) b(x).  The persistent solve kernel therefore runs unchanged, on
+// a real array of 2 (n_x / 2 + 1) columns per row (padded to a whole number
+// of 16-byte lanes; the padding stays zero).
+//
+// FFTs: power-of-two lengths.  Rows (x) use the half-length complex
+// transform of the even/odd-packed real row plus the standard split; y and z
+// transform strided columns, a workgroup taking a few adjacent columns so
+// that its loads are contiguous runs of them.  Each transform is radix-2,
+// decimation in time, in LDS after a bit-reversed load.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "gd_internal.h"
+#include "gd_twiddle.h"
+
+namespace gdspec {
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    gd::set_error_text(buf);
+    return code;
+}
+
+__constant__ gdtw::Table c_tw = gdtw::make_table();
+
+template <typename T> struct V2;
+template <> struct V2<float> { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+
+template <typename T>
+__device__ __forceinline__ typename V2<T>::t cmul(typename V2<T>::t a, typename V2<T>::t b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// exp(-+2 pi i k / n), k < n / 2 (n a power of two <= kTwN), from the table
+template <typename T, bool INV>
+__device__ __forceinline__ typename V2<T>::t tw(int k, int tstride) {
+    const gdtw::Cd c = c_tw.v[k * tstride];
+    return {T(c.re), INV ? T(-c.im) : T(c.im)};
+}
+
+// exp(-+2 pi i k / n) for 0 <= k <= n (used by the real-row split)
+template <typename T, bool INV>
+__device__ __forceinline__ typename V2<T>::t tw_full(int k, int n) {
+    const int half = n / 2;
+    if (k == half) return {T(-1), T(0)};
+    if (k == n) return {T(1), T(0)};
+    if (k < half) return tw<T, INV>(k, gdtw::kTwN / n);
+    typename V2<T>::t w = tw<T, INV>(k - half, gdtw::kTwN / n);
+    return {-w.x, -w.y};
+}
+
+__device__ __forceinline__ int bitrev(int j, int logn) { return logn == 0 ? 0 : (int)(__brev((unsigned)j) >> (32 - logn)); }
+
+// In-place radix-2 DIT transforms of ncols columns of length n, stored
+// buf[j * cw + c], already in bit-reversed order.
+template <typename T, bool INV>
+__device__ __forceinline__ void lds_fft(typename V2<T>::t *buf, int n, int logn, int cw, int ncols) {
+    using V = typename V2<T>::t;
+    const int nb = (n / 2) * ncols;
+    for (int s = 1; s <= logn; ++s) {
+        const int half = 1 << (s - 1);
+        const int tstride = gdtw::kTwN >> s;  // twiddle of pos: exp(-2 pi i pos / 2^s)
+        for (int b = threadIdx.x; b < nb; b += 256) {
+            const int c = b % ncols, bb = b / ncols;
+            const int pos = bb & (half - 1);
+            const int i0 = ((bb >> (s - 1)) << s) + pos;
+            const V w = tw<T, INV>(pos, tstride);
+            const V a = buf[i0 * cw + c];
+            const V x = cmul<T>(buf[(i0 + half) * cw + c], w);
+            buf[i0 * cw + c] = {a.x + x.x, a.y + x.y};
+            buf[(i0 + half) * cw + c] = {a.x - x.x, a.y - x.y};
+        }
+        __syncthreads();
+    }
+}
+
+// Multipliers applied to the spectrum (see the file comment).
+enum Mul : int { MUL_NONE = 0, MUL_C = 1, MUL_INV_CN = 2, MUL_GHAT_N = 3 };
+
+struct SpecMap {
+    int64_t nx, ny, nz;  // logical grid
+    int64_t nxh;         // complex columns per stored row (padded)
+    int64_t nxc;         // nx / 2 + 1
+    double inv_kc2, npts;
+    int ndim, axis;      // axis of this column pass: 1 (y) or 2 (z)
+    int mul;
+};
+
+__device__ __forceinline__ int64_t signed_k(int64_t k, int64_t n) { return k <= n / 2 ? k : k - n; }
+
+// multiplier at spectral index (kx, ky, kz)
+__device__ __forceinline__ double mul_at(const SpecMap &m, int64_t kx, int64_t ky, int64_t kz) {
+    if (kx >= m.nxc) return 0.0;  // padding columns
+    const double w = (kx == 0 || 2 * kx == m.nx) ? 1.0 : 2.0;
+    switch (m.mul) {
+    case MUL_C: return sqrt(w / m.npts);
+    case MUL_INV_CN: return 1.0 / sqrt(w * m.npts);
+    case MUL_GHAT_N: {
+        const double a = (double)signed_k(ky, m.ny), b = (double)signed_k(kz, m.nz);
+        const double k2 = (double)(kx * kx) + a * a + b * b;
+        return 1.0 / ((1.0 + k2 * m.inv_kc2) * m.npts);
+    }
+    default: return 1.0;
+    }
+}
+
+// Complex transforms of length n along the middle axis of a [outer][n][inner]
+// array of complex values, cw adjacent inner columns per workgroup (in place).
+// The multiplier (if any) is applied after a forward / before an inverse
+// transform.
+template <typename T, bool INV>
+__global__ __launch_bounds__(256) void k_fft_cols(T *data, int64_t inner, int n, int logn, int cw, int64_t nchunks,
+                                                  SpecMap m) {
+    using V = typename V2<T>::t;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    V *buf = reinterpret_cast<V *>(lds_raw);
+    const int64_t chunk = blockIdx.x % nchunks, o = blockIdx.x / nchunks;
+    const int64_t i0 = chunk * cw;
+    const int ncols = (int)std::min<int64_t>(cw, inner - i0);
+    V *base = reinterpret_cast<V *>(data) + (o * n) * inner + i0;
+    auto mult = [&](int j, int c) -> double {
+        const int64_t ii = i0 + c;
+        if (m.axis == 1) return mul_at(m, ii, j, m.ndim == 3 ? o % m.nz : 0);
+        return mul_at(m, ii % m.nxh, ii / m.nxh, j);
+    };
+    for (int idx = threadIdx.x; idx < n * ncols; idx += 256) {
+        const int c = idx % ncols, j = idx / ncols;
+        V v = base[(int64_t)j * inner + c];
+        if (INV && m.mul != MUL_NONE) {
+            const T s = T(mult(j, c));
+            v = {v.x * s, v.y * s};
+        }
+        buf[bitrev(j, logn) * cw + c] = v;
+    }
+    __syncthreads();
+    lds_fft<T, INV>(buf, n, logn, cw, ncols);
+    for (int idx = threadIdx.x; idx < n * ncols; idx += 256) {
+        const int c = idx % ncols, j = idx / ncols;
+        V v = buf[j * cw + c];
+        if (!INV && m.mul != MUL_NONE) {
+            const T s = T(mult(j, c));
+            v = {v.x * s, v.y * s};
+        }
+        base[(int64_t)j * inner + c] = v;
+    }
+}
+
+// Forward real rows: x (rows of nx reals) -> X (rows of nxh complex values:
+// k = 0 .. nx/2, then zero padding).  rpw rows per workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rfft_rows(const T *x, T *X, int64_t nrows, int nx, int logn2, int64_t nxh,
+                                                   int rpw) {
+    using V = typename V2<T>::t;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    V *buf = reinterpret_cast<V *>(lds_raw);
+    const int n2 = nx / 2;
+    const int64_t r0 = (int64_t)blockIdx.x * rpw;
+    const int nr = (int)std::min<int64_t>(rpw, nrows - r0);
+    const V *src = reinterpret_cast<const V *>(x + r0 * nx);  // z[j] = x[2j] + i x[2j+1]
+    for (int idx = threadIdx.x; idx < n2 * nr; idx += 256) {
+        const int r = idx / n2, j = idx % n2;
+        buf[bitrev(j, logn2) * rpw + r] = src[(int64_t)r * n2 + j];
+    }
+    __syncthreads();
+    lds_fft<T, false>(buf, n2, logn2, rpw, nr);
+    V *dst = reinterpret_cast<V *>(X) + r0 * nxh;
+    for (int idx = threadIdx.x; idx < (int)nxh * nr; idx += 256) {
+        const int r = idx / (int)nxh, k = idx % (int)nxh;
+        V out = {T(0), T(0)};
+        if (k <= n2) {
+            // X[k] = (Z[k] + conj Z[n2-k]) / 2 - i/2 exp(-2 pi i k / nx) (Z[k] - conj Z[n2-k])
+            const V zk = buf[(k % n2) * rpw + r];
+            const V zm0 = buf[((n2 - k) % n2) * rpw + r];
+            const V zm = {zm0.x, -zm0.y};
+            const V e = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y + zm.y)};
+            const V d = {T(0.5) * (zk.x - zm.x), T(0.5) * (zk.y - zm.y)};
+            const V w = tw_full<T, false>(k, nx);
+            const V wd = cmul<T>(w, d);  // times -i: (a + ib)(-i) = b - ia
+            out = {e.x + wd.y, e.y - wd.x};
+        }
+        dst[(int64_t)r * nxh + k] = out;
+    }
+}
+
+// Inverse real rows: X (rows of nxh complex, k = 0 .. nx/2 used) -> x, the
+// unnormalised inverse (nx times the inverse DFT along x).
+template <typename T>
+__global__ __launch_bounds__(256) void k_irfft_rows(const T *X, T *x, int64_t nrows, int nx, int logn2, int64_t nxh,
+                                                    int rpw) {
+    using V = typename V2<T>::t;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    V *buf = reinterpret_cast<V *>(lds_raw);
+    const int n2 = nx / 2;
+    const int64_t r0 = (int64_t)blockIdx.x * rpw;
+    const int nr = (int)std::min<int64_t>(rpw, nrows - r0);
+    const V *src = reinterpret_cast<const V *>(X) + r0 * nxh;
+    const int np = n2 / 2 + 1;  // pairs (k, n2 - k), k = 0 .. n2/2
+    for (int idx = threadIdx.x; idx < np * nr; idx += 256) {
+        const int r = idx / np, k = idx % np;
+        const V a = src[(int64_t)r * nxh + k], b = src[(int64_t)r * nxh + (n2 - k)];
+        // Z[k] = (X[k] + conj X[n2-k]) + i exp(2 pi i k / nx) (X[k] - conj X[n2-k])
+        auto z_of = [&](V xk, V xm, int kk) -> V {
+            const V s = {xk.x + xm.x, xk.y - xm.y};
+            const V d = {xk.x - xm.x, xk.y + xm.y};
+            const V wd = cmul<T>(tw_full<T, true>(kk, nx), d);
+            return {s.x - wd.y, s.y + wd.x};  // s + i wd
+        };
+        if (k < n2) buf[bitrev(k, logn2) * rpw + r] = z_of(a, b, k);
+        if (k != 0 && n2 - k != k) buf[bitrev(n2 - k, logn2) * rpw + r] = z_of(b, a, n2 - k);
+    }
+    __syncthreads();
+    lds_fft<T, true>(buf, n2, logn2, rpw, nr);
+    V *dst = reinterpret_cast<V *>(x + r0 * nx);
+    for (int idx = threadIdx.x; idx < n2 * nr; idx += 256) {
+        const int r = idx / n2, j = idx % n2;
+        dst[(int64_t)r * n2 + j] = buf[j * rpw + r];
+    }
+}
+
+constexpr size_t kLdsBudget = 64 * 1024;
+
+int ilog2(int64_t n) {
+    int l = 0;
+    while ((int64_t(1) << l) < n) ++l;
+    return l;
+}
+
+bool pow2(int64_t n) { return n >= 2 && (n & (n - 1)) == 0; }
+
+// Geometry of the stored half spectrum of a grid.
+struct Spec {
+    int ndim;
+    int64_t nx, ny, nz, batch;
+    int64_t nxc, nxs, nxh;  // complex columns, stored reals per row, stored complex per row
+    int64_t elems;          // stored reals of the batch
+    size_t tsize;
+};
+
+Spec spec_of(const gd_grid *g) {
+    Spec s;
+    s.ndim = g->ndim;
+    s.nx = g->n[0];
+    s.ny = g->n[1];
+    s.nz = g->ndim == 3 ? g->n[2] : 1;
+    s.batch = g->batch;
+    s.tsize = g->dtype == GD_F32 ? 4 : 8;
+    const int64_t lane = 16 / (int64_t)s.tsize;  // reals per 16-byte lane
+    s.nxc = s.nx / 2 + 1;
+    s.nxs = (2 * s.nxc + lane - 1) / lane * lane;
+    s.nxh = s.nxs / 2;
+    s.elems = s.batch * s.nz * s.ny * s.nxs;
+    return s;
+}
+
+int validate_spec_grid(const gd_grid *g) {
+    int rc = gd::validate_grid(g);
+    if (rc) return rc;
+    const int64_t maxn = g->dtype == GD_F32 ? 4096 : 2048;
+    for (int d = 0; d < g->ndim; ++d)
+        if (!pow2(g->n[d]) || g->n[d] > maxn)
+            return fail(GD_EINVAL, "the differential filter needs power-of-two sizes in [2, %lld] (n[%d] = %lld)",
+                        (long long)maxn, d, (long long)g->n[d]);
+    return GD_OK;
+}
+
+double inv_kc2_of(const gd_grid *g, double gamma) {
+    int64_t nmin = g->n[0];
+    for (int d = 1; d < g->ndim; ++d) nmin = std::min<int64_t>(nmin, g->n[d]);
+    const double kc = gamma * (double)nmin / 2.0;
+    return 1.0 / (kc * kc);
+}
+
+SpecMap map_of(const Spec &s, int axis, int mul, double inv_kc2) {
+    SpecMap m;
+    m.nx = s.nx;
+    m.ny = s.ny;
+    m.nz = s.nz;
+    m.nxh = s.nxh;
+    m.nxc = s.nxc;
+    m.inv_kc2 = inv_kc2;
+    m.npts = (double)(s.nx * s.ny * s.nz);
+    m.ndim = s.ndim;
+    m.axis = axis;
+    m.mul = mul;
+    return m;
+}
+
+template <typename T>
+int launch_cols(const Spec &s, T *data, int axis, bool inv, int mul, double inv_kc2, hipStream_t st) {
+    const int64_t n = axis == 1 ? s.ny : s.nz;
+    const int64_t inner = axis == 1 ? s.nxh : s.ny * s.nxh;
+    const int64_t outer = axis == 1 ? s.batch * s.nz : s.batch;
+    const size_t cs = 2 * sizeof(T);
+    const int cw = (int)std::max<int64_t>(1, std::min<int64_t>({16, inner, (int64_t)(kLdsBudget / (n * cs))}));
+    const int64_t nchunks = (inner + cw - 1) / cw;
+    const int64_t blocks = outer * nchunks;
+    if (blocks > 0x7fffffff) return fail(GD_EINVAL, "grid too large for the FFT");
+    const SpecMap m = map_of(s, axis, mul, inv_kc2);
+    const size_t lds = (size_t)n * cw * cs;
+    if (inv)
+        hipLaunchKernelGGL((k_fft_cols<T, true>), dim3((unsigned)blocks), dim3(256), lds, st, data, inner, (int)n,
+                           ilog2(n), cw, nchunks, m);
+    else
+        hipLaunchKernelGGL((k_fft_cols<T, false>), dim3((unsigned)blocks), dim3(256), lds, st, data, inner, (int)n,
+                           ilog2(n), cw, nchunks, m);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GD_OK : fail(GD_EHIP, "FFT column launch: %s", hipGetErrorString(e));
+}
+
+template <typename T>
+int rows_per_wg(const Spec &s) {
+    const int64_t n2 = s.nx / 2;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(256 / std::max<int64_t>(1, n2 / 4) + 1,
+                                                       (int64_t)(kLdsBudget / (n2 * 2 * sizeof(T)))));
+}
+
+// real fields x -> stored half spectrum X (scaled by c(k) when `scaled`, by
+// G_hat / N when `ghat`)
+template <typename T>
+int forward(const Spec &s, const T *x, T *X, int mul, double inv_kc2, hipStream_t st) {
+    const int64_t nrows = s.batch * s.nz * s.ny;
+    const int rpw = rows_per_wg<T>(s);
+    const int64_t blocks = (nrows + rpw - 1) / rpw;
+    const size_t lds = (size_t)(s.nx / 2) * rpw * 2 * sizeof(T);
+    hipLaunchKernelGGL((k_rfft_rows<T>), dim3((unsigned)blocks), dim3(256), lds, st, x, X, nrows, (int)s.nx,
+                       ilog2(s.nx / 2), s.nxh, rpw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(GD_EHIP, "FFT row launch: %s", hipGetErrorString(e));
+    int rc;
+    if (s.ndim == 2) return launch_cols<T>(s, X, 1, false, mul, inv_kc2, st);
+    if ((rc = launch_cols<T>(s, X, 1, false, MUL_NONE, inv_kc2, st))) return rc;
+    return launch_cols<T>(s, X, 2, false, mul, inv_kc2, st);
+}
+
+// stored half spectrum X (overwritten) -> real fields x
+template <typename T>
+int inverse(const Spec &s, T *X, T *x, int mul, double inv_kc2, hipStream_t st) {
+    int rc;
+    if (s.ndim == 3) {
+        if ((rc = launch_cols<T>(s, X, 2, true, mul, inv_kc2, st))) return rc;
+        if ((rc = launch_cols<T>(s, X, 1, true, MUL_NONE, inv_kc2, st))) return rc;
+    } else if ((rc = launch_cols<T>(s, X, 1, true, mul, inv_kc2, st))) {
+        return rc;
+    }
+    const int64_t nrows = s.batch * s.nz * s.ny;
+    const int rpw = rows_per_wg<T>(s);
+    const int64_t blocks = (nrows + rpw - 1) / rpw;
+    const size_t lds = (size_t)(s.nx / 2) * rpw * 2 * sizeof(T);
+    hipLaunchKernelGGL((k_irfft_rows<T>), dim3((unsigned)blocks), dim3(256), lds, st, X, x, nrows, (int)s.nx,
+                       ilog2(s.nx / 2), s.nxh, rpw);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GD_OK : fail(GD_EHIP, "FFT row launch: %s", hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// the virtual grid the persistent solve kernel runs on: the stored spectrum
+gd_grid spectral_grid(const gd_grid *g, const Spec &s) {
+    gd_grid v = *g;
+    v.n[0] = s.nxs;
+    for (int d = 0; d < g->ndim; ++d) v.h[d] = g->h[d] > 0.0 ? g->h[d] : 2.0 * M_PI / (double)g->n[d];
+    return v;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace gdspec
+
+using namespace gdspec;
+
+extern "C" {
+
+size_t germano_workspace_bytes(const gd_grid *g, int32_t solver) {
+    if (validate_spec_grid(g)) return 0;
+    const Spec s = spec_of(g);
+    const size_t spec_bytes = align256((size_t)s.elems * s.tsize);
+    if (solver < 0) return spec_bytes;
+    if (solver > GD_STEEPEST_DESCENT) return 0;
+    const gd_grid v = spectral_grid(g, s);
+    const size_t solve = deconvolve_workspace_bytes(&v, solver);
+    return solve ? 2 * spec_bytes + solve : 0;
+}
+
+int germano_filter_apply(const gd_grid *g, double gamma, const void *x, void *y, void *work, size_t wb,
+                         void *stream) {
+    int rc = validate_spec_grid(g);
+    if (rc) return rc;
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(GD_EINVAL, "gamma must be positive");
+    if (!x || !y) return fail(GD_EINVAL, "x and y must be non-NULL");
+    if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
+    if ((uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be 256-byte aligned");
+    const Spec s = spec_of(g);
+    const size_t need = germano_workspace_bytes(g, -1);
+    if (wb < need) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", need, wb);
+    const size_t fb = (size_t)s.batch * s.nx * s.ny * s.nz * s.tsize;
+    if (overlap(x, fb, work, need) || overlap(y, fb, work, need)) return fail(GD_EINVAL, "a field overlaps the workspace");
+    const double ik = inv_kc2_of(g, gamma);
+    hipStream_t st = (hipStream_t)stream;
+    if (g->dtype == GD_F32) {
+        if ((rc = forward<float>(s, (const float *)x, (float *)work, MUL_GHAT_N, ik, st))) return rc;
+        return inverse<float>(s, (float *)work, (float *)y, MUL_NONE, ik, st);
+    }
+    if ((rc = forward<double>(s, (const double *)x, (double *)work, MUL_GHAT_N, ik, st))) return rc;
+    return inverse<double>(s, (double *)work, (double *)y, MUL_NONE, ik, st);
+}
+
+int deconvolve_germano(int32_t solver, const gd_grid *g, double gamma, const void *ubar, void *u, const gd_opts *o,
+                       void *work, size_t wb, gd_info *info, void *stream) {
+    int rc = validate_spec_grid(g);
+    if (rc) return rc;
+    if ((rc = gd::validate_opts(o))) return rc;
+    if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(GD_EINVAL, "gamma must be positive");
+    if (!ubar || !u || !info) return fail(GD_EINVAL, "ubar, u and info must be non-NULL");
+    if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
+    if ((uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be 256-byte aligned");
+    const size_t need = germano_workspace_bytes(g, solver);
+    if (wb < need) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", need, wb);
+    const Spec s = spec_of(g);
+    const size_t fb = (size_t)s.batch * s.nx * s.ny * s.nz * s.tsize;
+    if (overlap(ubar, fb, u, fb)) return fail(GD_EINVAL, "ubar and u overlap");
+    if (overlap(ubar, fb, work, need) || overlap(u, fb, work, need))
+        return fail(GD_EINVAL, "a field overlaps the workspace");
+    const size_t sb = align256((size_t)s.elems * s.tsize);
+    char *w = (char *)work;
+    void *UB = w, *U = w + sb;
+    void *solve_work = w + 2 * sb;
+    const double ik = inv_kc2_of(g, gamma);
+    hipStream_t st = (hipStream_t)stream;
+    const bool f32 = g->dtype == GD_F32;
+    rc = f32 ? forward<float>(s, (const float *)ubar, (float *)UB, MUL_C, ik, st)
+             : forward<double>(s, (const double *)ubar, (double *)UB, MUL_C, ik, st);
+    if (rc) return rc;
+    if (o->init == GD_INIT_GIVEN) {
+        rc = f32 ? forward<float>(s, (const float *)u, (float *)U, MUL_C, ik, st)
+                 : forward<double>(s, (const double *)u, (double *)U, MUL_C, ik, st);
+        if (rc) return rc;
+    }
+    const gd_grid v = spectral_grid(g, s);
+    gd::SpecParams sp;
+    sp.inv_kc2 = ik;
+    sp.nxc = s.nxc;
+    gd::TuneCfg cfg;
+    rc = gd::solve_uniform(solver, &v, UB, U, o, solve_work, wb - 2 * sb, info, stream, &cfg, &sp);
+    if (rc) return rc;
+    return f32 ? inverse<float>(s, (float *)U, (float *)u, MUL_INV_CN, ik, st)
+               : inverse<double>(s, (double *)U, (double *)u, MUL_INV_CN, ik, st);
+}
+
+}  // extern "C"

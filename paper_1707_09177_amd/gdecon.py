@@ -80,7 +80,8 @@ EXPORTS = ["filter_apply", "deconvolve_workspace_bytes", "deconvolve_vancittert"
            "deconvolve_bicgstab", "deconvolve_steepest_descent", "gd_status_string", "gd_last_error",
            "gd_last_launch", "gd_set_trace", "deconvolve_batch_workspace_bytes", "deconvolve_batch",
            "deconvolve_autotune", "deconvolve_batch_autotune", "gd_tune_reset", "gd_tune_set", "gd_tune_set_batch", "warmstart_param_count",
-           "warmstart_workspace_bytes", "warmstart_forward", "warmstart_train_step", "closure_stress"]
+           "warmstart_workspace_bytes", "warmstart_forward", "warmstart_train_step", "closure_stress",
+           "germano_filter", "GermanoDeconvolver", "deconvolve_germano"]
 
 _lib = None
 
@@ -126,6 +127,12 @@ def load(path: str = LIB_PATH):
     lib.gd_tune_set.restype = ctypes.c_int
     lib.gd_tune_set_batch.argtypes = [i32, i32, ip, i32, tp]
     lib.gd_tune_set_batch.restype = ctypes.c_int
+    lib.germano_workspace_bytes.argtypes = [gp, ctypes.c_int32]
+    lib.germano_workspace_bytes.restype = ctypes.c_size_t
+    lib.germano_filter_apply.argtypes = [gp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.germano_filter_apply.restype = ctypes.c_int
+    lib.deconvolve_germano.argtypes = [ctypes.c_int32, gp, ctypes.c_double, vp, vp, op, vp, ctypes.c_size_t, vp, vp]
+    lib.deconvolve_germano.restype = ctypes.c_int
     lib.closure_stress.argtypes = [gp, vp, vp, vp, vp]
     lib.closure_stress.restype = ctypes.c_int
     cp = ctypes.POINTER(Cnn)
@@ -280,6 +287,69 @@ class Deconvolver:
                       self.work.data_ptr(), self.work.numel(), self.info_dev.data_ptr(), _stream_handle(stream))
         _check(rc)
         return SolveResult(u, self.info_dev, history)
+
+
+def germano_filter(x: torch.Tensor, gamma: float, ndim: int = 2, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """y = G x with the paper's differential filter G = (I - delta^2 lap)^-1,
+    transfer function 1 / (1 + (|k| / k_c)^2), k_c = gamma * min(n) / 2, applied
+    through the library's FFTs (germano_filter_apply).  Power-of-two sizes."""
+    lib = load()
+    g = make_grid(x.shape, ndim, x.dtype)
+    n = lib.germano_workspace_bytes(ctypes.byref(g), -1)
+    if n == 0:
+        raise GdError(-1, "bad grid (the differential filter needs power-of-two sizes)")
+    work = torch.empty(int(n), dtype=torch.uint8, device=x.device)
+    y = torch.empty_like(x) if out is None else out
+    _check(lib.germano_filter_apply(ctypes.byref(g), float(gamma), _dev_ptr(x), _dev_ptr(y), work.data_ptr(),
+                                    work.numel(), _stream_handle(stream)))
+    return y
+
+
+class GermanoDeconvolver(Deconvolver):
+    """Deconvolver for the differential filter with parameter gamma
+    (deconvolve_germano): the solve runs on the Fourier coefficients."""
+
+    def __init__(self, field_shape, ndim: int, dtype: torch.dtype, solver: str, gamma: float, device=None, h=None):
+        self.lib = load()
+        self.shape = tuple(field_shape)
+        self.ndim = ndim
+        self.dtype = dtype
+        self.solver = solver
+        self.gamma = float(gamma)
+        self.grid = make_grid(self.shape, ndim, dtype, h)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        n = self.lib.germano_workspace_bytes(ctypes.byref(self.grid), SOLVERS[solver])
+        if n == 0:
+            raise GdError(-1, "bad grid or solver (the differential filter needs power-of-two sizes)")
+        self.work = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        self.batch = int(self.grid.batch)
+        self.info_dev = torch.zeros(self.batch * INFO_BYTES, dtype=torch.uint8, device=self.device)
+        code = SOLVERS[solver]
+        fn = self.lib.deconvolve_germano
+
+        def call(grid, ub, u, o, work, wb, info, stream):
+            return fn(code, grid, self.gamma, ub, u, o, work, wb, info, stream)
+        self._fn = call
+
+
+def deconvolve_germano(solver: str, ubar: torch.Tensor, max_iter: int, gamma: float, tol: float = 0.0,
+                       ndim: int = 2, init: str = "ubar", u0: torch.Tensor | None = None, norm_ref: str = "r0ubar",
+                       history: bool = False, h=None, stream=None):
+    """One-shot solve of G u = ubar with the differential filter.  Returns
+    (u, infos, history or None); synchronises the stream."""
+    d = GermanoDeconvolver(ubar.shape, ndim, ubar.dtype, solver, gamma, device=ubar.device, h=h)
+    out = None
+    if init == "given":
+        if u0 is None:
+            raise ValueError("init='given' needs u0")
+        out = u0.clone()
+    hist = None
+    if history:
+        hist = torch.full((d.batch, max_iter + 1), float("nan"), dtype=torch.float64, device=ubar.device)
+    res = d.solve(ubar, max_iter, tol, init=init, out=out, norm_ref=norm_ref, history=hist, stream=stream)
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return res.u, res.info(), hist
 
 
 def _make_opts(max_iter, tol, init, norm_ref, history, wait_limit_us) -> Opts:
