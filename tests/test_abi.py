@@ -156,3 +156,37 @@ def test_closure_stress_host_side_validation():
     assert lib.closure_stress(ctypes.byref(g), ub, us, us + 4096, None) == -1
     assert "overlaps" in lib.gd_last_error().decode()
     assert lib.closure_stress(ctypes.byref(g), ub, us, us - 12288 + 4, None) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgdecon.so not built")
+def test_germano_host_side_validation():
+    """The differential-filter entry points accept power-of-two sizes only and
+    check gamma, pointers and the workspace before any launch."""
+    from paper_1707_09177_amd import gdecon
+    lib = gdecon.load()
+    g = gdecon.make_grid((2, 64, 32), 2, gdecon.torch.float32)
+    assert lib.germano_workspace_bytes(ctypes.byref(g), -1) >= 2 * 64 * (32 + 4) * 4
+    assert lib.germano_workspace_bytes(ctypes.byref(g), 2) > lib.deconvolve_workspace_bytes(ctypes.byref(g), 2)
+    assert lib.germano_workspace_bytes(ctypes.byref(g), 9) == 0
+    bad = gdecon.make_grid((2, 48, 32), 2, gdecon.torch.float32)
+    assert lib.germano_workspace_bytes(ctypes.byref(bad), -1) == 0
+    assert lib.germano_filter_apply(ctypes.byref(bad), 0.1, 0x10000, 0x20000, 0x100000, 1 << 30, None) == -1
+    assert "power-of-two" in lib.gd_last_error().decode()
+    big = gdecon.make_grid((8192, 2), 2, gdecon.torch.float32)
+    assert lib.germano_workspace_bytes(ctypes.byref(big), -1) == 0
+    f64 = gdecon.make_grid((4096, 2), 2, gdecon.torch.float64)
+    assert lib.germano_workspace_bytes(ctypes.byref(f64), -1) == 0
+    assert lib.germano_filter_apply(ctypes.byref(g), 0.0, 0x10000, 0x20000, 0x100000, 1 << 30, None) == -1
+    assert "gamma" in lib.gd_last_error().decode()
+    assert lib.germano_filter_apply(ctypes.byref(g), 0.1, 0x10000, 0x20000, None, 0, None) == -2
+    assert lib.germano_filter_apply(ctypes.byref(g), 0.1, 0x10000, 0x20000, 0x100010, 1 << 30, None) == -4
+    o = gdecon.Opts()
+    o.max_iter = 3
+    info = ctypes.c_void_p(0x1000)
+    assert lib.deconvolve_germano(2, ctypes.byref(g), 0.1, 0x10000, 0x10000, ctypes.byref(o), 0x1000000, 1 << 30,
+                                  info, None) == -1
+    assert "overlap" in lib.gd_last_error().decode()
+    assert lib.deconvolve_germano(7, ctypes.byref(g), 0.1, 0x10000, 0x20000, ctypes.byref(o), 0x1000000, 1 << 30,
+                                  info, None) == -1
+    assert lib.deconvolve_germano(2, ctypes.byref(g), 0.1, 0x10000, 0x40000, ctypes.byref(o), 0x1000000, 16,
+                                  info, None) == -2
