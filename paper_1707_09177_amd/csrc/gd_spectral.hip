@@ -22,8 +22,8 @@
 // FFTs: power-of-two lengths.  Rows (x) use the half-length complex
 // transform of the even/odd-packed real row plus the standard split; y and z
 // transform strided columns, a workgroup taking a few adjacent columns so
-// that its loads are contiguous runs of them.  Each transform is radix-2,
-// decimation in time, in LDS after a bit-reversed load.
+// that its loads are contiguous runs of them.  Each transform is decimation
+// in time in LDS after a bit-reversed load, two radix-2 stages at a time.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,6 +49,17 @@ int fail(int code, const char *fmt, ...) {
 
 __constant__ gdtw::Table c_tw = gdtw::make_table();
 
+struct TableF {
+    float2 v[gdtw::kTwN / 2];
+};
+constexpr TableF make_table_f() {
+    TableF t{};
+    const gdtw::Table d = gdtw::make_table();
+    for (int k = 0; k < gdtw::kTwN / 2; ++k) t.v[k] = float2{float(d.v[k].re), float(d.v[k].im)};
+    return t;
+}
+__constant__ TableF c_twf = make_table_f();
+
 template <typename T> struct V2;
 template <> struct V2<float> { using t = float2; };
 template <> struct V2<double> { using t = double2; };
@@ -61,8 +72,13 @@ __device__ __forceinline__ typename V2<T>::t cmul(typename V2<T>::t a, typename 
 // exp(-+2 pi i k / n), k < n / 2 (n a power of two <= kTwN), from the table
 template <typename T, bool INV>
 __device__ __forceinline__ typename V2<T>::t tw(int k, int tstride) {
-    const gdtw::Cd c = c_tw.v[k * tstride];
-    return {T(c.re), INV ? T(-c.im) : T(c.im)};
+    if constexpr (sizeof(T) == 4) {
+        const float2 c = c_twf.v[k * tstride];
+        return {c.x, INV ? -c.y : c.y};
+    } else {
+        const gdtw::Cd c = c_tw.v[k * tstride];
+        return {c.re, INV ? -c.im : c.im};
+    }
 }
 
 // exp(-+2 pi i k / n) for 0 <= k <= n (used by the real-row split)
@@ -78,24 +94,48 @@ __device__ __forceinline__ typename V2<T>::t tw_full(int k, int n) {
 
 __device__ __forceinline__ int bitrev(int j, int logn) { return logn == 0 ? 0 : (int)(__brev((unsigned)j) >> (32 - logn)); }
 
-// In-place radix-2 DIT transforms of ncols columns of length n, stored
-// buf[j * cw + c], already in bit-reversed order.
+// In-place DIT transforms of the cw = 2^logcw columns of length n stored
+// buf[j * cw + c], already in bit-reversed order: one radix-2 stage when
+// log2 n is odd, then pairs of radix-2 stages fused into radix-4 butterflies
+// held in registers (half the LDS round trips and barriers).
 template <typename T, bool INV>
-__device__ __forceinline__ void lds_fft(typename V2<T>::t *buf, int n, int logn, int cw, int ncols) {
+__device__ __forceinline__ void lds_fft(typename V2<T>::t *buf, int n, int logn, int logcw) {
     using V = typename V2<T>::t;
-    const int nb = (n / 2) * ncols;
-    for (int s = 1; s <= logn; ++s) {
-        const int half = 1 << (s - 1);
-        const int tstride = gdtw::kTwN >> s;  // twiddle of pos: exp(-2 pi i pos / 2^s)
-        for (int b = threadIdx.x; b < nb; b += 256) {
-            const int c = b % ncols, bb = b / ncols;
-            const int pos = bb & (half - 1);
-            const int i0 = ((bb >> (s - 1)) << s) + pos;
-            const V w = tw<T, INV>(pos, tstride);
-            const V a = buf[i0 * cw + c];
-            const V x = cmul<T>(buf[(i0 + half) * cw + c], w);
-            buf[i0 * cw + c] = {a.x + x.x, a.y + x.y};
-            buf[(i0 + half) * cw + c] = {a.x - x.x, a.y - x.y};
+    const int cmask = (1 << logcw) - 1;
+    auto at = [&](int i, int c) -> V & { return buf[(i << logcw) + c]; };
+    int s = 1;
+    if (logn & 1) {
+        for (int b = threadIdx.x; b < (n / 2) << logcw; b += 256) {
+            const int c = b & cmask, i0 = (b >> logcw) << 1;
+            const V a = at(i0, c), x = at(i0 + 1, c);
+            at(i0, c) = {a.x + x.x, a.y + x.y};
+            at(i0 + 1, c) = {a.x - x.x, a.y - x.y};
+        }
+        __syncthreads();
+        s = 2;
+    }
+    for (; s < logn; s += 2) {
+        const int h = 1 << (s - 1);
+        const int ts1 = gdtw::kTwN >> s, ts2 = gdtw::kTwN >> (s + 1);
+        for (int b = threadIdx.x; b < (n / 4) << logcw; b += 256) {
+            const int c = b & cmask, bb = b >> logcw;
+            const int pos = bb & (h - 1);
+            const int i0 = ((bb >> (s - 1)) << (s + 1)) + pos;
+            const V x0 = at(i0, c), x1 = at(i0 + h, c), x2 = at(i0 + 2 * h, c), x3 = at(i0 + 3 * h, c);
+            const V w1 = tw<T, INV>(pos, ts1), w2 = tw<T, INV>(pos, ts2);
+            // stage s: pairs (x0, x1) and (x2, x3), twiddle W_2h^pos
+            V t = cmul<T>(x1, w1);
+            const V a0 = {x0.x + t.x, x0.y + t.y}, a1 = {x0.x - t.x, x0.y - t.y};
+            t = cmul<T>(x3, w1);
+            const V a2 = {x2.x + t.x, x2.y + t.y}, a3 = {x2.x - t.x, x2.y - t.y};
+            // stage s+1: pairs (a0, a2) with W_4h^pos, (a1, a3) with W_4h^(pos+h) = W_4h^pos (-+i)
+            t = cmul<T>(a2, w2);
+            at(i0, c) = {a0.x + t.x, a0.y + t.y};
+            at(i0 + 2 * h, c) = {a0.x - t.x, a0.y - t.y};
+            t = cmul<T>(a3, w2);
+            t = INV ? V{-t.y, t.x} : V{t.y, -t.x};
+            at(i0 + h, c) = {a1.x + t.x, a1.y + t.y};
+            at(i0 + 3 * h, c) = {a1.x - t.x, a1.y - t.y};
         }
         __syncthreads();
     }
@@ -136,11 +176,12 @@ __device__ __forceinline__ double mul_at(const SpecMap &m, int64_t kx, int64_t k
 // The multiplier (if any) is applied after a forward / before an inverse
 // transform.
 template <typename T, bool INV>
-__global__ __launch_bounds__(256) void k_fft_cols(T *data, int64_t inner, int n, int logn, int cw, int64_t nchunks,
+__global__ __launch_bounds__(256) void k_fft_cols(T *data, int64_t inner, int n, int logn, int logcw, int64_t nchunks,
                                                   SpecMap m) {
     using V = typename V2<T>::t;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     V *buf = reinterpret_cast<V *>(lds_raw);
+    const int cw = 1 << logcw;
     const int64_t chunk = blockIdx.x % nchunks, o = blockIdx.x / nchunks;
     const int64_t i0 = chunk * cw;
     const int ncols = (int)std::min<int64_t>(cw, inner - i0);
@@ -150,20 +191,24 @@ __global__ __launch_bounds__(256) void k_fft_cols(T *data, int64_t inner, int n,
         if (m.axis == 1) return mul_at(m, ii, j, m.ndim == 3 ? o % m.nz : 0);
         return mul_at(m, ii % m.nxh, ii / m.nxh, j);
     };
-    for (int idx = threadIdx.x; idx < n * ncols; idx += 256) {
-        const int c = idx % ncols, j = idx / ncols;
-        V v = base[(int64_t)j * inner + c];
-        if (INV && m.mul != MUL_NONE) {
-            const T s = T(mult(j, c));
-            v = {v.x * s, v.y * s};
+    for (int idx = threadIdx.x; idx < n << logcw; idx += 256) {
+        const int c = idx & (cw - 1), j = idx >> logcw;
+        V v = {T(0), T(0)};
+        if (c < ncols) {
+            v = base[(int64_t)j * inner + c];
+            if (INV && m.mul != MUL_NONE) {
+                const T s = T(mult(j, c));
+                v = {v.x * s, v.y * s};
+            }
         }
-        buf[bitrev(j, logn) * cw + c] = v;
+        buf[(bitrev(j, logn) << logcw) + c] = v;
     }
     __syncthreads();
-    lds_fft<T, INV>(buf, n, logn, cw, ncols);
-    for (int idx = threadIdx.x; idx < n * ncols; idx += 256) {
-        const int c = idx % ncols, j = idx / ncols;
-        V v = buf[j * cw + c];
+    lds_fft<T, INV>(buf, n, logn, logcw);
+    for (int idx = threadIdx.x; idx < n << logcw; idx += 256) {
+        const int c = idx & (cw - 1), j = idx >> logcw;
+        if (c >= ncols) continue;
+        V v = buf[(j << logcw) + c];
         if (!INV && m.mul != MUL_NONE) {
             const T s = T(mult(j, c));
             v = {v.x * s, v.y * s};
@@ -176,28 +221,28 @@ __global__ __launch_bounds__(256) void k_fft_cols(T *data, int64_t inner, int n,
 // k = 0 .. nx/2, then zero padding).  rpw rows per workgroup.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rfft_rows(const T *x, T *X, int64_t nrows, int nx, int logn2, int64_t nxh,
-                                                   int rpw) {
+                                                   int logrpw) {
     using V = typename V2<T>::t;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     V *buf = reinterpret_cast<V *>(lds_raw);
-    const int n2 = nx / 2;
+    const int n2 = nx / 2, rpw = 1 << logrpw;
     const int64_t r0 = (int64_t)blockIdx.x * rpw;
     const int nr = (int)std::min<int64_t>(rpw, nrows - r0);
     const V *src = reinterpret_cast<const V *>(x + r0 * nx);  // z[j] = x[2j] + i x[2j+1]
-    for (int idx = threadIdx.x; idx < n2 * nr; idx += 256) {
-        const int r = idx / n2, j = idx % n2;
-        buf[bitrev(j, logn2) * rpw + r] = src[(int64_t)r * n2 + j];
+    for (int idx = threadIdx.x; idx < n2 << logrpw; idx += 256) {
+        const int r = idx >> logn2, j = idx & (n2 - 1);
+        buf[(bitrev(j, logn2) << logrpw) + r] = r < nr ? src[(int64_t)r * n2 + j] : V{T(0), T(0)};
     }
     __syncthreads();
-    lds_fft<T, false>(buf, n2, logn2, rpw, nr);
+    lds_fft<T, false>(buf, n2, logn2, logrpw);
     V *dst = reinterpret_cast<V *>(X) + r0 * nxh;
     for (int idx = threadIdx.x; idx < (int)nxh * nr; idx += 256) {
         const int r = idx / (int)nxh, k = idx % (int)nxh;
         V out = {T(0), T(0)};
         if (k <= n2) {
             // X[k] = (Z[k] + conj Z[n2-k]) / 2 - i/2 exp(-2 pi i k / nx) (Z[k] - conj Z[n2-k])
-            const V zk = buf[(k % n2) * rpw + r];
-            const V zm0 = buf[((n2 - k) % n2) * rpw + r];
+            const V zk = buf[((k & (n2 - 1)) << logrpw) + r];
+            const V zm0 = buf[(((n2 - k) & (n2 - 1)) << logrpw) + r];
             const V zm = {zm0.x, -zm0.y};
             const V e = {T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y + zm.y)};
             const V d = {T(0.5) * (zk.x - zm.x), T(0.5) * (zk.y - zm.y)};
@@ -213,18 +258,22 @@ __global__ __launch_bounds__(256) void k_rfft_rows(const T *x, T *X, int64_t nro
 // unnormalised inverse (nx times the inverse DFT along x).
 template <typename T>
 __global__ __launch_bounds__(256) void k_irfft_rows(const T *X, T *x, int64_t nrows, int nx, int logn2, int64_t nxh,
-                                                    int rpw) {
+                                                    int logrpw) {
     using V = typename V2<T>::t;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     V *buf = reinterpret_cast<V *>(lds_raw);
-    const int n2 = nx / 2;
+    const int n2 = nx / 2, rpw = 1 << logrpw;
     const int64_t r0 = (int64_t)blockIdx.x * rpw;
     const int nr = (int)std::min<int64_t>(rpw, nrows - r0);
     const V *src = reinterpret_cast<const V *>(X) + r0 * nxh;
     const int np = n2 / 2 + 1;  // pairs (k, n2 - k), k = 0 .. n2/2
-    for (int idx = threadIdx.x; idx < np * nr; idx += 256) {
+    for (int idx = threadIdx.x; idx < np * rpw; idx += 256) {
         const int r = idx / np, k = idx % np;
-        const V a = src[(int64_t)r * nxh + k], b = src[(int64_t)r * nxh + (n2 - k)];
+        V a = {T(0), T(0)}, b = {T(0), T(0)};
+        if (r < nr) {
+            a = src[(int64_t)r * nxh + k];
+            b = src[(int64_t)r * nxh + (n2 - k)];
+        }
         // Z[k] = (X[k] + conj X[n2-k]) + i exp(2 pi i k / nx) (X[k] - conj X[n2-k])
         auto z_of = [&](V xk, V xm, int kk) -> V {
             const V s = {xk.x + xm.x, xk.y - xm.y};
@@ -232,15 +281,15 @@ __global__ __launch_bounds__(256) void k_irfft_rows(const T *X, T *x, int64_t nr
             const V wd = cmul<T>(tw_full<T, true>(kk, nx), d);
             return {s.x - wd.y, s.y + wd.x};  // s + i wd
         };
-        if (k < n2) buf[bitrev(k, logn2) * rpw + r] = z_of(a, b, k);
-        if (k != 0 && n2 - k != k) buf[bitrev(n2 - k, logn2) * rpw + r] = z_of(b, a, n2 - k);
+        if (k < n2) buf[(bitrev(k, logn2) << logrpw) + r] = z_of(a, b, k);
+        if (k != 0 && n2 - k != k) buf[(bitrev(n2 - k, logn2) << logrpw) + r] = z_of(b, a, n2 - k);
     }
     __syncthreads();
-    lds_fft<T, true>(buf, n2, logn2, rpw, nr);
+    lds_fft<T, true>(buf, n2, logn2, logrpw);
     V *dst = reinterpret_cast<V *>(x + r0 * nx);
     for (int idx = threadIdx.x; idx < n2 * nr; idx += 256) {
-        const int r = idx / n2, j = idx % n2;
-        dst[(int64_t)r * n2 + j] = buf[j * rpw + r];
+        const int r = idx >> logn2, j = idx & (n2 - 1);
+        dst[(int64_t)r * n2 + j] = buf[(j << logrpw) + r];
     }
 }
 
@@ -318,7 +367,9 @@ int launch_cols(const Spec &s, T *data, int axis, bool inv, int mul, double inv_
     const int64_t inner = axis == 1 ? s.nxh : s.ny * s.nxh;
     const int64_t outer = axis == 1 ? s.batch * s.nz : s.batch;
     const size_t cs = 2 * sizeof(T);
-    const int cw = (int)std::max<int64_t>(1, std::min<int64_t>({16, inner, (int64_t)(kLdsBudget / (n * cs))}));
+    int logcw = 0;  // adjacent columns per workgroup: a power of two, up to 16, within the LDS budget
+    while (logcw < 4 && (int64_t(2) << logcw) <= inner && (size_t)n * (size_t(2) << logcw) * cs <= kLdsBudget) ++logcw;
+    const int cw = 1 << logcw;
     const int64_t nchunks = (inner + cw - 1) / cw;
     const int64_t blocks = outer * nchunks;
     if (blocks > 0x7fffffff) return fail(GD_EINVAL, "grid too large for the FFT");
@@ -326,19 +377,23 @@ int launch_cols(const Spec &s, T *data, int axis, bool inv, int mul, double inv_
     const size_t lds = (size_t)n * cw * cs;
     if (inv)
         hipLaunchKernelGGL((k_fft_cols<T, true>), dim3((unsigned)blocks), dim3(256), lds, st, data, inner, (int)n,
-                           ilog2(n), cw, nchunks, m);
+                           ilog2(n), logcw, nchunks, m);
     else
         hipLaunchKernelGGL((k_fft_cols<T, false>), dim3((unsigned)blocks), dim3(256), lds, st, data, inner, (int)n,
-                           ilog2(n), cw, nchunks, m);
+                           ilog2(n), logcw, nchunks, m);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GD_OK : fail(GD_EHIP, "FFT column launch: %s", hipGetErrorString(e));
 }
 
+// log2 of the rows per workgroup of the row transforms: enough rows for 256
+// threads' worth of radix-4 butterflies (n2 / 4 per row), within the LDS budget
 template <typename T>
-int rows_per_wg(const Spec &s) {
+int log_rows_per_wg(const Spec &s) {
     const int64_t n2 = s.nx / 2;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(256 / std::max<int64_t>(1, n2 / 4) + 1,
-                                                       (int64_t)(kLdsBudget / (n2 * 2 * sizeof(T)))));
+    int l = 0;
+    while ((std::max<int64_t>(1, n2 / 4) << l) < 256 && (n2 << (l + 1)) * 2 * (int64_t)sizeof(T) <= (int64_t)kLdsBudget)
+        ++l;
+    return l;
 }
 
 // real fields x -> stored half spectrum X (scaled by c(k) when `scaled`, by
@@ -346,11 +401,11 @@ int rows_per_wg(const Spec &s) {
 template <typename T>
 int forward(const Spec &s, const T *x, T *X, int mul, double inv_kc2, hipStream_t st) {
     const int64_t nrows = s.batch * s.nz * s.ny;
-    const int rpw = rows_per_wg<T>(s);
+    const int lr = log_rows_per_wg<T>(s), rpw = 1 << lr;
     const int64_t blocks = (nrows + rpw - 1) / rpw;
     const size_t lds = (size_t)(s.nx / 2) * rpw * 2 * sizeof(T);
     hipLaunchKernelGGL((k_rfft_rows<T>), dim3((unsigned)blocks), dim3(256), lds, st, x, X, nrows, (int)s.nx,
-                       ilog2(s.nx / 2), s.nxh, rpw);
+                       ilog2(s.nx / 2), s.nxh, lr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(GD_EHIP, "FFT row launch: %s", hipGetErrorString(e));
     int rc;
@@ -370,11 +425,11 @@ int inverse(const Spec &s, T *X, T *x, int mul, double inv_kc2, hipStream_t st) 
         return rc;
     }
     const int64_t nrows = s.batch * s.nz * s.ny;
-    const int rpw = rows_per_wg<T>(s);
+    const int lr = log_rows_per_wg<T>(s), rpw = 1 << lr;
     const int64_t blocks = (nrows + rpw - 1) / rpw;
     const size_t lds = (size_t)(s.nx / 2) * rpw * 2 * sizeof(T);
     hipLaunchKernelGGL((k_irfft_rows<T>), dim3((unsigned)blocks), dim3(256), lds, st, X, x, nrows, (int)s.nx,
-                       ilog2(s.nx / 2), s.nxh, rpw);
+                       ilog2(s.nx / 2), s.nxh, lr);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GD_OK : fail(GD_EHIP, "FFT row launch: %s", hipGetErrorString(e));
 }
