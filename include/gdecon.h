@@ -337,6 +337,33 @@ int deconvolve_germano(int32_t solver, const gd_grid *grid, double gamma, const 
                        const gd_opts *opts, void *work, size_t work_bytes, gd_info *info, void *stream);
 
 /*
+ * ---- A-priori diagnostics -------------------------------------------------------
+ *
+ * The paper judges recovered fields by their energy spectra and by the PDFs
+ * of their values (Sec. 4, the spectra and PDF figures of the 2D and 3D
+ * cases).  With f_hat(k) = (1/N) sum_x f(x) exp(-i k.x) (integer wavenumbers
+ * of the 2 pi periodic grid):
+ *   energy_spectrum: out[b][s] = 1/2 sum over the wavenumbers whose |k|
+ *     rounds to s of |k|^kpow |f_hat(k)|^2, s = 0 .. spectrum_shells() - 1
+ *     (kpow = 0: the spectrum of f, summing to mean(f^2)/2; kpow = -2 turns a
+ *     2D vorticity field into its kinetic energy spectrum, k = 0 then adding
+ *     nothing).  Power-of-two sizes as for the differential filter.  out is
+ *     device FP64 [batch][nshells]; work of spectrum_workspace_bytes().
+ *   pdf_counts: counts[b][i] = number of points of field b whose value v has
+ *     floor((v - lo) * (nbins / (hi - lo))) = i (evaluated in FP64), v = hi in
+ *     the last bin, values outside [lo, hi] and NaN not counted.  Any grid
+ *     size; 1 <= nbins <= 8192; counts is device int64 [batch][nbins],
+ *     cleared by the call (by a kernel, so it can be captured).
+ * Stream-ordered.  Errors: GD_EINVAL, GD_EWORKSPACE, GD_EALIGN, GD_EHIP.
+ */
+int32_t spectrum_shells(const gd_grid *grid);
+size_t spectrum_workspace_bytes(const gd_grid *grid);
+int energy_spectrum(const gd_grid *grid, double kpow, const void *x, double *out, void *work, size_t work_bytes,
+                    void *stream);
+int pdf_counts(const gd_grid *grid, double lo, double hi, int32_t nbins, const void *x, int64_t *counts,
+               void *stream);
+
+/*
  * ---- Closure stress ----------------------------------------------------------
  *
  * The sub-filter stress of the filtered equations, tau_ij = ubar_i ubar_j -

@@ -449,6 +449,115 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     return x < y + nb && y < x + na;
 }
 
+// ---- a-priori diagnostics: energy spectra and PDFs ---------------------------
+
+// nearest integer to sqrt(k2) for integer k2 >= 0, decided in integer arithmetic
+__host__ __device__ inline int64_t shell_of(int64_t k2) {
+    int64_t s = (int64_t)sqrt((double)k2);
+    if ((2 * s + 1) * (2 * s + 1) <= 4 * k2) ++s;
+    if (s > 0 && (2 * s - 1) * (2 * s - 1) > 4 * k2) --s;
+    return s;
+}
+
+int64_t num_shells(const Spec &s) {
+    const int64_t a = s.nx / 2, b = s.ny / 2, c = s.ndim == 3 ? s.nz / 2 : 0;
+    return shell_of(a * a + b * b + c * c) + 1;
+}
+
+// Partial shell sums of one chunk of rows of one field's stored spectrum:
+// 1/2 w(k_x) |X / N|^2 |k|^p per coefficient, accumulated per shell in LDS.
+// A wave takes whole rows; along a row |k| grows with k_x, so the lanes of a
+// wave hold nondecreasing shells, summed by a segmented scan before one LDS
+// atomic per segment.
+template <typename T>
+__global__ __launch_bounds__(256) void k_spectrum_part(const T *X, double *part, int64_t rows_per_field,
+                                                       int64_t rows_per_chunk, int64_t nchunks, int64_t nshells, Spec s,
+                                                       double kpow) {
+    using V = typename V2<T>::t;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double *bins = reinterpret_cast<double *>(lds_raw);
+    for (int64_t i = threadIdx.x; i < nshells; i += 256) bins[i] = 0.0;
+    __syncthreads();
+    const int64_t b = blockIdx.x / nchunks, ch = blockIdx.x % nchunks;
+    const int64_t row0 = ch * rows_per_chunk, row1 = std::min(rows_per_field, row0 + rows_per_chunk);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const V *F = reinterpret_cast<const V *>(X) + b * rows_per_field * s.nxh;
+    const double inv_n2 = 1.0 / ((double)(s.nx * s.ny * s.nz) * (double)(s.nx * s.ny * s.nz));
+    for (int64_t row = row0 + wave; row < row1; row += 4) {
+        const int64_t ky = row % s.ny, kz = row / s.ny;
+        const int64_t a = ky <= s.ny / 2 ? ky : ky - s.ny, c = kz <= s.nz / 2 ? kz : kz - s.nz;
+        const int64_t kyz2 = a * a + c * c;
+        for (int64_t kx0 = 0; kx0 < s.nxc; kx0 += 64) {
+            const int64_t kx = kx0 + lane;
+            double v = 0.0;
+            int64_t key = -1;
+            if (kx < s.nxc) {
+                const V z = F[row * s.nxh + kx];
+                const int64_t k2 = kx * kx + kyz2;
+                const double w = (kx == 0 || 2 * kx == s.nx) ? 0.5 : 1.0;
+                double kp = 1.0;
+                if (kpow != 0.0) kp = k2 > 0 ? pow((double)k2, 0.5 * kpow) : 0.0;
+                v = w * ((double)z.x * (double)z.x + (double)z.y * (double)z.y) * inv_n2 * kp;
+                key = shell_of(k2);
+            }
+            // segmented inclusive scan over equal, contiguous keys
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const double ov = __shfl_up(v, off, 64);
+                const int64_t ok = __shfl_up(key, off, 64);
+                if (lane >= off && ok == key) v += ov;
+            }
+            const int64_t next = __shfl_down(key, 1, 64);
+            if (key >= 0 && (lane == 63 || next != key)) atomicAdd(&bins[key], v);
+        }
+    }
+    __syncthreads();
+    double *dst = part + (b * nchunks + ch) * nshells;
+    for (int64_t i = threadIdx.x; i < nshells; i += 256) dst[i] = bins[i];
+}
+
+// out[b][s] = sum over chunks in chunk order
+__global__ void k_spectrum_reduce(const double *part, double *out, int64_t nchunks, int64_t nshells, int64_t batch) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= batch * nshells) return;
+    const int64_t b = t / nshells, sh = t % nshells;
+    double acc = 0.0;
+    for (int64_t c = 0; c < nchunks; ++c) acc += part[(b * nchunks + c) * nshells + sh];
+    out[t] = acc;
+}
+
+__global__ void k_zero_i64(int64_t *p, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0;
+}
+
+// PDF bin counts: LDS counters per workgroup (one field's chunk), then one
+// global integer atomic per nonzero bin.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pdf(const T *x, int64_t *counts, int64_t npts, int64_t chunk, int64_t nchunks,
+                                             double lo, double hi, double scale, int nbins) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    unsigned *bins = reinterpret_cast<unsigned *>(lds_raw);
+    for (int i = threadIdx.x; i < nbins; i += 256) bins[i] = 0u;
+    __syncthreads();
+    const int64_t b = blockIdx.x / nchunks, ch = blockIdx.x % nchunks;
+    const int64_t i0 = ch * chunk, i1 = std::min(npts, i0 + chunk);
+    const T *f = x + b * npts;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const double v = (double)f[i];
+        if (v >= lo && v <= hi) {  // false for NaN
+            int64_t k = (int64_t)floor((v - lo) * scale);
+            if (k > nbins - 1) k = nbins - 1;
+            atomicAdd(&bins[k], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += 256)
+        if (bins[i]) atomicAdd(reinterpret_cast<unsigned long long *>(&counts[b * nbins + i]), (unsigned long long)bins[i]);
+}
+
+constexpr int kMaxPdfBins = 8192;
+
 }  // namespace gdspec
 
 using namespace gdspec;
@@ -530,6 +639,85 @@ int deconvolve_germano(int32_t solver, const gd_grid *g, double gamma, const voi
     if (rc) return rc;
     return f32 ? inverse<float>(s, (float *)U, (float *)u, MUL_INV_CN, ik, st)
                : inverse<double>(s, (double *)U, (double *)u, MUL_INV_CN, ik, st);
+}
+
+int32_t spectrum_shells(const gd_grid *g) {
+    if (validate_spec_grid(g)) return 0;
+    return (int32_t)num_shells(spec_of(g));
+}
+
+static int64_t spectrum_chunks(const Spec &s) {
+    const int64_t rows = s.ny * s.nz;
+    return std::max<int64_t>(1, std::min<int64_t>(rows / 8, std::max<int64_t>(1, 2048 / s.batch)));
+}
+
+size_t spectrum_workspace_bytes(const gd_grid *g) {
+    if (validate_spec_grid(g)) return 0;
+    const Spec s = spec_of(g);
+    return align256((size_t)s.elems * s.tsize) +
+           align256((size_t)s.batch * spectrum_chunks(s) * num_shells(s) * sizeof(double));
+}
+
+int energy_spectrum(const gd_grid *g, double kpow, const void *x, double *out, void *work, size_t wb, void *stream) {
+    int rc = validate_spec_grid(g);
+    if (rc) return rc;
+    if (!std::isfinite(kpow)) return fail(GD_EINVAL, "kpow must be finite");
+    if (!x || !out) return fail(GD_EINVAL, "x and out must be non-NULL");
+    if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
+    if ((uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be 256-byte aligned");
+    const Spec s = spec_of(g);
+    const size_t need = spectrum_workspace_bytes(g);
+    if (wb < need) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", need, wb);
+    const int64_t ns = num_shells(s), nch = spectrum_chunks(s);
+    const size_t fb = (size_t)s.batch * s.nx * s.ny * s.nz * s.tsize;
+    if (overlap(x, fb, work, need) || overlap(out, (size_t)s.batch * ns * 8, work, need))
+        return fail(GD_EINVAL, "a buffer overlaps the workspace");
+    if ((size_t)ns * sizeof(double) > kLdsBudget) return fail(GD_EINVAL, "too many shells");
+    hipStream_t st = (hipStream_t)stream;
+    double *part = (double *)((char *)work + align256((size_t)s.elems * s.tsize));
+    const int64_t rows = s.ny * s.nz, rpc = (rows + nch - 1) / nch;
+    const dim3 grid((unsigned)(s.batch * nch));
+    if (g->dtype == GD_F32) {
+        if ((rc = forward<float>(s, (const float *)x, (float *)work, MUL_NONE, 0.0, st))) return rc;
+        hipLaunchKernelGGL(k_spectrum_part<float>, grid, dim3(256), ns * sizeof(double), st, (const float *)work, part,
+                           rows, rpc, nch, ns, s, kpow);
+    } else {
+        if ((rc = forward<double>(s, (const double *)x, (double *)work, MUL_NONE, 0.0, st))) return rc;
+        hipLaunchKernelGGL(k_spectrum_part<double>, grid, dim3(256), ns * sizeof(double), st, (const double *)work,
+                           part, rows, rpc, nch, ns, s, kpow);
+    }
+    const int64_t tot = s.batch * ns;
+    hipLaunchKernelGGL(k_spectrum_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, out, nch, ns,
+                       s.batch);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GD_OK : fail(GD_EHIP, "spectrum launch: %s", hipGetErrorString(e));
+}
+
+int pdf_counts(const gd_grid *g, double lo, double hi, int32_t nbins, const void *x, int64_t *counts, void *stream) {
+    int rc = gd::validate_grid(g);
+    if (rc) return rc;
+    if (!(lo < hi) || !std::isfinite(lo) || !std::isfinite(hi)) return fail(GD_EINVAL, "need finite lo < hi");
+    if (nbins < 1 || nbins > kMaxPdfBins) return fail(GD_EINVAL, "nbins must be in [1, %d]", kMaxPdfBins);
+    if (!x || !counts) return fail(GD_EINVAL, "x and counts must be non-NULL");
+    const int64_t npts = g->n[0] * g->n[1] * (g->ndim == 3 ? g->n[2] : 1);
+    const size_t tsize = g->dtype == GD_F32 ? 4 : 8;
+    if (overlap(x, (size_t)g->batch * npts * tsize, counts, (size_t)g->batch * nbins * 8))
+        return fail(GD_EINVAL, "counts overlaps x");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nc = g->batch * nbins;
+    hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, counts, nc);
+    const int64_t chunk = std::max<int64_t>(4096, (npts * g->batch + 2047) / 2048);
+    const int64_t nch = (npts + chunk - 1) / chunk;
+    const double scale = (double)nbins / (hi - lo);
+    const dim3 grid((unsigned)(g->batch * nch));
+    if (g->dtype == GD_F32)
+        hipLaunchKernelGGL(k_pdf<float>, grid, dim3(256), nbins * sizeof(unsigned), st, (const float *)x, counts, npts,
+                           chunk, nch, lo, hi, scale, nbins);
+    else
+        hipLaunchKernelGGL(k_pdf<double>, grid, dim3(256), nbins * sizeof(unsigned), st, (const double *)x, counts,
+                           npts, chunk, nch, lo, hi, scale, nbins);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GD_OK : fail(GD_EHIP, "pdf launch: %s", hipGetErrorString(e));
 }
 
 }  // extern "C"

@@ -81,7 +81,7 @@ EXPORTS = ["filter_apply", "deconvolve_workspace_bytes", "deconvolve_vancittert"
            "gd_last_launch", "gd_set_trace", "deconvolve_batch_workspace_bytes", "deconvolve_batch",
            "deconvolve_autotune", "deconvolve_batch_autotune", "gd_tune_reset", "gd_tune_set", "gd_tune_set_batch", "warmstart_param_count",
            "warmstart_workspace_bytes", "warmstart_forward", "warmstart_train_step", "closure_stress",
-           "germano_filter", "GermanoDeconvolver", "deconvolve_germano"]
+           "germano_filter", "GermanoDeconvolver", "deconvolve_germano", "energy_spectrum", "pdf_counts"]
 
 _lib = None
 
@@ -133,6 +133,14 @@ def load(path: str = LIB_PATH):
     lib.germano_filter_apply.restype = ctypes.c_int
     lib.deconvolve_germano.argtypes = [ctypes.c_int32, gp, ctypes.c_double, vp, vp, op, vp, ctypes.c_size_t, vp, vp]
     lib.deconvolve_germano.restype = ctypes.c_int
+    lib.spectrum_shells.argtypes = [gp]
+    lib.spectrum_shells.restype = ctypes.c_int32
+    lib.spectrum_workspace_bytes.argtypes = [gp]
+    lib.spectrum_workspace_bytes.restype = ctypes.c_size_t
+    lib.energy_spectrum.argtypes = [gp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.energy_spectrum.restype = ctypes.c_int
+    lib.pdf_counts.argtypes = [gp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp, vp]
+    lib.pdf_counts.restype = ctypes.c_int
     lib.closure_stress.argtypes = [gp, vp, vp, vp, vp]
     lib.closure_stress.restype = ctypes.c_int
     cp = ctypes.POINTER(Cnn)
@@ -304,6 +312,32 @@ def germano_filter(x: torch.Tensor, gamma: float, ndim: int = 2, out: torch.Tens
     _check(lib.germano_filter_apply(ctypes.byref(g), float(gamma), _dev_ptr(x), _dev_ptr(y), work.data_ptr(),
                                     work.numel(), _stream_handle(stream)))
     return y
+
+
+def energy_spectrum(x: torch.Tensor, ndim: int = 2, kpow: float = 0.0, stream=None) -> torch.Tensor:
+    """Shell-summed spectrum 1/2 sum_{|k| ~ s} |k|^kpow |f_hat(k)|^2 of every
+    field (energy_spectrum): a float64 tensor (..., nshells)."""
+    lib = load()
+    g = make_grid(x.shape, ndim, x.dtype)
+    ns = lib.spectrum_shells(ctypes.byref(g))
+    if ns == 0:
+        raise GdError(-1, "bad grid (spectra need power-of-two sizes)")
+    work = torch.empty(int(lib.spectrum_workspace_bytes(ctypes.byref(g))), dtype=torch.uint8, device=x.device)
+    out = torch.empty(tuple(x.shape[:-ndim]) + (ns,), dtype=torch.float64, device=x.device)
+    _check(lib.energy_spectrum(ctypes.byref(g), float(kpow), _dev_ptr(x), _dev_ptr(out), work.data_ptr(),
+                               work.numel(), _stream_handle(stream)))
+    return out
+
+
+def pdf_counts(x: torch.Tensor, lo: float, hi: float, nbins: int, ndim: int = 2, stream=None) -> torch.Tensor:
+    """Counts of every field's values in nbins equal bins over [lo, hi]
+    (pdf_counts): an int64 tensor (..., nbins)."""
+    lib = load()
+    g = make_grid(x.shape, ndim, x.dtype)
+    out = torch.empty(tuple(x.shape[:-ndim]) + (int(nbins),), dtype=torch.int64, device=x.device)
+    _check(lib.pdf_counts(ctypes.byref(g), float(lo), float(hi), int(nbins), _dev_ptr(x), _dev_ptr(out),
+                          _stream_handle(stream)))
+    return out
 
 
 class GermanoDeconvolver(Deconvolver):
