@@ -88,14 +88,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_solve_kernel_bicgstab
 CLOSURE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_closure_kernel.txt")
 
 
-def kernel_source_hash() -> str:
-    """sha256 over the solve kernel's sources (every library source except the
-    warm-start network's), the build script and the C header."""
-    import glob
+SOLVE_SOURCES = ["gd_device.h", "gd_kernels.h", "gd_ops.h", "gd_internal.h", "gd_inst.inc", "gd_api.hip",
+                 "gd_tune.hip"] + [f"gd_inst_{t}_{s}.hip" for t in ("f32", "f64") for s in ("vc", "cg", "bicgstab", "sd")]
+CLOSURE_SOURCES = ["gd_closure.hip"]
+
+
+def kernel_source_hash(sources=None) -> str:
+    """sha256 over a kernel's sources (by default the persistent solve
+    kernel's), the build script and the C header."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1707_09177_amd", "csrc")
-    files = sorted(f for f in glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))
-                   + glob.glob(os.path.join(csrc, "*.inc")) if os.path.basename(f) != "gd_cnn.hip")
+    files = [os.path.join(csrc, f) for f in (sources or SOLVE_SOURCES)]
     files += [os.path.join(csrc, "build.py"), os.path.join(ROOT, "include", "gdecon.h")]
     h = hashlib.sha256()
     for f in files:
@@ -105,7 +108,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(key: str, path: str = TRAFFIC_FILE):
+def measured_traffic(key: str, path: str = TRAFFIC_FILE, sources=None):
     """HBM bytes per launch of a kernel (the BiCGSTAB solve kernel by default)
     from a committed FETCH_SIZE / WRITE_SIZE summary, or None when the kernel
     sources have changed since those counters were taken (or no figure exists)."""
@@ -114,7 +117,7 @@ def measured_traffic(key: str, path: str = TRAFFIC_FILE):
             kv = dict(line.split(" = ", 1) for line in fh.read().splitlines() if " = " in line)
     except OSError:
         return None
-    if kv.get("kernel_sources_sha256", "").strip() != kernel_source_hash():
+    if kv.get("kernel_sources_sha256", "").strip() != kernel_source_hash(sources):
         return None
     v = kv.get(f"traffic_bytes[{key}]")
     return float(v) if v is not None else None
@@ -276,7 +279,7 @@ def main_closure(args, w, torch, gd, dev):
         "config": {"workload": w["desc"], "velocity_fields": vel.shape[0], "grid": [w["n"]] * nd, "points": npts,
                    "pairs": nd * (nd + 1) // 2},
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(w["key"], CLOSURE_TRAFFIC_FILE), "kernel": f"k_closure<float,{nd}>",
+                     "traffic": measured_traffic(w["key"], CLOSURE_TRAFFIC_FILE, CLOSURE_SOURCES), "kernel": f"k_closure<float,{nd}>",
                      "bytes_per_launch": algo},
         "closure_ms_min": ms_cl_min,
         "chain": {"ms": ms_chain, "points_per_s": npts / (ms_chain * 1e-3),
