@@ -318,6 +318,7 @@ def main_germano(args, w, torch, gd, dev):
     for s in args.solvers.split(","):
         d = gd.GermanoDeconvolver(ubar.shape, nd, ubar.dtype, s, gamma, device=dev)
         out = torch.empty_like(ubar)
+        tuned = d.autotune(ubar, out) if not args.no_tune else None   # untimed
         reps = args.steps if s == "bicgstab" else max(2, args.steps // (10 if s in ("vc", "sd") else 2))
         for _ in range(args.warmup):
             d.solve(ubar, 5000, tol, out=out)
@@ -339,7 +340,7 @@ def main_germano(args, w, torch, gd, dev):
         launch = gd.last_launch()
         results[s] = dict(ms=ms, iters=sorted(set(iters)), status=sorted({i["status_name"] for i in info}),
                           worst_true_rel_residual=max(i["r_true"] / i["r_ref"] for i in info),
-                          points_per_s=npts / (ms * 1e-3), solve_kernel_bytes=algo, launch=launch)
+                          points_per_s=npts / (ms * 1e-3), solve_kernel_bytes=algo, launch=launch, tune=tuned)
         del d, out
     # the paper's spectral assessment (its N = 5 comparison): the highest shell up to
     # which the recovered energy spectrum keeps at least half of the true one

@@ -335,6 +335,11 @@ int germano_filter_apply(const gd_grid *grid, double gamma, const void *x, void 
                          void *stream);
 int deconvolve_germano(int32_t solver, const gd_grid *grid, double gamma, const void *ubar, void *u,
                        const gd_opts *opts, void *work, size_t work_bytes, gd_info *info, void *stream);
+/* As deconvolve_autotune, for deconvolve_germano with this grid and solver:
+ * times the launch configurations of the solve on the Fourier coefficients
+ * of ubar and remembers the fastest (u is overwritten).  Synchronous. */
+int deconvolve_germano_autotune(int32_t solver, const gd_grid *grid, double gamma, const void *ubar, void *u,
+                                void *work, size_t work_bytes, gd_info *info, void *stream, gd_tune_info *out);
 
 /*
  * ---- A-priori diagnostics -------------------------------------------------------

@@ -414,7 +414,7 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
     const bool aligned = ((uintptr_t)ubar % 16 == 0) && ((uintptr_t)u % 16 == 0);
     TuneCfg cfg;
     if (force) cfg = *force;
-    else tune_lookup(key_uniform(solver, g, aligned), &cfg);
+    else tune_lookup(key_uniform(solver, g, aligned) + (spec ? ":spec" : ""), &cfg);
     TileShape ts = choose_tiles(g->ndim, nx, ny, nz, g->batch, (int)tsize, aligned, solver, false);
     if (g->ndim == 3 && cfg.rows > 0 && variant_ok((int)tsize, 3, ts.vw, cfg.rows) && (cfg.rows == 1 || ny >= cfg.rows))
         ts.R = cfg.rows;
@@ -796,6 +796,42 @@ gd_opts trial_opts(int solver) {
 const int kTpwCands[] = {kTilesPerWave, 1, 3, 4, 6};
 const int kTailCands[] = {kTailPct, 0, 25};
 
+// Time the launch configurations of a uniform solve (on a stored spectrum
+// when `spec` is set) and remember the fastest.
+int tune_uniform(int solver, const gd_grid *g, const void *ubar, void *u, void *work, size_t wb, gd_info *info,
+                 void *stream, gd_tune_info *out, const SpecParams *spec) {
+    int rc = validate_grid(g);
+    if (rc) return rc;
+    if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
+    const gd_opts o = trial_opts(solver);
+    std::vector<TuneCfg> cands;
+    std::vector<int> rows = {0};
+    if (g->ndim == 3 && !spec) rows = {0, 1, 2, 4};
+    for (int r : rows)
+        for (int t : kTpwCands)
+            for (int tl : kTailCands)
+                for (int il = 0; il < 2; ++il)
+                    for (int wc = 0; wc < 2; ++wc) {
+                        TuneCfg c;
+                        c.tpw = t;
+                        c.rows = r;
+                        c.tail = tl;
+                        c.ilv = il;
+                        c.wc = wc;
+                        cands.push_back(c);
+                    }
+    // every candidate must launch; a shape the field cannot use falls back to
+    // the default rule inside solve_uniform, so duplicates are harmless
+    auto launch = [&](const TuneCfg &c) {
+        return solve_uniform(solver, g, ubar, u, &o, work, wb, info, stream, &c, spec);
+    };
+    const int best = time_candidates(cands, launch, (hipStream_t)stream, out);
+    if (best < 0) return best;
+    const bool aligned = ((uintptr_t)ubar % 16 == 0) && ((uintptr_t)u % 16 == 0);
+    tune_store(key_uniform(solver, g, aligned) + (spec ? ":spec" : ""), cands[best]);
+    return GD_OK;
+}
+
 }  // namespace gd
 
 using namespace gd;
@@ -877,34 +913,7 @@ int deconvolve_batch(int32_t solver, int32_t dtype, const gd_instance *list, int
 
 int deconvolve_autotune(int32_t solver, const gd_grid *g, const void *ubar, void *u, void *work, size_t wb,
                         gd_info *info, void *stream, gd_tune_info *out) {
-    int rc = validate_grid(g);
-    if (rc) return rc;
-    if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
-    const gd_opts o = trial_opts(solver);
-    std::vector<TuneCfg> cands;
-    std::vector<int> rows = {0};
-    if (g->ndim == 3) rows = {0, 1, 2, 4};
-    for (int r : rows)
-        for (int t : kTpwCands)
-            for (int tl : kTailCands)
-                for (int il = 0; il < 2; ++il)
-                    for (int wc = 0; wc < 2; ++wc) {
-                        TuneCfg c;
-                        c.tpw = t;
-                        c.rows = r;
-                        c.tail = tl;
-                        c.ilv = il;
-                        c.wc = wc;
-                        cands.push_back(c);
-                    }
-    // every candidate must launch; a shape the field cannot use falls back to
-    // the default rule inside solve_uniform, so duplicates are harmless
-    auto launch = [&](const TuneCfg &c) { return solve_uniform(solver, g, ubar, u, &o, work, wb, info, stream, &c, nullptr); };
-    const int best = time_candidates(cands, launch, (hipStream_t)stream, out);
-    if (best < 0) return best;
-    const bool aligned = ((uintptr_t)ubar % 16 == 0) && ((uintptr_t)u % 16 == 0);
-    tune_store(key_uniform(solver, g, aligned), cands[best]);
-    return GD_OK;
+    return tune_uniform(solver, g, ubar, u, work, wb, info, stream, out, nullptr);
 }
 
 int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count, void *work,

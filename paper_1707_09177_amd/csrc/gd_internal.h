@@ -198,6 +198,8 @@ const void *filter_kernel_ptr(int dtype, int variant);
 Geo make_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int vw, int R, int64_t L, int tail_pct);
 int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *work,
                   size_t work_bytes, gd_info *info, void *stream, const TuneCfg *force, const SpecParams *spec);
+int tune_uniform(int solver, const gd_grid *g, const void *ubar, void *u, void *work, size_t wb, gd_info *info,
+                 void *stream, gd_tune_info *out, const SpecParams *spec);
 int validate_grid(const gd_grid *g);
 int validate_opts(const gd_opts *o);
 void set_error_text(const char *msg);

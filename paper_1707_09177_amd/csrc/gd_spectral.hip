@@ -634,11 +634,35 @@ int deconvolve_germano(int32_t solver, const gd_grid *g, double gamma, const voi
     gd::SpecParams sp;
     sp.inv_kc2 = ik;
     sp.nxc = s.nxc;
-    gd::TuneCfg cfg;
-    rc = gd::solve_uniform(solver, &v, UB, U, o, solve_work, wb - 2 * sb, info, stream, &cfg, &sp);
+    rc = gd::solve_uniform(solver, &v, UB, U, o, solve_work, wb - 2 * sb, info, stream, nullptr, &sp);
     if (rc) return rc;
     return f32 ? inverse<float>(s, (float *)U, (float *)u, MUL_INV_CN, ik, st)
                : inverse<double>(s, (double *)U, (double *)u, MUL_INV_CN, ik, st);
+}
+
+int deconvolve_germano_autotune(int32_t solver, const gd_grid *g, double gamma, const void *ubar, void *u, void *work,
+                                size_t wb, gd_info *info, void *stream, gd_tune_info *out) {
+    int rc = validate_spec_grid(g);
+    if (rc) return rc;
+    if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(GD_EINVAL, "gamma must be positive");
+    if (!ubar || !u || !info) return fail(GD_EINVAL, "ubar, u and info must be non-NULL");
+    if (!work || (uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be non-NULL and 256-byte aligned");
+    const size_t need = germano_workspace_bytes(g, solver);
+    if (wb < need) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", need, wb);
+    const Spec s = spec_of(g);
+    const size_t sb = align256((size_t)s.elems * s.tsize);
+    char *w = (char *)work;
+    const double ik = inv_kc2_of(g, gamma);
+    hipStream_t st = (hipStream_t)stream;
+    rc = g->dtype == GD_F32 ? forward<float>(s, (const float *)ubar, (float *)w, MUL_C, ik, st)
+                            : forward<double>(s, (const double *)ubar, (double *)w, MUL_C, ik, st);
+    if (rc) return rc;
+    const gd_grid v = spectral_grid(g, s);
+    gd::SpecParams sp;
+    sp.inv_kc2 = ik;
+    sp.nxc = s.nxc;
+    return gd::tune_uniform(solver, &v, w, w + sb, w + 2 * sb, wb - 2 * sb, info, stream, out, &sp);
 }
 
 int32_t spectrum_shells(const gd_grid *g) {

@@ -133,6 +133,9 @@ def load(path: str = LIB_PATH):
     lib.germano_filter_apply.restype = ctypes.c_int
     lib.deconvolve_germano.argtypes = [ctypes.c_int32, gp, ctypes.c_double, vp, vp, op, vp, ctypes.c_size_t, vp, vp]
     lib.deconvolve_germano.restype = ctypes.c_int
+    lib.deconvolve_germano_autotune.argtypes = [ctypes.c_int32, gp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp,
+                                                vp, ctypes.POINTER(TuneInfo)]
+    lib.deconvolve_germano_autotune.restype = ctypes.c_int
     lib.spectrum_shells.argtypes = [gp]
     lib.spectrum_shells.restype = ctypes.c_int32
     lib.spectrum_workspace_bytes.argtypes = [gp]
@@ -365,6 +368,17 @@ class GermanoDeconvolver(Deconvolver):
         def call(grid, ub, u, o, work, wb, info, stream):
             return fn(code, grid, self.gamma, ub, u, o, work, wb, info, stream)
         self._fn = call
+
+    def autotune(self, ubar: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> dict:
+        """Time the launch configurations on these buffers and keep the
+        fastest for later solves of this shape (deconvolve_germano_autotune)."""
+        u = torch.empty_like(ubar) if out is None else out
+        t = TuneInfo()
+        _check(self.lib.deconvolve_germano_autotune(SOLVERS[self.solver], ctypes.byref(self.grid), self.gamma,
+                                                    _dev_ptr(ubar), _dev_ptr(u), self.work.data_ptr(),
+                                                    self.work.numel(), self.info_dev.data_ptr(),
+                                                    _stream_handle(stream), ctypes.byref(t)))
+        return _tune_dict(t)
 
 
 def deconvolve_germano(solver: str, ubar: torch.Tensor, max_iter: int, gamma: float, tol: float = 0.0,

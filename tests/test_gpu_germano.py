@@ -158,3 +158,21 @@ def test_paper_setting_2048sq_fp32_bench_batch():
     gcg, icg, _ = gdecon.deconvolve_germano("cg", dub[:1].contiguous(), 200, 0.01, tol=1e-2)
     want, _, _ = oracle.solve("cg", ub[0], 2, icg[0]["iters"], gamma=0.01)
     assert rel_l2(gcg[0].double().cpu().numpy(), want) <= 10 * kappa * 6e-8
+
+
+@pytest.mark.parametrize("solver", ["bicgstab", "vc"])
+def test_autotuned_solve_matches_oracle(solver):
+    """The tuner's launch choice changes the tile schedule only: the tuned
+    solve still matches the oracle."""
+    shape, gamma = (64, 128), 0.3
+    u = rand((3,) + shape, 50)
+    ub = oracle.germano_filter(u, 2, gamma)
+    dub = to_dev(ub, torch.float64)
+    d = gdecon.GermanoDeconvolver(dub.shape, 2, dub.dtype, solver, gamma)
+    t = d.autotune(dub)
+    assert t["candidates"] > 1 and 0 <= t["best"] < t["candidates"]
+    res = d.solve(dub, 6)
+    torch.cuda.synchronize()
+    want, _, _ = oracle.solve(solver, ub, 2, 6, gamma=gamma)
+    for e in rel_l2_per_field(res.u.cpu().numpy(), want, 2):
+        assert e <= 1e-10
