@@ -314,6 +314,11 @@ def main_germano(args, w, torch, gd, dev):
     del ut
     npts = int(ubar.numel())
     stream = torch.cuda.current_stream()
+    if args.tune_only:
+        for s in args.solvers.split(","):
+            d = gd.GermanoDeconvolver(ubar.shape, nd, ubar.dtype, s, gamma, device=dev)
+            print(json.dumps({"solver": s, "tune": d.autotune(ubar)}))
+        return
     results = {}
     for s in args.solvers.split(","):
         d = gd.GermanoDeconvolver(ubar.shape, nd, ubar.dtype, s, gamma, device=dev)
