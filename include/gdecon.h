@@ -303,6 +303,25 @@ int warmstart_train_step(const gd_cnn *net, const gd_grid *grid, const void *uba
                          size_t work_bytes, double *loss, void *stream);
 
 /*
+ * ---- Van Cittert with several passes per sweep ----------------------------------
+ *
+ * Algorithm 1 with the trapezoidal stencil, computed K passes at a time
+ * (temporal blocking): a tile of r with a K-point halo is advanced K passes in
+ * LDS while u accumulates the residuals, so one read and one write of u and r
+ * serve K passes.  Arguments, options, results and info records are those of
+ * deconvolve_vancittert.  The stopping rule acts after every pass: a field
+ * that stops inside a sweep has that sweep recomputed with the exact pass
+ * count, so pass counts, statuses and histories match the one-pass solve.
+ * Any grid size.  vancittert_blocked_passes() gives K (8 in 2D, 2 in 3D).
+ * The call is a sequence of ceil(max_iter / K) + 4 stream-ordered launches;
+ * a launch after every field has stopped costs one state read per tile.
+ */
+size_t vancittert_blocked_workspace_bytes(const gd_grid *grid);
+int32_t vancittert_blocked_passes(const gd_grid *grid);
+int deconvolve_vancittert_blocked(const gd_grid *grid, const void *ubar, void *u, const gd_opts *opts, void *work,
+                                  size_t work_bytes, gd_info *info, void *stream);
+
+/*
  * ---- The paper's differential filter ----------------------------------------
  *
  * The results section filters with G = (I - delta^2 lap)^-1 (Sec. 4, Eq. df),

@@ -201,6 +201,7 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
 int tune_uniform(int solver, const gd_grid *g, const void *ubar, void *u, void *work, size_t wb, gd_info *info,
                  void *stream, gd_tune_info *out, const SpecParams *spec);
 int validate_grid(const gd_grid *g);
+double grid_weight(const gd_grid *g);
 int validate_opts(const gd_opts *o);
 void set_error_text(const char *msg);
 int64_t geo_tiles(const Geo &g);

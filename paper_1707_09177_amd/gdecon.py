@@ -81,7 +81,7 @@ EXPORTS = ["filter_apply", "deconvolve_workspace_bytes", "deconvolve_vancittert"
            "gd_last_launch", "gd_set_trace", "deconvolve_batch_workspace_bytes", "deconvolve_batch",
            "deconvolve_autotune", "deconvolve_batch_autotune", "gd_tune_reset", "gd_tune_set", "gd_tune_set_batch", "warmstart_param_count",
            "warmstart_workspace_bytes", "warmstart_forward", "warmstart_train_step", "closure_stress",
-           "germano_filter", "GermanoDeconvolver", "deconvolve_germano", "energy_spectrum", "pdf_counts"]
+           "germano_filter", "GermanoDeconvolver", "deconvolve_germano", "energy_spectrum", "pdf_counts", "BlockedVanCittert"]
 
 _lib = None
 
@@ -127,6 +127,12 @@ def load(path: str = LIB_PATH):
     lib.gd_tune_set.restype = ctypes.c_int
     lib.gd_tune_set_batch.argtypes = [i32, i32, ip, i32, tp]
     lib.gd_tune_set_batch.restype = ctypes.c_int
+    lib.vancittert_blocked_workspace_bytes.argtypes = [gp]
+    lib.vancittert_blocked_workspace_bytes.restype = ctypes.c_size_t
+    lib.vancittert_blocked_passes.argtypes = [gp]
+    lib.vancittert_blocked_passes.restype = ctypes.c_int32
+    lib.deconvolve_vancittert_blocked.argtypes = [gp, vp, vp, op, vp, ctypes.c_size_t, vp, vp]
+    lib.deconvolve_vancittert_blocked.restype = ctypes.c_int
     lib.germano_workspace_bytes.argtypes = [gp, ctypes.c_int32]
     lib.germano_workspace_bytes.restype = ctypes.c_size_t
     lib.germano_filter_apply.argtypes = [gp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
@@ -341,6 +347,28 @@ def pdf_counts(x: torch.Tensor, lo: float, hi: float, nbins: int, ndim: int = 2,
     _check(lib.pdf_counts(ctypes.byref(g), float(lo), float(hi), int(nbins), _dev_ptr(x), _dev_ptr(out),
                           _stream_handle(stream)))
     return out
+
+
+class BlockedVanCittert(Deconvolver):
+    """Van Cittert with several passes per sweep (deconvolve_vancittert_blocked):
+    same results as the "vc" solver, less memory traffic."""
+
+    def __init__(self, field_shape, ndim: int, dtype: torch.dtype, device=None, h=None):
+        self.lib = load()
+        self.shape = tuple(field_shape)
+        self.ndim = ndim
+        self.dtype = dtype
+        self.solver = "vcb"
+        self.grid = make_grid(self.shape, ndim, dtype, h)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        n = self.lib.vancittert_blocked_workspace_bytes(ctypes.byref(self.grid))
+        if n == 0:
+            raise GdError(-1, "bad grid")
+        self.work = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        self.batch = int(self.grid.batch)
+        self.info_dev = torch.zeros(self.batch * INFO_BYTES, dtype=torch.uint8, device=self.device)
+        self.passes_per_sweep = int(self.lib.vancittert_blocked_passes(ctypes.byref(self.grid)))
+        self._fn = self.lib.deconvolve_vancittert_blocked
 
 
 class GermanoDeconvolver(Deconvolver):
