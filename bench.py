@@ -195,7 +195,7 @@ def main_batch(args, w, torch, gd, dev):
     npts = int(sum(int(np.prod(s)) for s in shapes))
     itemsize = ubars[0].element_size()
     results = {}
-    for s in args.solvers.split(","):
+    for s in [x for x in args.solvers.split(",") if x != "vcb"]:   # uneven batches: the persistent solvers
         r = time_batch(gd, torch, shapes, ubars, s, args.steps if s == "bicgstab" else max(3, args.steps // 2),
                        args.warmup)
         iters = [i["iters"] for i in r["info"]]
@@ -535,9 +535,13 @@ def warm_3d(gd, torch, dev, synth, timed, args, n_train=64, n_eval=128, count_ev
 
 
 def time_solver(gd, torch, ubar, w, solver, steps, warmup, tol=1e-6, max_iter=500, tune=True):
-    d = gd.Deconvolver(ubar.shape, w["ndim"], ubar.dtype, solver)
     out = torch.empty_like(ubar)
-    tuned = gd.autotune(solver, ubar, ndim=w["ndim"], out=out) if tune else None   # first-call tuning, untimed
+    if solver == "vcb":  # Van Cittert with several passes per sweep
+        d = gd.BlockedVanCittert(ubar.shape, w["ndim"], ubar.dtype)
+        tuned = None
+    else:
+        d = gd.Deconvolver(ubar.shape, w["ndim"], ubar.dtype, solver)
+        tuned = gd.autotune(solver, ubar, ndim=w["ndim"], out=out) if tune else None   # first-call tuning, untimed
     for _ in range(warmup):
         d.solve(ubar, max_iter, tol, out=out)
     torch.cuda.synchronize()
@@ -584,7 +588,8 @@ def main():
     ap.add_argument("--tune-only", action="store_true",
                     help="run the autotuner for the workload's solvers and exit (with GD_TUNE_CACHE set, the "
                          "choices are saved for later --no-tune runs, e.g. under a profiler)")
-    ap.add_argument("--solvers", default="bicgstab,cg,vc")
+    ap.add_argument("--solvers", default="bicgstab,cg,vc,vcb",
+                    help="vcb: Van Cittert with several passes per sweep (same iterates, less traffic)")
     ap.add_argument("--train-steps", type=int, default=1500, help="warm-start workload: Adam steps")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (x5): the reference kernel that scales "
@@ -617,12 +622,12 @@ def main():
     if w.get("closure"):
         return main_closure(args, w, torch, gd, dev)
     if w.get("germano"):
-        if args.solvers == "bicgstab,cg,vc":
+        if args.solvers == "bicgstab,cg,vc,vcb":
             args.solvers = "bicgstab,cg,sd,vc"
         return main_germano(args, w, torch, gd, dev)
     u32, ubar = make_inputs(w, torch, gd, dev)
     if args.tune_only:
-        for s in args.solvers.split(","):
+        for s in [x for x in args.solvers.split(",") if x != "vcb"]:   # vcb has no launch choices
             print(json.dumps({"solver": s, "tune": gd.autotune(s, ubar, ndim=w["ndim"])}))
         return
     npts = int(ubar.numel())
@@ -635,7 +640,7 @@ def main():
         iters = [i["iters"] for i in r["info"]]
         st = {i["status_name"] for i in r["info"]}
         worst_true = max(i["r_true"] / i["r_ref"] for i in r["info"])
-        acc = accesses(s, max(iters))
+        acc = accesses("vc" if s == "vcb" else s, max(iters))   # vcb: the one-pass solve's accesses, for comparison
         gbs = npts * itemsize * acc / (r["ms_events"] * 1e-3) / 1e9
         results[s] = dict(ms=r["ms_events"], ms_min=r["ms_min"], wall_ms=r["wall_ms"], iters=iters,
                           status=sorted(st), worst_true_rel_residual=worst_true,
@@ -672,6 +677,8 @@ def main():
     }
     if "vc" in results and main_s != "vc":
         out["vs_vancittert"] = results["vc"]["ms"] / m["ms"]
+    if "vcb" in results and main_s != "vcb":
+        out["vs_vancittert_blocked"] = results["vcb"]["ms"] / m["ms"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, u32)
     print(json.dumps(out))

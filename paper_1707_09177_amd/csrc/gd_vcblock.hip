@@ -9,8 +9,8 @@
 // sweep reads r (with its halo) and u, and writes r and u: about 4 + halo
 // field accesses for K passes, against 4 K for one pass per sweep.
 //
-// The stopping rule still acts after every pass.  The last tile of a field
-// to finish a sweep sums the K partial norms per pass in tile order and
+// The stopping rule still acts after every pass.  After each sweep launch a
+// small kernel sums every field's K partial norms per pass in tile order and
 // applies the rule pass by pass.  When the field stops at pass j < K inside
 // the sweep, the sweep is redone from its inputs with j passes: u and r
 // ping-pong between two buffer sets, and later sweeps skip a finished field,
@@ -39,10 +39,14 @@ int fail(int code, const char *fmt, ...) {
 }
 
 // Tile shapes: interior TX x TY (x TZ) and K passes per sweep, sized so that
-// two LDS copies of the tile with its halo fit in 64 KB.
+// two LDS copies of the tile with its halo fit in 64 KB and a halo row
+// (TX + 2K points) is a whole number of 64-lane waves.
 template <typename T, int NDIM> struct Shape;
-template <typename T> struct Shape<T, 2> {
-    static constexpr int TX = 64, TY = 32, TZ = 1, K = 8;
+template <> struct Shape<float, 2> {
+    static constexpr int TX = 112, TY = 32, TZ = 1, K = 8;
+};
+template <> struct Shape<double, 2> {
+    static constexpr int TX = 48, TY = 32, TZ = 1, K = 8;
 };
 template <> struct Shape<float, 3> {
     static constexpr int TX = 32, TY = 8, TZ = 8, K = 2;
@@ -57,10 +61,16 @@ struct alignas(128) VState {
     double r_ref, r0, r_last;
     int32_t iters, status, done, redo;  // redo: passes of the sweep to recompute
     int32_t parity;                     // buffer set holding the current u, r
-    uint32_t cnt;                       // tiles of the current launch that have finished
+    uint32_t pad;
+};
+
+// fields still iterating (the sweeps' fast exit) and fields with a sweep to recompute
+struct alignas(128) Global {
+    int32_t active, redo;
 };
 
 struct Args {
+    Global *glob;
     const void *ubar;
     void *u[2], *r[2];
     double *part;     // [field][tile][kMaxK + 1]
@@ -74,9 +84,11 @@ struct Args {
     int32_t max_iter, init, norm_ref, steps;
 };
 
+// periodic index; the common case (already in range) takes no division
 __device__ __forceinline__ int64_t wrapi(int64_t v, int64_t n) {
-    v %= n;
-    return v < 0 ? v + n : v;
+    if (v >= 0 && v < n) return v;
+    const int64_t m = (int64_t)((int32_t)v % (int32_t)n);  // |v| < 2^31 for every field accepted
+    return m < 0 ? m + n : m;
 }
 
 // Tile t of a field: origin and which interior points lie in the field.
@@ -91,38 +103,42 @@ __device__ __forceinline__ TileOrg tile_org(const Args &A, int64_t t, int TX, in
     return o;
 }
 
-// Load a field region [x0-h, x0+TX+h) x ... (periodic) into LDS, x fastest.
-template <typename T, int NDIM>
-__device__ __forceinline__ void load_region(T *dst, const T *src, const Args &A, const TileOrg &o, int h, int RX, int RY,
-                                            int RZ) {
-    const int n = RX * RY * RZ;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        const int ix = i % RX, iy = (i / RX) % RY, iz = i / (RX * RY);
-        const int64_t gx = wrapi(o.x0 + ix - h, A.nx), gy = wrapi(o.y0 + iy - h, A.ny);
+// Load a field region [x0-h, x0+TX+h) x ... (periodic) into LDS, x fastest:
+// a wave per row, lanes along x.
+template <typename T, int NDIM, int RX, int RY, int RZ>
+__device__ __forceinline__ void load_region(T *dst, const T *src, const Args &A, const TileOrg &o, int h) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int row = wave; row < RY * RZ; row += 4) {
+        const int iy = row % RY, iz = row / RY;
+        const int64_t gy = wrapi(o.y0 + iy - h, A.ny);
         const int64_t gz = NDIM == 3 ? wrapi(o.z0 + iz - h, A.nz) : 0;
-        dst[i] = src[(gz * A.ny + gy) * A.nx + gx];
+        const T *srow = src + (gz * A.ny + gy) * A.nx;
+        T *drow = dst + row * RX;
+        for (int ix = lane; ix < RX; ix += 64) drow[ix] = srow[wrapi(o.x0 + ix - h, A.nx)];
     }
 }
 
-// y = x - G x on the region shrunk by s points per side (region extent R* in
-// the LDS layout of extent R*, halo h), reading x, writing y.
-template <typename T, int NDIM>
-__device__ __forceinline__ void step(const T *x, T *y, int s, int RX, int RY, int RZ) {
-    const int ex = RX - 2 * s, ey = RY - 2 * s, ez = NDIM == 3 ? RZ - 2 * s : 1;
-    const int n = ex * ey * ez;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        const int ix = i % ex + s, iy = (i / ex) % ey + s, iz = NDIM == 3 ? i / (ex * ey) + s : 0;
-        const int c = (iz * RY + iy) * RX + ix;
-        auto row = [&](int off) {
-            const T *p = x + c + off;
-            return T(0.5) * p[0] + T(0.25) * (p[-1] + p[1]);
-        };
-        auto plane = [&](int off) { return T(0.5) * row(off) + T(0.25) * (row(off - RX) + row(off + RX)); };
-        T g;
-        if constexpr (NDIM == 2) g = plane(0);
-        else g = T(0.5) * plane(0) + T(0.25) * (plane(-RX * RY) + plane(RX * RY));
-        y[c] = x[c] - g;
-    }
+// y = x - G x on the region shrunk by s points per side, reading x, writing y
+// (a wave per row, lanes along x).
+template <typename T, int NDIM, int RX, int RY, int RZ>
+__device__ __forceinline__ void step(const T *x, T *y, int s) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int zlo = NDIM == 3 ? s : 0, zhi = NDIM == 3 ? RZ - s : 1;
+    const int ny = RY - 2 * s;
+    for (int iz = zlo; iz < zhi; ++iz)
+        for (int iy = s + wave; iy < s + ny; iy += 4)
+            for (int ix = s + lane; ix < RX - s; ix += 64) {
+                const int c = (iz * RY + iy) * RX + ix;
+                auto row = [&](int off) {
+                    const T *p = x + c + off;
+                    return T(0.5) * p[0] + T(0.25) * (p[-1] + p[1]);
+                };
+                auto plane = [&](int off) { return T(0.5) * row(off) + T(0.25) * (row(off - RX) + row(off + RX)); };
+                T g;
+                if constexpr (NDIM == 2) g = plane(0);
+                else g = T(0.5) * plane(0) + T(0.25) * (plane(-RX * RY) + plane(RX * RY));
+                y[c] = x[c] - g;
+            }
 }
 
 __device__ __forceinline__ double block_sum(double v, double *red) {
@@ -134,21 +150,6 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     const double s = (red[0] + red[1]) + (red[2] + red[3]);
     __syncthreads();
     return s;
-}
-
-// The last tile of a field to finish: returns true in that workgroup.
-__device__ __forceinline__ bool last_tile(VState *st, int64_t tiles, int *flag) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = __hip_atomic_fetch_add(&st->cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        *flag = prev + 1 == (uint32_t)tiles;
-        if (*flag) __hip_atomic_store(&st->cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    const bool last = *flag != 0;
-    if (last) __threadfence();
-    return last;
 }
 
 // sums over the field's tiles, in tile order per thread, then threads in order
@@ -182,17 +183,16 @@ __global__ __launch_bounds__(256) void k_vcb_init(Args A) {
     constexpr int RX = S::TX + 2, RY = S::TY + 2, RZ = NDIM == 3 ? S::TZ + 2 : 1;
     __shared__ T a[RX * RY * RZ], b[RX * RY * RZ];
     __shared__ double red[4];
-    __shared__ int flag;
     const int64_t f = blockIdx.x / A.tiles, t = blockIdx.x % A.tiles;
     const T *ub = static_cast<const T *>(A.ubar) + f * A.npts;
     T *u = static_cast<T *>(A.u[0]) + f * A.npts;
     T *r = static_cast<T *>(A.r[0]) + f * A.npts;
     const TileOrg o = tile_org(A, t, S::TX, S::TY, S::TZ);
     // G u0 over the interior (u0 = ubar, 0 or the caller's u)
-    if (A.init == GD_INIT_GIVEN) load_region<T, NDIM>(a, u, A, o, 1, RX, RY, RZ);
-    else load_region<T, NDIM>(a, ub, A, o, 1, RX, RY, RZ);
+    if (A.init == GD_INIT_GIVEN) load_region<T, NDIM, RX, RY, RZ>(a, u, A, o, 1);
+    else load_region<T, NDIM, RX, RY, RZ>(a, ub, A, o, 1);
     __syncthreads();
-    step<T, NDIM>(a, b, 1, RX, RY, RZ);  // b = a - G a
+    step<T, NDIM, RX, RY, RZ>(a, b, 1);  // b = a - G a
     __syncthreads();
     double rr = 0.0, rf = 0.0;
     constexpr int NI = S::TX * S::TY * S::TZ;
@@ -221,9 +221,9 @@ __global__ __launch_bounds__(256) void k_vcb_init(Args A) {
     if (A.norm_ref == GD_REF_R0UBAR && A.init == GD_INIT_GIVEN) {
         // a held u0: recompute ubar - G ubar for the reference norm
         __syncthreads();
-        load_region<T, NDIM>(a, ub, A, o, 1, RX, RY, RZ);
+        load_region<T, NDIM, RX, RY, RZ>(a, ub, A, o, 1);
         __syncthreads();
-        step<T, NDIM>(a, b, 1, RX, RY, RZ);
+        step<T, NDIM, RX, RY, RZ>(a, b, 1);
         __syncthreads();
         rf = 0.0;
         for (int i = threadIdx.x; i < NI; i += 256) {
@@ -239,34 +239,36 @@ __global__ __launch_bounds__(256) void k_vcb_init(Args A) {
         pp[0] = srr;
         pp[1] = srf;
     }
+}
+
+// Per field, after the init launch: r0, the reference norm, the guards and the
+// stopping rule at pass 0.  One workgroup per field; partials summed in tile order.
+__global__ __launch_bounds__(256) void k_vcb_init_reduce(Args A) {
+    __shared__ double red[4];
+    const int64_t f = blockIdx.x;
     VState *st = A.st + f;
-    if (!last_tile(st, A.tiles, &flag)) return;
     const double r0sq = field_sum(A.part + f * A.tiles * (kMaxK + 1), A.tiles, 0, red);
     const double rfsq = field_sum(A.part + f * A.tiles * (kMaxK + 1), A.tiles, 1, red);
-    if (threadIdx.x == 0) {
-        const double r0 = sqrt(r0sq);
-        const double r_ref = (A.norm_ref == GD_REF_R0UBAR && A.init == GD_INIT_UBAR) ? r0 : sqrt(rfsq);
-        // the spacing weight h^d scales every norm alike; it is applied by the host to the reported norms
-        st->r0 = r0;
-        st->r_ref = r_ref;
-        st->r_last = r0;
-        st->iters = 0;
-        st->parity = 0;
-        st->redo = 0;
-        int status = GD_MAXITER, done;
-        if (!isfinite(r_ref)) {
-            status = GD_NONFINITE;
-            done = 1;
-        } else if (r_ref == 0.0) {
-            status = GD_ZERO_REF;
-            done = 1;
-        } else {
-            done = stop_rule(r0, A.tol, r_ref, 0, A.max_iter, &status);
-        }
-        st->status = status;
-        st->done = done;
-        if (A.hist) A.hist[f * (A.max_iter + 1)] = r0;
+    if (threadIdx.x != 0) return;
+    const double r0 = sqrt(r0sq);
+    const double r_ref = (A.norm_ref == GD_REF_R0UBAR && A.init == GD_INIT_UBAR) ? r0 : sqrt(rfsq);
+    st->r0 = r0;
+    st->r_ref = r_ref;
+    st->r_last = r0;
+    int status = GD_MAXITER, done;
+    if (!isfinite(r_ref)) {
+        status = GD_NONFINITE;
+        done = 1;
+    } else if (r_ref == 0.0) {
+        status = GD_ZERO_REF;
+        done = 1;
+    } else {
+        done = stop_rule(r0, A.tol, r_ref, 0, A.max_iter, &status);
     }
+    st->status = status;
+    st->done = done;
+    if (done) atomicAdd(&A.glob->active, -1);
+    if (A.hist) A.hist[f * (A.max_iter + 1)] = r0;
 }
 
 // One sweep of up to K passes over every tile (REDO: recompute a stopped
@@ -282,20 +284,25 @@ __global__ __launch_bounds__(256) void k_vcb_sweep(Args A) {
     constexpr int PER = (NI + 255) / 256;  // interior points per thread
     __shared__ T a[RX * RY * RZ], b[RX * RY * RZ];
     __shared__ double red[4];
-    __shared__ int flag, skip, passes, par;
+    __shared__ int skip, passes, par, any;
+    // the state is only written between launches (by the reduction kernels)
+    if (threadIdx.x == 0) any = REDO ? A.glob->redo : A.glob->active;
+    __syncthreads();
+    if (any <= 0) return;  // every field has stopped (or nothing to recompute)
+    int64_t fcur = -1;
     for (int64_t bt = blockIdx.x; bt < A.nfields * A.tiles; bt += gridDim.x) {
         const int64_t f = bt / A.tiles, t = bt % A.tiles;
         VState *st = A.st + f;
-        __syncthreads();  // the previous tile is finished with the shared state
-        if (threadIdx.x == 0) {
-            // the field's state cannot change while one of its tiles is pending
-            const int done = __hip_atomic_load(&st->done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            const int redo = __hip_atomic_load(&st->redo, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-            skip = REDO ? redo == 0 : done != 0;
-            passes = REDO ? redo : A.steps;
-            par = __hip_atomic_load(&st->parity, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (f != fcur) {
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                skip = REDO ? st->redo == 0 : st->done != 0;
+                passes = REDO ? st->redo : A.steps;
+                par = st->parity;
+            }
+            __syncthreads();
+            fcur = f;
         }
-        __syncthreads();
         if (skip) continue;
         const int p = par;
         const int steps = passes;
@@ -304,7 +311,7 @@ __global__ __launch_bounds__(256) void k_vcb_sweep(Args A) {
         T *rout = static_cast<T *>(A.r[1 - p]) + f * A.npts;
         T *uout = static_cast<T *>(A.u[1 - p]) + f * A.npts;
         const TileOrg o = tile_org(A, t, S::TX, S::TY, S::TZ);
-        load_region<T, NDIM>(a, rin, A, o, K, RX, RY, RZ);
+        load_region<T, NDIM, RX, RY, RZ>(a, rin, A, o, K);
         // the thread's interior points: LDS index, field index, in-field flag
         int li[PER];
         int64_t gi[PER];
@@ -329,7 +336,7 @@ __global__ __launch_bounds__(256) void k_vcb_sweep(Args A) {
                 if (in[q]) uacc[q] += x[li[q]];  // u_{n+j+1} = u_{n+j} + r_{n+j}
             // pass j leaves r valid on the region shrunk by K - steps + j + 1
             // points per side: the interior after the last pass
-            step<T, NDIM>(x, y, K - steps + j + 1, RX, RY, RZ);
+            step<T, NDIM, RX, RY, RZ>(x, y, K - steps + j + 1);
             __syncthreads();
             double sum = 0.0;
 #pragma unroll
@@ -351,39 +358,54 @@ __global__ __launch_bounds__(256) void k_vcb_sweep(Args A) {
             const double sj = block_sum(nrm[j], red);
             if (threadIdx.x == 0) pp[j] = sj;
         }
-        if (!last_tile(st, A.tiles, &flag)) continue;
-        double tot[kMaxK];
-        for (int j = 0; j < steps; ++j) tot[j] = field_sum(A.part + f * A.tiles * (kMaxK + 1), A.tiles, j, red);
-        if (threadIdx.x != 0) continue;
-        if (REDO) {
-            st->r_last = sqrt(tot[steps - 1]);
-            st->parity = 1 - p;
-            __hip_atomic_store(&st->redo, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            continue;
-        }
-        const int n0 = st->iters;
-        int status = GD_MAXITER;
-        bool stopped = false;
-        for (int j = 0; j < steps && !stopped; ++j) {
-            const int n = n0 + j + 1;
-            const double rn = sqrt(tot[j]);
-            if (A.hist) A.hist[f * (A.max_iter + 1) + n] = rn;
-            if (stop_rule(rn, A.tol, st->r_ref, n, A.max_iter, &status)) {
-                st->iters = n;
-                st->status = status;
-                st->r_last = rn;
-                if (j + 1 < steps) st->redo = j + 1;  // stopped inside the sweep: recompute j + 1 passes
-                else st->parity = 1 - p;
-                __hip_atomic_store(&st->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                stopped = true;
+    }
+}
+
+// Per field, after a sweep launch: the residual norm of every pass of the
+// sweep (partials summed in tile order), the stopping rule pass by pass, and
+// the state for the next launch.
+template <bool REDO>
+__global__ __launch_bounds__(256) void k_vcb_sweep_reduce(Args A) {
+    __shared__ double red[4];
+    const int64_t f = blockIdx.x;
+    VState *st = A.st + f;
+    if (REDO ? st->redo == 0 : st->done != 0) return;  // uniform across the workgroup
+    const int steps = REDO ? st->redo : A.steps;
+    double tot[kMaxK];
+    for (int j = 0; j < steps; ++j) tot[j] = field_sum(A.part + f * A.tiles * (kMaxK + 1), A.tiles, j, red);
+    if (threadIdx.x != 0) return;
+    const int p = st->parity;
+    if (REDO) {
+        st->r_last = sqrt(tot[steps - 1]);
+        st->parity = 1 - p;
+        st->redo = 0;
+        atomicAdd(&A.glob->redo, -1);
+        return;
+    }
+    const int n0 = st->iters;
+    int status = GD_MAXITER;
+    for (int j = 0; j < steps; ++j) {
+        const int n = n0 + j + 1;
+        const double rn = sqrt(tot[j]);
+        if (A.hist) A.hist[f * (A.max_iter + 1) + n] = rn;
+        if (stop_rule(rn, A.tol, st->r_ref, n, A.max_iter, &status)) {
+            st->iters = n;
+            st->status = status;
+            st->r_last = rn;
+            if (j + 1 < steps) {  // stopped inside the sweep: recompute j + 1 passes
+                st->redo = j + 1;
+                atomicAdd(&A.glob->redo, 1);
+            } else {
+                st->parity = 1 - p;
             }
-        }
-        if (!stopped) {
-            st->iters = n0 + steps;
-            st->r_last = sqrt(tot[steps - 1]);
-            st->parity = 1 - p;
+            st->done = 1;
+            atomicAdd(&A.glob->active, -1);
+            return;
         }
     }
+    st->iters = n0 + steps;
+    st->r_last = sqrt(tot[steps - 1]);
+    st->parity = 1 - p;
 }
 
 // Exit: the true residual ||ubar - G u|| of the final u, the info record, and
@@ -395,16 +417,16 @@ __global__ __launch_bounds__(256) void k_vcb_finish(Args A, double hw_sqrt) {
     constexpr int NI = S::TX * S::TY * S::TZ;
     __shared__ T a[RX * RY * RZ], b[RX * RY * RZ];
     __shared__ double red[4];
-    __shared__ int flag;
     const int64_t f = blockIdx.x / A.tiles, t = blockIdx.x % A.tiles;
-    VState *st = A.st + f;
+    const VState *st = A.st + f;
     const int p = st->parity;
     const T *ub = static_cast<const T *>(A.ubar) + f * A.npts;
     const T *uf = static_cast<const T *>(A.u[p]) + f * A.npts;
+    T *uc = static_cast<T *>(A.u[0]) + f * A.npts;
     const TileOrg o = tile_org(A, t, S::TX, S::TY, S::TZ);
-    load_region<T, NDIM>(a, uf, A, o, 1, RX, RY, RZ);
+    load_region<T, NDIM, RX, RY, RZ>(a, uf, A, o, 1);
     __syncthreads();
-    step<T, NDIM>(a, b, 1, RX, RY, RZ);  // b = u - G u
+    step<T, NDIM, RX, RY, RZ>(a, b, 1);  // b = u - G u
     __syncthreads();
     double s = 0.0;
     for (int i = threadIdx.x; i < NI; i += 256) {
@@ -415,31 +437,25 @@ __global__ __launch_bounds__(256) void k_vcb_finish(Args A, double hw_sqrt) {
         const int64_t g = (gz * A.ny + gy) * A.nx + gx;
         const double d = double(ub[g]) - (double(a[c]) - double(b[c]));  // ubar - G u
         s += d * d;
+        if (p != 0) uc[g] = a[c];  // the result ended in the workspace copy
     }
     const double ss = block_sum(s, red);
-    double *pp = A.part + (f * A.tiles + t) * (kMaxK + 1);
-    if (threadIdx.x == 0) pp[kMaxK] = ss;
-    if (!last_tile(st, A.tiles, &flag)) return;
-    const double tsq = field_sum(A.part + f * A.tiles * (kMaxK + 1), A.tiles, kMaxK, red);
-    if (threadIdx.x == 0) {
-        gd_info &I = A.info[f];
-        I.iters = st->iters;
-        I.status = st->status;
-        I.r_ref = st->r_ref * hw_sqrt;
-        I.r0 = st->r0 * hw_sqrt;
-        I.r_final = st->r_last * hw_sqrt;
-        I.r_true = sqrt(tsq) * hw_sqrt;
-    }
+    if (threadIdx.x == 0) A.part[(f * A.tiles + t) * (kMaxK + 1) + kMaxK] = ss;
 }
 
-// copy the final u into the caller's buffer when it ended in the workspace
-template <typename T>
-__global__ void k_vcb_copy(Args A) {
-    const T *src = static_cast<const T *>(A.u[1]);
-    T *dst = static_cast<T *>(A.u[0]);
-    const int64_t n = A.nfields * A.npts;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        if (A.st[i / A.npts].parity != 0) dst[i] = src[i];
+__global__ __launch_bounds__(256) void k_vcb_finish_reduce(Args A, double hw_sqrt) {
+    __shared__ double red[4];
+    const int64_t f = blockIdx.x;
+    const VState *st = A.st + f;
+    const double tsq = field_sum(A.part + f * A.tiles * (kMaxK + 1), A.tiles, kMaxK, red);
+    if (threadIdx.x != 0) return;
+    gd_info &I = A.info[f];
+    I.iters = st->iters;
+    I.status = st->status;
+    I.r_ref = st->r_ref * hw_sqrt;
+    I.r0 = st->r0 * hw_sqrt;
+    I.r_final = st->r_last * hw_sqrt;
+    I.r_true = sqrt(tsq) * hw_sqrt;
 }
 
 // history entries are norms without the spacing weight until scaled here
@@ -448,10 +464,13 @@ __global__ void k_vcb_hist_scale(double *hist, int64_t n, double w) {
     if (i < n) hist[i] *= w;
 }
 
-__global__ void k_vcb_prep(VState *st, int64_t nfields) {
+__global__ void k_vcb_prep(VState *st, Global *glob, int64_t nfields) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        glob->active = (int32_t)nfields;
+        glob->redo = 0;
+    }
     if (i < nfields) {
-        st[i].cnt = 0;
         st[i].done = 0;
         st[i].redo = 0;
         st[i].parity = 0;
@@ -470,7 +489,7 @@ void tiles_of(const gd_grid *g, int64_t &tx, int64_t &ty, int64_t &tz) {
 }
 
 struct Layout {
-    size_t st, part, r0, r1, u1, total;
+    size_t glob, st, part, r0, r1, u1, total;
     int64_t tiles;
 };
 
@@ -488,6 +507,8 @@ Layout layout(const gd_grid *g) {
     const size_t ts = g->dtype == GD_F32 ? 4 : 8;
     const size_t fb = align256((size_t)g->batch * g->n[0] * g->n[1] * (g->ndim == 3 ? g->n[2] : 1) * ts);
     size_t off = 0;
+    L.glob = off;
+    off = align256(off + sizeof(Global));
     L.st = off;
     off = align256(off + (size_t)g->batch * sizeof(VState));
     L.part = off;
@@ -513,6 +534,7 @@ int run(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *wor
     A.r[1] = w + L.r1;
     A.part = (double *)(w + L.part);
     A.st = (VState *)(w + L.st);
+    A.glob = (Global *)(w + L.glob);
     A.hist = o->history;
     A.info = info;
     A.nx = g->n[0];
@@ -534,18 +556,22 @@ int run(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *wor
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_vcb_sweep<T, NDIM, false>, 256, 0) != hipSuccess)
         return fail(GD_EHIP, "device query failed");
     const unsigned sweep_blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nblk, (int64_t)std::max(occ, 1) * ncu));
-    hipLaunchKernelGGL(k_vcb_prep, dim3((unsigned)((g->batch + 255) / 256)), dim3(256), 0, st, A.st, g->batch);
+    hipLaunchKernelGGL(k_vcb_prep, dim3((unsigned)((g->batch + 255) / 256)), dim3(256), 0, st, A.st, A.glob, g->batch);
+    const dim3 per_field((unsigned)g->batch);
     hipLaunchKernelGGL((k_vcb_init<T, NDIM>), dim3((unsigned)nblk), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_vcb_init_reduce, per_field, dim3(256), 0, st, A);
     for (int done = 0; done < o->max_iter; done += S::K) {
         A.steps = std::min(S::K, o->max_iter - done);
         hipLaunchKernelGGL((k_vcb_sweep<T, NDIM, false>), dim3(sweep_blocks), dim3(256), 0, st, A);
+        hipLaunchKernelGGL(k_vcb_sweep_reduce<false>, per_field, dim3(256), 0, st, A);
     }
     A.steps = 0;
     hipLaunchKernelGGL((k_vcb_sweep<T, NDIM, true>), dim3(sweep_blocks), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_vcb_sweep_reduce<true>, per_field, dim3(256), 0, st, A);
     // norms above are plain sums; the inner product carries the spacing weight h^d
     const double hw = gd::grid_weight(g);
     hipLaunchKernelGGL((k_vcb_finish<T, NDIM>), dim3((unsigned)nblk), dim3(256), 0, st, A, sqrt(hw));
-    hipLaunchKernelGGL(k_vcb_copy<T>, dim3(2048), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_vcb_finish_reduce, per_field, dim3(256), 0, st, A, sqrt(hw));
     if (o->history) {
         const int64_t nh = g->batch * (int64_t)(o->max_iter + 1);
         hipLaunchKernelGGL(k_vcb_hist_scale, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, st, o->history, nh,
@@ -573,7 +599,7 @@ size_t vancittert_blocked_workspace_bytes(const gd_grid *g) {
 
 int32_t vancittert_blocked_passes(const gd_grid *g) {
     if (gd::validate_grid(g)) return 0;
-    if (g->ndim == 2) return Shape<float, 2>::K;
+    if (g->ndim == 2) return g->dtype == GD_F32 ? Shape<float, 2>::K : Shape<double, 2>::K;
     return g->dtype == GD_F32 ? Shape<float, 3>::K : Shape<double, 3>::K;
 }
 
@@ -585,6 +611,8 @@ int deconvolve_vancittert_blocked(const gd_grid *g, const void *ubar, void *u, c
     if (!ubar || !u || !info) return fail(GD_EINVAL, "ubar, u and info must be non-NULL");
     if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
     if ((uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be 256-byte aligned");
+    for (int d = 0; d < g->ndim; ++d)
+        if (g->n[d] >= (int64_t(1) << 30)) return fail(GD_EINVAL, "n[%d] must be below 2^30", d);
     const Layout L = layout(g);
     if (wb < L.total) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", L.total, wb);
     const size_t fb = (size_t)g->batch * g->n[0] * g->n[1] * (g->ndim == 3 ? g->n[2] : 1) * (g->dtype == GD_F32 ? 4 : 8);
