@@ -182,7 +182,14 @@ __global__ __launch_bounds__(256) void k_fft_cols(T *data, int64_t inner, int n,
     extern __shared__ __align__(16) unsigned char lds_raw[];
     V *buf = reinterpret_cast<V *>(lds_raw);
     const int cw = 1 << logcw;
-    const int64_t chunk = blockIdx.x % nchunks, o = blockIdx.x / nchunks;
+    // workgroups are dealt round-robin over the 8 XCDs: give each XCD a
+    // contiguous range, so that the chunks sharing a cache line share an L2
+    int64_t lin = blockIdx.x;
+    {
+        const int64_t nb = gridDim.x, per = nb / 8, rem = nb % 8, xcd = lin % 8, k = lin / 8;
+        lin = xcd * per + (xcd < rem ? xcd : rem) + k;
+    }
+    const int64_t chunk = lin % nchunks, o = lin / nchunks;
     const int64_t i0 = chunk * cw;
     const int ncols = (int)std::min<int64_t>(cw, inner - i0);
     V *base = reinterpret_cast<V *>(data) + (o * n) * inner + i0;
