@@ -301,6 +301,8 @@ __global__ __launch_bounds__(256) void k_irfft_rows(const T *X, T *x, int64_t nr
 }
 
 constexpr size_t kLdsBudget = 64 * 1024;
+// column transforms: a smaller share, so that more workgroups are resident
+constexpr size_t kColLds = 32 * 1024;
 
 int ilog2(int64_t n) {
     int l = 0;
@@ -375,7 +377,7 @@ int launch_cols(const Spec &s, T *data, int axis, bool inv, int mul, double inv_
     const int64_t outer = axis == 1 ? s.batch * s.nz : s.batch;
     const size_t cs = 2 * sizeof(T);
     int logcw = 0;  // adjacent columns per workgroup: a power of two, up to 16, within the LDS budget
-    while (logcw < 4 && (int64_t(2) << logcw) <= inner && (size_t)n * (size_t(2) << logcw) * cs <= kLdsBudget) ++logcw;
+    while (logcw < 4 && (int64_t(2) << logcw) <= inner && (size_t)n * (size_t(2) << logcw) * cs <= kColLds) ++logcw;
     const int cw = 1 << logcw;
     const int64_t nchunks = (inner + cw - 1) / cw;
     const int64_t blocks = outer * nchunks;
@@ -392,13 +394,13 @@ int launch_cols(const Spec &s, T *data, int axis, bool inv, int mul, double inv_
     return e == hipSuccess ? GD_OK : fail(GD_EHIP, "FFT column launch: %s", hipGetErrorString(e));
 }
 
-// log2 of the rows per workgroup of the row transforms: enough rows for 256
-// threads' worth of radix-4 butterflies (n2 / 4 per row), within the LDS budget
+// log2 of the rows per workgroup of the row transforms: enough rows for two
+// radix-4 butterflies (n2 / 4 per row) per thread, within the LDS share
 template <typename T>
 int log_rows_per_wg(const Spec &s) {
     const int64_t n2 = s.nx / 2;
     int l = 0;
-    while ((std::max<int64_t>(1, n2 / 4) << l) < 256 && (n2 << (l + 1)) * 2 * (int64_t)sizeof(T) <= (int64_t)kLdsBudget)
+    while ((std::max<int64_t>(1, n2 / 4) << l) < 512 && (n2 << (l + 1)) * 2 * (int64_t)sizeof(T) <= (int64_t)kColLds)
         ++l;
     return l;
 }
