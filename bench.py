@@ -558,7 +558,7 @@ def time_solver(gd, torch, ubar, w, solver, steps, warmup, tol=1e-6, max_iter=50
     wall = (time.perf_counter() - t0) / steps
     ms = [a.elapsed_time(b) for a, b in evs]
     return dict(info=info, ms_events=float(np.mean(ms)), ms_min=float(np.min(ms)), wall_ms=wall * 1e3, u=out,
-                tune=tuned, launch=gd.last_launch())
+                tune=tuned, launch=gd.last_launch() if solver != "vcb" else None)
 
 
 def cpu_baseline(w, u32, tol=1e-6, sample_fields=12):
