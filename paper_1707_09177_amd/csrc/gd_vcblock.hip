@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_vcb_init(Args A) {
         if (gx >= A.nx || gy >= A.ny || (NDIM == 3 && gz >= A.nz)) continue;
         const int c = ((NDIM == 3 ? iz + 1 : 0) * RY + iy + 1) * RX + ix + 1;
         const int64_t g = (gz * A.ny + gy) * A.nx + gx;
-        const T ubv = ub[g];
+        const T ubv = A.init == GD_INIT_GIVEN ? ub[g] : a[c];  // the tile holds ubar unless u0 is given
         T rv;
         if (A.init == GD_INIT_UBAR) {
             rv = b[c];  // ubar - G ubar
