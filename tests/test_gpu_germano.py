@@ -176,3 +176,17 @@ def test_autotuned_solve_matches_oracle(solver):
     want, _, _ = oracle.solve(solver, ub, 2, 6, gamma=gamma)
     for e in rel_l2_per_field(res.u.cpu().numpy(), want, 2):
         assert e <= 1e-10
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_table1_setting_pass_counts(nd):
+    """Table 1's setting (256^2 / 64^3, gamma = 0.1, 99 % residual reduction),
+    FP64: every solver stops at the oracle's pass count, with the same u."""
+    u = synth.config_fields(2, n=256, count=1) if nd == 2 else synth.config_fields(3, n=64, count=1)
+    ub = oracle.germano_filter(u, nd, 0.1)
+    for solver in ("vc", "sd", "cg", "bicgstab"):
+        got, gi, _ = gdecon.deconvolve_germano(solver, to_dev(ub, torch.float64), 500, 0.1, tol=1e-2, ndim=nd)
+        want, wi, _ = oracle.solve(solver, ub, nd, 500, tol=1e-2, gamma=0.1)
+        assert gi[0]["status_name"] == wi[0]["status_name"] == "CONVERGED", solver
+        assert gi[0]["iters"] == wi[0]["iters"], (solver, gi[0]["iters"], wi[0]["iters"])
+        assert rel_l2(got.cpu().numpy(), want) <= 1e-9, solver
