@@ -85,8 +85,8 @@ __global__ void prep_kernel(Params P) {
 }
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
 int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -97,6 +97,10 @@ int fail(int code, const char *fmt, ...) {
     g_err = buf;
     return code;
 }
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+namespace {
 
 struct DevProps {
     int ncu = 0;
@@ -157,8 +161,6 @@ int nvec_of(int solver) {
     for (int v = 0; v < NVEC; ++v) n += vec_used(solver, v);
     return n;
 }
-
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 

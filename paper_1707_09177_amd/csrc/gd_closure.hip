@@ -23,11 +23,7 @@
 #include <cstdio>
 #include <cstring>
 
-#include "gdecon.h"
-
-namespace gd {
-void set_error_text(const char *msg);
-}
+#include "gd_internal.h"
 
 namespace gdclosure {
 
@@ -187,20 +183,8 @@ int launch(const T *ub, const T *us, T *tau, int64_t nx, int64_t ny, int64_t nz,
     return 0;
 }
 
-int fail(int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    gd::set_error_text(buf);
-    return code;
-}
+using gd::fail;
 
-bool overlap(const void *a, size_t na, const void *b, size_t nb) {
-    const char *x = (const char *)a, *y = (const char *)b;
-    return x < y + nb && y < x + na;
-}
 
 }  // namespace gdclosure
 
@@ -220,7 +204,7 @@ int closure_stress(const gd_grid *g, const void *ubar, const void *ustar, void *
     const size_t ts = g->dtype == GD_F32 ? 4 : 8;
     const int nc = g->ndim, np = nc * (nc + 1) / 2;
     const size_t in_bytes = (size_t)g->batch * nc * nx * ny * nz * ts, out_bytes = (size_t)g->batch * np * nx * ny * nz * ts;
-    if (overlap(tau, out_bytes, ubar, in_bytes) || overlap(tau, out_bytes, ustar, in_bytes))
+    if (gd::ranges_overlap(tau, out_bytes, ubar, in_bytes) || gd::ranges_overlap(tau, out_bytes, ustar, in_bytes))
         return fail(GD_EINVAL, "tau overlaps an input");
     hipStream_t st = (hipStream_t)stream;
     int rc;

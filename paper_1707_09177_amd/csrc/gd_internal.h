@@ -202,6 +202,10 @@ int tune_uniform(int solver, const gd_grid *g, const void *ubar, void *u, void *
                  void *stream, gd_tune_info *out, const SpecParams *spec);
 int validate_grid(const gd_grid *g);
 double grid_weight(const gd_grid *g);
+// error text for gd_last_error, then the code; every entry point reports through it
+int fail(int code, const char *fmt, ...);
+bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb);
+size_t align_up(size_t x, size_t a);
 int validate_opts(const gd_opts *o);
 void set_error_text(const char *msg);
 int64_t geo_tiles(const Geo &g);

@@ -37,15 +37,9 @@
 
 namespace gdspec {
 
-int fail(int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    gd::set_error_text(buf);
-    return code;
-}
+using gd::fail;
+
+inline size_t align_up_256(size_t x) { return gd::align_up(x, 256); }
 
 __constant__ gdtw::Table c_tw = gdtw::make_table();
 
@@ -443,7 +437,6 @@ int inverse(const Spec &s, T *X, T *x, int mul, double inv_kc2, hipStream_t st) 
     return e == hipSuccess ? GD_OK : fail(GD_EHIP, "FFT row launch: %s", hipGetErrorString(e));
 }
 
-size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // the virtual grid the persistent solve kernel runs on: the stored spectrum
 gd_grid spectral_grid(const gd_grid *g, const Spec &s) {
@@ -453,10 +446,6 @@ gd_grid spectral_grid(const gd_grid *g, const Spec &s) {
     return v;
 }
 
-bool overlap(const void *a, size_t na, const void *b, size_t nb) {
-    const char *x = (const char *)a, *y = (const char *)b;
-    return x < y + nb && y < x + na;
-}
 
 // ---- a-priori diagnostics: energy spectra and PDFs ---------------------------
 
@@ -576,7 +565,7 @@ extern "C" {
 size_t germano_workspace_bytes(const gd_grid *g, int32_t solver) {
     if (validate_spec_grid(g)) return 0;
     const Spec s = spec_of(g);
-    const size_t spec_bytes = align256((size_t)s.elems * s.tsize);
+    const size_t spec_bytes = align_up_256((size_t)s.elems * s.tsize);
     if (solver < 0) return spec_bytes;
     if (solver > GD_STEEPEST_DESCENT) return 0;
     const gd_grid v = spectral_grid(g, s);
@@ -596,7 +585,7 @@ int germano_filter_apply(const gd_grid *g, double gamma, const void *x, void *y,
     const size_t need = germano_workspace_bytes(g, -1);
     if (wb < need) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", need, wb);
     const size_t fb = (size_t)s.batch * s.nx * s.ny * s.nz * s.tsize;
-    if (overlap(x, fb, work, need) || overlap(y, fb, work, need)) return fail(GD_EINVAL, "a field overlaps the workspace");
+    if (gd::ranges_overlap(x, fb, work, need) || gd::ranges_overlap(y, fb, work, need)) return fail(GD_EINVAL, "a field overlaps the workspace");
     const double ik = inv_kc2_of(g, gamma);
     hipStream_t st = (hipStream_t)stream;
     if (g->dtype == GD_F32) {
@@ -621,10 +610,10 @@ int deconvolve_germano(int32_t solver, const gd_grid *g, double gamma, const voi
     if (wb < need) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", need, wb);
     const Spec s = spec_of(g);
     const size_t fb = (size_t)s.batch * s.nx * s.ny * s.nz * s.tsize;
-    if (overlap(ubar, fb, u, fb)) return fail(GD_EINVAL, "ubar and u overlap");
-    if (overlap(ubar, fb, work, need) || overlap(u, fb, work, need))
+    if (gd::ranges_overlap(ubar, fb, u, fb)) return fail(GD_EINVAL, "ubar and u overlap");
+    if (gd::ranges_overlap(ubar, fb, work, need) || gd::ranges_overlap(u, fb, work, need))
         return fail(GD_EINVAL, "a field overlaps the workspace");
-    const size_t sb = align256((size_t)s.elems * s.tsize);
+    const size_t sb = align_up_256((size_t)s.elems * s.tsize);
     char *w = (char *)work;
     void *UB = w, *U = w + sb;
     void *solve_work = w + 2 * sb;
@@ -660,7 +649,7 @@ int deconvolve_germano_autotune(int32_t solver, const gd_grid *g, double gamma, 
     const size_t need = germano_workspace_bytes(g, solver);
     if (wb < need) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", need, wb);
     const Spec s = spec_of(g);
-    const size_t sb = align256((size_t)s.elems * s.tsize);
+    const size_t sb = align_up_256((size_t)s.elems * s.tsize);
     char *w = (char *)work;
     const double ik = inv_kc2_of(g, gamma);
     hipStream_t st = (hipStream_t)stream;
@@ -687,8 +676,8 @@ static int64_t spectrum_chunks(const Spec &s) {
 size_t spectrum_workspace_bytes(const gd_grid *g) {
     if (validate_spec_grid(g)) return 0;
     const Spec s = spec_of(g);
-    return align256((size_t)s.elems * s.tsize) +
-           align256((size_t)s.batch * spectrum_chunks(s) * num_shells(s) * sizeof(double));
+    return align_up_256((size_t)s.elems * s.tsize) +
+           align_up_256((size_t)s.batch * spectrum_chunks(s) * num_shells(s) * sizeof(double));
 }
 
 int energy_spectrum(const gd_grid *g, double kpow, const void *x, double *out, void *work, size_t wb, void *stream) {
@@ -703,11 +692,11 @@ int energy_spectrum(const gd_grid *g, double kpow, const void *x, double *out, v
     if (wb < need) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", need, wb);
     const int64_t ns = num_shells(s), nch = spectrum_chunks(s);
     const size_t fb = (size_t)s.batch * s.nx * s.ny * s.nz * s.tsize;
-    if (overlap(x, fb, work, need) || overlap(out, (size_t)s.batch * ns * 8, work, need))
+    if (gd::ranges_overlap(x, fb, work, need) || gd::ranges_overlap(out, (size_t)s.batch * ns * 8, work, need))
         return fail(GD_EINVAL, "a buffer overlaps the workspace");
     if ((size_t)ns * sizeof(double) > kLdsBudget) return fail(GD_EINVAL, "too many shells");
     hipStream_t st = (hipStream_t)stream;
-    double *part = (double *)((char *)work + align256((size_t)s.elems * s.tsize));
+    double *part = (double *)((char *)work + align_up_256((size_t)s.elems * s.tsize));
     const int64_t rows = s.ny * s.nz, rpc = (rows + nch - 1) / nch;
     const dim3 grid((unsigned)(s.batch * nch));
     if (g->dtype == GD_F32) {
@@ -734,7 +723,7 @@ int pdf_counts(const gd_grid *g, double lo, double hi, int32_t nbins, const void
     if (!x || !counts) return fail(GD_EINVAL, "x and counts must be non-NULL");
     const int64_t npts = g->n[0] * g->n[1] * (g->ndim == 3 ? g->n[2] : 1);
     const size_t tsize = g->dtype == GD_F32 ? 4 : 8;
-    if (overlap(x, (size_t)g->batch * npts * tsize, counts, (size_t)g->batch * nbins * 8))
+    if (gd::ranges_overlap(x, (size_t)g->batch * npts * tsize, counts, (size_t)g->batch * nbins * 8))
         return fail(GD_EINVAL, "counts overlaps x");
     hipStream_t st = (hipStream_t)stream;
     const int64_t nc = g->batch * nbins;

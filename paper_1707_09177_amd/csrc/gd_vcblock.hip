@@ -28,15 +28,9 @@
 
 namespace gdvcb {
 
-int fail(int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    gd::set_error_text(buf);
-    return code;
-}
+using gd::fail;
+
+inline size_t align_up_256(size_t x) { return gd::align_up(x, 256); }
 
 // Tile shapes: interior TX x TY (x TZ) and K passes per sweep, sized so that
 // two LDS copies of the tile with its halo fit in 64 KB and a halo row
@@ -478,7 +472,6 @@ __global__ void k_vcb_prep(VState *st, Global *glob, int64_t nfields) {
     }
 }
 
-size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 template <typename T, int NDIM>
 void tiles_of(const gd_grid *g, int64_t &tx, int64_t &ty, int64_t &tz) {
@@ -505,14 +498,14 @@ Layout layout(const gd_grid *g) {
     }
     L.tiles = tx * ty * tz;
     const size_t ts = g->dtype == GD_F32 ? 4 : 8;
-    const size_t fb = align256((size_t)g->batch * g->n[0] * g->n[1] * (g->ndim == 3 ? g->n[2] : 1) * ts);
+    const size_t fb = align_up_256((size_t)g->batch * g->n[0] * g->n[1] * (g->ndim == 3 ? g->n[2] : 1) * ts);
     size_t off = 0;
     L.glob = off;
-    off = align256(off + sizeof(Global));
+    off = align_up_256(off + sizeof(Global));
     L.st = off;
-    off = align256(off + (size_t)g->batch * sizeof(VState));
+    off = align_up_256(off + (size_t)g->batch * sizeof(VState));
     L.part = off;
-    off = align256(off + (size_t)g->batch * L.tiles * (kMaxK + 1) * sizeof(double));
+    off = align_up_256(off + (size_t)g->batch * L.tiles * (kMaxK + 1) * sizeof(double));
     L.r0 = off;
     L.r1 = off + fb;
     L.u1 = off + 2 * fb;
@@ -581,10 +574,6 @@ int run(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *wor
     return e == hipSuccess ? GD_OK : fail(GD_EHIP, "blocked Van Cittert launch: %s", hipGetErrorString(e));
 }
 
-bool overlap(const void *a, size_t na, const void *b, size_t nb) {
-    const char *x = (const char *)a, *y = (const char *)b;
-    return x < y + nb && y < x + na;
-}
 
 }  // namespace gdvcb
 
@@ -616,8 +605,8 @@ int deconvolve_vancittert_blocked(const gd_grid *g, const void *ubar, void *u, c
     const Layout L = layout(g);
     if (wb < L.total) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", L.total, wb);
     const size_t fb = (size_t)g->batch * g->n[0] * g->n[1] * (g->ndim == 3 ? g->n[2] : 1) * (g->dtype == GD_F32 ? 4 : 8);
-    if (overlap(ubar, fb, u, fb)) return fail(GD_EINVAL, "ubar and u overlap");
-    if (overlap(ubar, fb, work, L.total) || overlap(u, fb, work, L.total))
+    if (gd::ranges_overlap(ubar, fb, u, fb)) return fail(GD_EINVAL, "ubar and u overlap");
+    if (gd::ranges_overlap(ubar, fb, work, L.total) || gd::ranges_overlap(u, fb, work, L.total))
         return fail(GD_EINVAL, "a field overlaps the workspace");
     hipStream_t st = (hipStream_t)stream;
     if (g->dtype == GD_F32)

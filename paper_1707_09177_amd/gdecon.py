@@ -273,15 +273,21 @@ class Deconvolver:
         self.solver = solver
         self.grid = make_grid(self.shape, ndim, dtype, h)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        n = self.lib.deconvolve_workspace_bytes(ctypes.byref(self.grid), SOLVERS[solver])
+        n = self._workspace_bytes()
         if n == 0:
             raise GdError(-1, "bad grid or solver")
         self.work = torch.empty(int(n), dtype=torch.uint8, device=self.device)
         self.batch = int(self.grid.batch)
         self.info_dev = torch.zeros(self.batch * INFO_BYTES, dtype=torch.uint8, device=self.device)
-        self._fn = getattr(self.lib, {"vc": "deconvolve_vancittert", "cg": "deconvolve_cg",
-                                      "bicgstab": "deconvolve_bicgstab",
-                                      "sd": "deconvolve_steepest_descent"}[solver])
+        self._fn = self._entry()
+
+    # the C entry point and its workspace size; subclasses for other solves override these
+    def _workspace_bytes(self) -> int:
+        return self.lib.deconvolve_workspace_bytes(ctypes.byref(self.grid), SOLVERS[self.solver])
+
+    def _entry(self):
+        return getattr(self.lib, {"vc": "deconvolve_vancittert", "cg": "deconvolve_cg",
+                                  "bicgstab": "deconvolve_bicgstab", "sd": "deconvolve_steepest_descent"}[self.solver])
 
     def solve(self, ubar: torch.Tensor, max_iter: int, tol: float = 0.0, init: str = "ubar",
               out: torch.Tensor | None = None, norm_ref: str = "r0ubar", history: torch.Tensor | None = None,
@@ -354,21 +360,14 @@ class BlockedVanCittert(Deconvolver):
     same results as the "vc" solver, less memory traffic."""
 
     def __init__(self, field_shape, ndim: int, dtype: torch.dtype, device=None, h=None):
-        self.lib = load()
-        self.shape = tuple(field_shape)
-        self.ndim = ndim
-        self.dtype = dtype
-        self.solver = "vcb"
-        self.grid = make_grid(self.shape, ndim, dtype, h)
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        n = self.lib.vancittert_blocked_workspace_bytes(ctypes.byref(self.grid))
-        if n == 0:
-            raise GdError(-1, "bad grid")
-        self.work = torch.empty(int(n), dtype=torch.uint8, device=self.device)
-        self.batch = int(self.grid.batch)
-        self.info_dev = torch.zeros(self.batch * INFO_BYTES, dtype=torch.uint8, device=self.device)
+        super().__init__(field_shape, ndim, dtype, "vcb", device=device, h=h)
         self.passes_per_sweep = int(self.lib.vancittert_blocked_passes(ctypes.byref(self.grid)))
-        self._fn = self.lib.deconvolve_vancittert_blocked
+
+    def _workspace_bytes(self) -> int:
+        return self.lib.vancittert_blocked_workspace_bytes(ctypes.byref(self.grid))
+
+    def _entry(self):
+        return self.lib.deconvolve_vancittert_blocked
 
 
 class GermanoDeconvolver(Deconvolver):
@@ -376,26 +375,19 @@ class GermanoDeconvolver(Deconvolver):
     (deconvolve_germano): the solve runs on the Fourier coefficients."""
 
     def __init__(self, field_shape, ndim: int, dtype: torch.dtype, solver: str, gamma: float, device=None, h=None):
-        self.lib = load()
-        self.shape = tuple(field_shape)
-        self.ndim = ndim
-        self.dtype = dtype
-        self.solver = solver
         self.gamma = float(gamma)
-        self.grid = make_grid(self.shape, ndim, dtype, h)
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        n = self.lib.germano_workspace_bytes(ctypes.byref(self.grid), SOLVERS[solver])
-        if n == 0:
-            raise GdError(-1, "bad grid or solver (the differential filter needs power-of-two sizes)")
-        self.work = torch.empty(int(n), dtype=torch.uint8, device=self.device)
-        self.batch = int(self.grid.batch)
-        self.info_dev = torch.zeros(self.batch * INFO_BYTES, dtype=torch.uint8, device=self.device)
-        code = SOLVERS[solver]
-        fn = self.lib.deconvolve_germano
+        super().__init__(field_shape, ndim, dtype, solver, device=device, h=h)
+
+    def _workspace_bytes(self) -> int:
+        # 0 also for sizes the FFTs do not take (not powers of two)
+        return self.lib.germano_workspace_bytes(ctypes.byref(self.grid), SOLVERS[self.solver])
+
+    def _entry(self):
+        code, fn = SOLVERS[self.solver], self.lib.deconvolve_germano
 
         def call(grid, ub, u, o, work, wb, info, stream):
             return fn(code, grid, self.gamma, ub, u, o, work, wb, info, stream)
-        self._fn = call
+        return call
 
     def autotune(self, ubar: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> dict:
         """Time the launch configurations on these buffers and keep the
