@@ -454,8 +454,12 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
     I.vw = ts.vw;
     I.R = ts.R;
     if (spec) {
+        I.hw = spec->hw;
         I.inv_kc2 = spec->inv_kc2;
-        I.nxc = spec->nxc;
+        I.nxc = (int32_t)spec->nxc;
+        I.nxs = (int32_t)spec->nxs;
+        I.lny = spec->lny;
+        I.lnz = spec->lnz;
     }
     P.table = nullptr;
     P.st = (State *)(w + off_st);

@@ -291,76 +291,4 @@ __device__ __forceinline__ void point_tile(const Geo &g, int64_t lt, const Op &o
             }
 }
 
-// Pointwise pass over a tile of a stored half spectrum (the differential
-// filter): G S = G_hat(k) S at every point, G_hat = 1 / (1 + |k|^2 / k_c^2).
-// A row holds complex values as (re, im) pairs, so element x has k_x = x / 2;
-// k_x >= nxc marks the zero padding of a row, where G_hat is taken as 0.
-// Rows are k_y (3D) and planes k_z (3D) or k_y (2D), in FFT order.
-template <int NDIM, int VW, int R, typename T, typename C, class Op>
-__device__ __forceinline__ void spectral_tile(const Geo &g, double inv_kc2, int64_t nxc, int64_t lt, const Op &op,
-                                              double (&acc)[NACC], int lane) {
-    constexpr int NI = Arr<Op::NI>::n;
-    constexpr int NO = Arr<Op::NO>::n;
-    const TilePos p = tile_pos<VW, R>(g, lt, lane);
-    if (!p.act) return;
-    C kx2[VW];
-    bool pad[VW];
-#pragma unroll
-    for (int k = 0; k < VW; ++k) {
-        const int64_t kx = (p.x0 + k) >> 1;
-        kx2[k] = C(kx * kx);
-        pad[k] = kx >= nxc;
-    }
-    const C ikc2 = C(inv_kc2);
-    auto sk = [](int64_t k, int64_t n) -> int64_t { return 2 * k <= n ? k : k - n; };
-    // one row at a time, its loads issued one step ahead
-    const int64_t nrow_steps = (p.m1 - p.m0) * R;
-    auto index_of = [&](int64_t q, int64_t &m, int64_t &row) {
-        m = p.m0 + q / R;
-        row = p.row0 + q % R;
-    };
-    T v[NI][VW], o[NO][VW];
-    auto load = [&](int64_t q, T (&vv)[NI][VW], T (&oo)[NO][VW]) {
-        int64_t m, row;
-        index_of(q, m, row);
-        if (NDIM == 3 && row >= g.nrows) row = g.nrows - 1;  // loads stay in the field
-        const int64_t i = m * g.plane + row * g.nx + p.x0;
-#pragma unroll
-        for (int f = 0; f < Op::NI; ++f) vld<T, VW>(op.in[f] + i, vv[f]);
-#pragma unroll
-        for (int f = 0; f < Op::NO; ++f) vld<T, VW>(op.oin[f] + i, oo[f]);
-    };
-    if (nrow_steps > 0) load(0, v, o);
-    for (int64_t q = 0; q < nrow_steps; ++q) {
-        T nv[NI][VW], no[NO][VW];
-        if (q + 1 < nrow_steps) load(q + 1, nv, no);
-        int64_t m, row;
-        index_of(q, m, row);
-        if (NDIM == 2 || row < g.nrows) {
-            const int64_t km = sk(m, g.nmarch);
-            const int64_t kr = NDIM == 3 ? sk(row, g.nrows) : 0;
-            const C kyz2 = C(km * km + kr * kr);
-            C s[VW], gv[VW];
-#pragma unroll
-            for (int k = 0; k < VW; ++k) {
-                T a[NI];
-#pragma unroll
-                for (int f = 0; f < NI; ++f) a[f] = v[f][k];
-                s[k] = op.mix(a);
-                const C gh = pad[k] ? C(0) : C(1) / (C(1) + (kx2[k] + kyz2) * ikc2);
-                gv[k] = gh * s[k];
-            }
-            op.out(m * g.plane + row * g.nx + p.x0, s, gv, o, acc);
-        }
-#pragma unroll
-        for (int f = 0; f < NI; ++f)
-#pragma unroll
-            for (int k = 0; k < VW; ++k) v[f][k] = nv[f][k];
-#pragma unroll
-        for (int f = 0; f < NO; ++f)
-#pragma unroll
-            for (int k = 0; k < VW; ++k) o[f][k] = no[f][k];
-    }
-}
-
 }  // namespace gd

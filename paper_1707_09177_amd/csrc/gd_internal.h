@@ -60,11 +60,14 @@ struct Inst {
     int64_t tile0, ntiles;  // partial-sum slots [tile0, tile0 + ntiles) of this instance
     int64_t b0, s0;         // first long / short tile in the claim order (table mode)
     double hw;              // h^d of the inner product
-    int32_t ndim, vw, R, pad;
-    // spectral solves: 1 / k_c^2 of the differential filter and the number of
-    // complex columns (n_x / 2 + 1) of the stored half spectrum
+    int32_t ndim, vw, R;
+    // spectral solves: 1 / k_c^2 of the differential filter; the stored half
+    // spectrum [k_z][k_y][row of nxs reals] has nxc = n_x / 2 + 1 complex
+    // columns, and log2 n_y, log2 n_z (each point's wavenumber comes from its
+    // index within the field, whatever tile geometry sweeps it)
+    int32_t lny;
     double inv_kc2;
-    int64_t nxc;
+    int32_t nxc, nxs, lnz, pad;
 };
 
 // FP64 scalars of one instance; written only by the barrier's last arriver.
@@ -153,10 +156,12 @@ struct TuneCfg {
     int wc = 0;   // per-wave tile claims
 };
 
-// A solve on a stored Fourier spectrum (the differential filter).
+// A solve on a stored Fourier spectrum (the differential filter); hw is the
+// inner product's weight of the grid the spectrum came from.
 struct SpecParams {
-    double inv_kc2;
-    int64_t nxc;
+    double inv_kc2, hw;
+    int64_t nxc, nxs;
+    int32_t lny, lnz;
 };
 
 // Tile shape of a field: lanes hold vw consecutive x values, a 3D tile spans

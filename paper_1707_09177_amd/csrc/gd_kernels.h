@@ -107,11 +107,94 @@ template <> struct PhaseNacc<PH_BIC> { static constexpr int v = 2; };
 
 __host__ __device__ constexpr inline int phase_nacc(int ph) { return ph == PH_BIB ? 3 : (ph == PH_BIC ? 2 : 1); }
 
+// Pointwise pass over a tile of a stored half spectrum (the differential
+// filter): G S = G_hat(k) S at every point, G_hat = 1 / (1 + |k|^2 / k_c^2).
+// The spectrum is [k_z][k_y][row of nxs reals, (re, im) pairs, k_x = 0 ..
+// nxc - 1, then zero padding] per field; the tile geometry may present it
+// with any row length, so each point's wavenumber comes from its index i in
+// the field: i = (k_z n_y + k_y) nxs + 2 k_x (+ 1 for the imaginary part).
+// A lane's VW elements lie in one stored row (nxs and the lane offset are
+// multiples of VW).  G_hat is taken as 0 on the padding.
+template <int NDIM, int VW, int R, typename T, typename C, class Op>
+__device__ __forceinline__ void spectral_tile(const Inst &I, int64_t lt, const Op &op, double (&acc)[NACC],
+                                              int lane) {
+    constexpr int NI = Arr<Op::NI>::n;
+    constexpr int NO = Arr<Op::NO>::n;
+    const Geo &g = I.geo;
+    const TilePos p = tile_pos<VW, R>(g, lt, lane);
+    if (!p.act) return;
+    const C ikc2 = C(I.inv_kc2);
+    const int64_t ny = int64_t(1) << I.lny, nz = int64_t(1) << I.lnz;
+    const int64_t nxs = I.nxs;
+    const double inv_nxs = 1.0 / (double)nxs;
+    auto sk = [](int64_t k, int64_t n) -> int64_t { return 2 * k <= n ? k : k - n; };
+    // one row at a time, its loads issued one step ahead
+    const int64_t nrow_steps = (p.m1 - p.m0) * R;
+    auto index_of = [&](int64_t q, int64_t &m, int64_t &row) {
+        m = p.m0 + q / R;
+        row = p.row0 + q % R;
+    };
+    T v[NI][VW], o[NO][VW];
+    auto load = [&](int64_t q, T (&vv)[NI][VW], T (&oo)[NO][VW]) {
+        int64_t m, row;
+        index_of(q, m, row);
+        if (NDIM == 3 && row >= g.nrows) row = g.nrows - 1;  // loads stay in the field
+        const int64_t i = m * g.plane + row * g.nx + p.x0;
+#pragma unroll
+        for (int f = 0; f < Op::NI; ++f) vld<T, VW>(op.in[f] + i, vv[f]);
+#pragma unroll
+        for (int f = 0; f < Op::NO; ++f) vld<T, VW>(op.oin[f] + i, oo[f]);
+    };
+    if (nrow_steps > 0) load(0, v, o);
+    for (int64_t q = 0; q < nrow_steps; ++q) {
+        T nv[NI][VW], no[NO][VW];
+        if (q + 1 < nrow_steps) load(q + 1, nv, no);
+        int64_t m, row;
+        index_of(q, m, row);
+        if (NDIM == 2 || row < g.nrows) {
+            const int64_t i = m * g.plane + row * g.nx + p.x0;
+            // stored row s = i / nxs, exactly: a double-precision estimate, then one correction
+            int64_t srow = (int64_t)((double)i * inv_nxs);
+            int64_t off = i - srow * nxs;
+            if (off < 0) {
+                --srow;
+                off += nxs;
+            } else if (off >= nxs) {
+                ++srow;
+                off -= nxs;
+            }
+            const int64_t ky = srow & (ny - 1), kz = srow >> I.lny;
+            const int64_t a = sk(ky, ny), b = sk(kz, nz);
+            const C kyz2 = C(a * a + b * b);
+            C s[VW], gv[VW];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) {
+                T av[NI];
+#pragma unroll
+                for (int f = 0; f < NI; ++f) av[f] = v[f][k];
+                s[k] = op.mix(av);
+                const int64_t kx = (off + k) >> 1;
+                const C gh = kx >= I.nxc ? C(0) : C(1) / (C(1) + (C(kx * kx) + kyz2) * ikc2);
+                gv[k] = gh * s[k];
+            }
+            op.out(i, s, gv, o, acc);
+        }
+#pragma unroll
+        for (int f = 0; f < NI; ++f)
+#pragma unroll
+            for (int k = 0; k < VW; ++k) v[f][k] = nv[f][k];
+#pragma unroll
+        for (int f = 0; f < NO; ++f)
+#pragma unroll
+            for (int k = 0; k < VW; ++k) o[f][k] = no[f][k];
+    }
+}
+
 // One tile of a sweep that applies G: the stencil march, or on a stored
 // spectrum the pointwise transfer function.
 template <int VS, int NDIM, int VW, int R, typename T, typename C, class Op>
 __device__ __forceinline__ void g_tile(const Inst &I, int64_t lt, const Op &op, double (&acc)[NACC], int lane) {
-    if constexpr (var_spec(VS)) spectral_tile<NDIM, VW, R, T, C>(I.geo, I.inv_kc2, I.nxc, lt, op, acc, lane);
+    if constexpr (var_spec(VS)) spectral_tile<NDIM, VW, R, T, C>(I, lt, op, acc, lane);
     else march_tile<NDIM, VW, R, T, C>(I.geo, lt, op, acc, lane);
 }
 

@@ -438,12 +438,38 @@ int inverse(const Spec &s, T *X, T *x, int mul, double inv_kc2, hipStream_t st) 
 }
 
 
-// the virtual grid the persistent solve kernel runs on: the stored spectrum
+// The grid the persistent solve kernel sweeps over the stored spectrum.  Its
+// sweeps are pointwise, so the spectrum of a field (nz ny rows of nxs reals)
+// is presented as rows of W reals, W the largest power of two up to 8192 that
+// divides the field: every 256-real wave segment is then full (rows of nxs =
+// n_x + 2 or + 4 reals would end in a nearly empty segment, half of all
+// segments at n_x = 256).  Small fields keep the stored rows.
 gd_grid spectral_grid(const gd_grid *g, const Spec &s) {
     gd_grid v = *g;
-    v.n[0] = s.nxs;
-    for (int d = 0; d < g->ndim; ++d) v.h[d] = g->h[d] > 0.0 ? g->h[d] : 2.0 * M_PI / (double)g->n[d];
+    const int64_t total = s.nz * s.ny * s.nxs;
+    int64_t W = 1;
+    while (W < 8192 && total % (2 * W) == 0) W *= 2;
+    if (W >= 1024 && total / W >= 16) {
+        v.ndim = 2;
+        v.n[0] = W;
+        v.n[1] = total / W;
+        v.n[2] = 1;
+    } else {
+        v.n[0] = s.nxs;
+    }
+    for (int d = 0; d < 3; ++d) v.h[d] = 0.0;  // the weight travels in SpecParams
     return v;
+}
+
+gd::SpecParams spec_params(const gd_grid *g, const Spec &s, double inv_kc2) {
+    gd::SpecParams sp;
+    sp.inv_kc2 = inv_kc2;
+    sp.hw = gd::grid_weight(g);
+    sp.nxc = s.nxc;
+    sp.nxs = s.nxs;
+    sp.lny = ilog2(s.ny);
+    sp.lnz = ilog2(s.nz);
+    return sp;
 }
 
 
@@ -629,9 +655,7 @@ int deconvolve_germano(int32_t solver, const gd_grid *g, double gamma, const voi
         if (rc) return rc;
     }
     const gd_grid v = spectral_grid(g, s);
-    gd::SpecParams sp;
-    sp.inv_kc2 = ik;
-    sp.nxc = s.nxc;
+    const gd::SpecParams sp = spec_params(g, s, ik);
     rc = gd::solve_uniform(solver, &v, UB, U, o, solve_work, wb - 2 * sb, info, stream, nullptr, &sp);
     if (rc) return rc;
     return f32 ? inverse<float>(s, (float *)U, (float *)u, MUL_INV_CN, ik, st)
@@ -657,9 +681,7 @@ int deconvolve_germano_autotune(int32_t solver, const gd_grid *g, double gamma, 
                             : forward<double>(s, (const double *)ubar, (double *)w, MUL_C, ik, st);
     if (rc) return rc;
     const gd_grid v = spectral_grid(g, s);
-    gd::SpecParams sp;
-    sp.inv_kc2 = ik;
-    sp.nxc = s.nxc;
+    const gd::SpecParams sp = spec_params(g, s, ik);
     return gd::tune_uniform(solver, &v, w, w + sb, w + 2 * sb, wb - 2 * sb, info, stream, out, &sp);
 }
 
