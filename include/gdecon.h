@@ -356,7 +356,9 @@ int deconvolve_germano(int32_t solver, const gd_grid *grid, double gamma, const 
                        const gd_opts *opts, void *work, size_t work_bytes, gd_info *info, void *stream);
 /* As deconvolve_autotune, for deconvolve_germano with this grid and solver:
  * times the launch configurations of the solve on the Fourier coefficients
- * of ubar and remembers the fastest (u is overwritten).  Synchronous. */
+ * of ubar and remembers the fastest.  The trials run on the workspace: u
+ * (non-NULL, as for deconvolve_germano) is not written, and ubar must not
+ * overlap the workspace.  Synchronous. */
 int deconvolve_germano_autotune(int32_t solver, const gd_grid *grid, double gamma, const void *ubar, void *u,
                                 void *work, size_t work_bytes, gd_info *info, void *stream, gd_tune_info *out);
 

@@ -673,6 +673,8 @@ int deconvolve_germano_autotune(int32_t solver, const gd_grid *g, double gamma, 
     const size_t need = germano_workspace_bytes(g, solver);
     if (wb < need) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", need, wb);
     const Spec s = spec_of(g);
+    const size_t fb = (size_t)s.batch * s.nx * s.ny * s.nz * s.tsize;
+    if (gd::ranges_overlap(ubar, fb, work, need)) return fail(GD_EINVAL, "ubar overlaps the workspace");
     const size_t sb = align_up_256((size_t)s.elems * s.tsize);
     char *w = (char *)work;
     const double ik = inv_kc2_of(g, gamma);

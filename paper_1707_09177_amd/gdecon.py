@@ -217,11 +217,24 @@ def _dev_ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
 
+def _out(out: torch.Tensor | None, shape, like: torch.Tensor, name: str = "out") -> torch.Tensor:
+    """A new output tensor shaped `shape` with like's dtype and device, or the
+    caller's, which must match exactly: the library writes through a bare
+    pointer, so a short or differently typed buffer would be overrun."""
+    shape = tuple(int(v) for v in shape)
+    if out is None:
+        return torch.empty(shape, dtype=like.dtype, device=like.device)
+    if tuple(out.shape) != shape or out.dtype != like.dtype or out.device != like.device:
+        raise ValueError(f"{name} must have shape {shape} and dtype {like.dtype} on {like.device}, "
+                         f"got {tuple(out.shape)} {out.dtype} on {out.device}")
+    return out
+
+
 def filter_apply(x: torch.Tensor, ndim: int = 2, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """y = G x with the periodic trapezoidal stencil (per field of the batch)."""
     lib = load()
     g = make_grid(x.shape, ndim, x.dtype)
-    y = torch.empty_like(x) if out is None else out
+    y = _out(out, x.shape, x)
     _check(lib.filter_apply(ctypes.byref(g), _dev_ptr(x), _dev_ptr(y), _stream_handle(stream)))
     return y
 
@@ -292,11 +305,11 @@ class Deconvolver:
     def solve(self, ubar: torch.Tensor, max_iter: int, tol: float = 0.0, init: str = "ubar",
               out: torch.Tensor | None = None, norm_ref: str = "r0ubar", history: torch.Tensor | None = None,
               wait_limit_us: int = 0, stream=None) -> SolveResult:
-        if tuple(ubar.shape) != self.shape or ubar.dtype != self.dtype:
-            raise ValueError(f"ubar must have shape {self.shape} and dtype {self.dtype}")
+        if tuple(ubar.shape) != self.shape or ubar.dtype != self.dtype or ubar.device != self.work.device:
+            raise ValueError(f"ubar must have shape {self.shape} and dtype {self.dtype} on {self.work.device}")
         if init == "given" and out is None:
             raise ValueError("init='given' reads the initial guess from `out`")
-        u = torch.empty_like(ubar) if out is None else out
+        u = _out(out, self.shape, ubar)
         o = Opts()
         o.max_iter = int(max_iter)
         o.init = INITS[init]
@@ -304,8 +317,9 @@ class Deconvolver:
         o.tol = float(tol)
         o.history = _dev_ptr(history) if history is not None else None
         o.wait_limit_us = int(wait_limit_us)
-        if history is not None and (history.dtype != torch.float64 or history.numel() < self.batch * (max_iter + 1)):
-            raise ValueError("history must be float64 with batch*(max_iter+1) entries")
+        if history is not None and (history.dtype != torch.float64 or history.numel() < self.batch * (max_iter + 1)
+                                    or history.device != ubar.device):
+            raise ValueError("history must be float64 with batch*(max_iter+1) entries, on ubar's device")
         rc = self._fn(ctypes.byref(self.grid), _dev_ptr(ubar), _dev_ptr(u), ctypes.byref(o),
                       self.work.data_ptr(), self.work.numel(), self.info_dev.data_ptr(), _stream_handle(stream))
         _check(rc)
@@ -323,7 +337,7 @@ def germano_filter(x: torch.Tensor, gamma: float, ndim: int = 2, out: torch.Tens
     if n == 0:
         raise GdError(-1, "bad grid (the differential filter needs power-of-two sizes)")
     work = torch.empty(int(n), dtype=torch.uint8, device=x.device)
-    y = torch.empty_like(x) if out is None else out
+    y = _out(out, x.shape, x)
     _check(lib.germano_filter_apply(ctypes.byref(g), float(gamma), _dev_ptr(x), _dev_ptr(y), work.data_ptr(),
                                     work.numel(), _stream_handle(stream)))
     return y
@@ -392,7 +406,9 @@ class GermanoDeconvolver(Deconvolver):
     def autotune(self, ubar: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> dict:
         """Time the launch configurations on these buffers and keep the
         fastest for later solves of this shape (deconvolve_germano_autotune)."""
-        u = torch.empty_like(ubar) if out is None else out
+        if tuple(ubar.shape) != self.shape or ubar.dtype != self.dtype or ubar.device != self.work.device:
+            raise ValueError(f"ubar must have shape {self.shape} and dtype {self.dtype} on {self.work.device}")
+        u = _out(out, self.shape, ubar)
         t = TuneInfo()
         _check(self.lib.deconvolve_germano_autotune(SOLVERS[self.solver], ctypes.byref(self.grid), self.gamma,
                                                     _dev_ptr(ubar), _dev_ptr(u), self.work.data_ptr(),
@@ -440,7 +456,7 @@ def autotune(solver: str, ubar: torch.Tensor, ndim: int = 2, out: torch.Tensor |
     the fastest for later solves of the same signature (deconvolve_autotune).
     ``out`` (or a scratch tensor) is overwritten.  Synchronous."""
     d = Deconvolver(ubar.shape, ndim, ubar.dtype, solver, device=ubar.device)
-    u = torch.empty_like(ubar) if out is None else out
+    u = _out(out, ubar.shape, ubar)
     t = TuneInfo()
     _check(d.lib.deconvolve_autotune(SOLVERS[solver], ctypes.byref(d.grid), _dev_ptr(ubar), _dev_ptr(u),
                                      d.work.data_ptr(), d.work.numel(), d.info_dev.data_ptr(),
@@ -519,8 +535,12 @@ class BatchDeconvolver:
         if len(ubars) != self.count or len(us) != self.count:
             raise ValueError(f"expected {self.count} fields")
         for i, (ub, u, sh) in enumerate(zip(ubars, us, self.shapes)):
-            if tuple(ub.shape) != sh or tuple(u.shape) != sh or ub.dtype != self.dtype or u.dtype != self.dtype:
-                raise ValueError(f"instance {i}: fields must have shape {sh} and dtype {self.dtype}")
+            if tuple(ub.shape) != sh or tuple(u.shape) != sh or ub.dtype != self.dtype or u.dtype != self.dtype \
+                    or ub.device != self.work.device or u.device != self.work.device:
+                raise ValueError(f"instance {i}: fields must have shape {sh} and dtype {self.dtype} "
+                                 f"on {self.work.device}")
+            if histories is not None and histories[i].device != self.work.device:
+                raise ValueError(f"instance {i}: history must be on {self.work.device}")
             self.list[i].ubar = _dev_ptr(ub)
             self.list[i].u = _dev_ptr(u)
             self.list[i].history = _dev_ptr(histories[i]) if histories is not None else None
@@ -531,6 +551,8 @@ class BatchDeconvolver:
             raise ValueError("init='given' reads the initial guesses from `outs`")
         us = [torch.empty_like(b) for b in ubars] if outs is None else list(outs)
         if histories is not None:
+            if len(histories) != self.count:
+                raise ValueError(f"expected {self.count} histories")
             for hst in histories:
                 if hst.dtype != torch.float64 or hst.numel() < max_iter + 1:
                     raise ValueError("each history must be float64 with max_iter+1 entries")
@@ -622,7 +644,7 @@ class WarmStart:
         return make_grid(x.shape, self.ndim, x.dtype)
 
     def _workspace(self, g: Grid, training: bool) -> torch.Tensor:
-        key = (int(g.n[0]), int(g.n[1]), int(g.batch), int(g.dtype), training)
+        key = (int(g.n[0]), int(g.n[1]), int(g.n[2]), int(g.batch), int(g.dtype), training)
         w = self._work.get(key)
         if w is None:
             n = self.lib.warmstart_workspace_bytes(ctypes.byref(self.net), ctypes.byref(g), int(training))
@@ -635,7 +657,7 @@ class WarmStart:
     def forward(self, ubar: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         """u0 for every field of ubar (launch only, no synchronisation)."""
         g = self._grid(ubar)
-        u0 = torch.empty_like(ubar) if out is None else out
+        u0 = _out(out, ubar.shape, ubar)
         w = self._workspace(g, False)
         _check(self.lib.warmstart_forward(ctypes.byref(self.net), ctypes.byref(g), _dev_ptr(ubar), _dev_ptr(u0),
                                           w.data_ptr(), w.numel(), _stream_handle(stream)))
@@ -644,7 +666,7 @@ class WarmStart:
     def train_step(self, ubar: torch.Tensor, u: torch.Tensor, stream=None) -> torch.Tensor:
         """One Adam step on the pairs (ubar, u); returns the device loss (before
         the update).  Launch only."""
-        if ubar.shape != u.shape or ubar.dtype != u.dtype:
+        if ubar.shape != u.shape or ubar.dtype != u.dtype or ubar.device != u.device:
             raise ValueError("ubar and u must match")
         g = self._grid(ubar)
         w = self._workspace(g, True)
@@ -666,8 +688,9 @@ def closure_stress(ubar: torch.Tensor, ustar: torch.Tensor, ndim: int, out: torc
     lead = tuple(ubar.shape[:-ndim - 1])
     g = make_grid(lead + (1,) + tuple(ubar.shape[-ndim:]), ndim, ubar.dtype)
     np_ = ndim * (ndim + 1) // 2
-    tau = torch.empty(lead + (np_,) + tuple(ubar.shape[-ndim:]), dtype=ubar.dtype, device=ubar.device) \
-        if out is None else out
+    if ustar.device != ubar.device:
+        raise ValueError("ubar and ustar must be on one device")
+    tau = _out(out, lead + (np_,) + tuple(ubar.shape[-ndim:]), ubar)
     _check(load().closure_stress(ctypes.byref(g), _dev_ptr(ubar), _dev_ptr(ustar), _dev_ptr(tau),
                                  _stream_handle(stream)))
     return tau

@@ -190,3 +190,22 @@ def test_germano_host_side_validation():
                                   info, None) == -1
     assert lib.deconvolve_germano(2, ctypes.byref(g), 0.1, 0x10000, 0x40000, ctypes.byref(o), 0x1000000, 16,
                                   info, None) == -2
+    t = gdecon.TuneInfo()
+    assert lib.deconvolve_germano_autotune(2, ctypes.byref(g), 0.1, 0x1000100, 0x40000, 0x1000000, 1 << 30, info,
+                                           None, ctypes.byref(t)) == -1
+    assert "overlaps the workspace" in lib.gd_last_error().decode()
+    assert lib.deconvolve_germano_autotune(2, ctypes.byref(g), 0.1, 0x10000, 0x40000, 0x1000000, 16, info,
+                                           None, ctypes.byref(t)) == -2
+
+
+def test_binding_output_check_on_host():
+    """The binding's output check (shape, dtype, device must match exactly)."""
+    from paper_1707_09177_amd import gdecon
+    torch = gdecon.torch
+    x = torch.zeros(2, 3, dtype=torch.float32)
+    assert gdecon._out(None, (2, 3), x).shape == (2, 3)
+    y = torch.zeros(2, 3)
+    assert gdecon._out(y, (2, 3), x) is y
+    for bad in (torch.zeros(2, 2), torch.zeros(3, 2), torch.zeros(2, 3, dtype=torch.float64)):
+        with pytest.raises(ValueError):
+            gdecon._out(bad, (2, 3), x)
