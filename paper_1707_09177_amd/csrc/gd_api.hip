@@ -181,10 +181,20 @@ int validate_grid(const gd_grid *g) {
     for (int d = 0; d < g->ndim; ++d)
         if (g->n[d] < 1) return fail(GD_EINVAL, "n[%d] must be >= 1", d);
     if (g->batch < 1) return fail(GD_EINVAL, "batch must be >= 1");
-    const int64_t npts = g->n[0] * g->n[1] * (g->ndim == 3 ? g->n[2] : 1);
-    if (g->n[0] > (int64_t(1) << 31) || npts > (int64_t(1) << 40) || g->batch > (int64_t(1) << 30))
+    const int64_t npts = checked_points(g->n, g->ndim, int64_t(1) << 40);
+    if (npts < 0 || g->n[0] > (int64_t(1) << 31) || g->batch > (int64_t(1) << 30) ||
+        g->batch > kMaxTotalPoints / npts)
         return fail(GD_EINVAL, "field too large");
     return GD_OK;
+}
+
+int64_t checked_points(const int64_t *n, int ndim, int64_t cap) {
+    int64_t p = 1;
+    for (int d = 0; d < ndim; ++d) {
+        if (n[d] < 1 || n[d] > cap / p) return -1;
+        p *= n[d];
+    }
+    return p;
 }
 
 int64_t grid_points(const gd_grid *g) { return g->n[0] * g->n[1] * (g->ndim == 3 ? g->n[2] : 1); }
@@ -525,9 +535,20 @@ int validate_instance(const gd_instance &d, int i) {
     if (d.ndim != 2 && d.ndim != 3) return fail(GD_EINVAL, "instance %d: ndim must be 2 or 3", i);
     for (int k = 0; k < d.ndim; ++k)
         if (d.n[k] < 1) return fail(GD_EINVAL, "instance %d: n[%d] must be >= 1", i, k);
-    const int64_t npts = inst_points(d);
-    if (d.n[0] > (int64_t(1) << 31) || npts > (int64_t(1) << 40))
+    if (checked_points(d.n, d.ndim, int64_t(1) << 40) < 0 || d.n[0] > (int64_t(1) << 31))
         return fail(GD_EINVAL, "instance %d: field too large", i);
+    return GD_OK;
+}
+
+// every instance valid, and all of them together within kMaxTotalPoints
+int validate_instances(const gd_instance *list, int32_t count) {
+    int64_t tot = 0;
+    for (int i = 0; i < count; ++i) {
+        const int rc = validate_instance(list[i], i);
+        if (rc) return rc;
+        tot += inst_points(list[i]);  // each at most 2^40: no overflow before the test below
+        if (tot > kMaxTotalPoints) return fail(GD_EINVAL, "the instances hold too many points");
+    }
     return GD_OK;
 }
 
@@ -607,8 +628,8 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
     int rc = validate_opts(o);
     if (rc) return rc;
     if (!info) return fail(GD_EINVAL, "info must be non-NULL");
+    if ((rc = validate_instances(list, count))) return rc;
     for (int i = 0; i < count; ++i) {
-        if ((rc = validate_instance(list[i], i))) return rc;
         if (!list[i].ubar || !list[i].u) return fail(GD_EINVAL, "instance %d: ubar and u must be non-NULL", i);
     }
     if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
@@ -907,8 +928,7 @@ int deconvolve_steepest_descent(const gd_grid *g, const void *ubar, void *u, con
 size_t deconvolve_batch_workspace_bytes(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count) {
     if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return 0;
     if ((dtype != GD_F32 && dtype != GD_F64) || !list || count < 1) return 0;
-    for (int i = 0; i < count; ++i)
-        if (validate_instance(list[i], i)) return 0;
+    if (validate_instances(list, count)) return 0;
     return batch_layout(solver, dtype, list, count).total;
 }
 
@@ -974,9 +994,8 @@ int gd_tune_set_batch(int32_t solver, int32_t dtype, const gd_instance *list, in
                       const gd_tune_info *choice) {
     if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
     if ((dtype != GD_F32 && dtype != GD_F64) || !list || count < 1) return fail(GD_EINVAL, "bad instance list");
-    int rc;
-    for (int i = 0; i < count; ++i)
-        if ((rc = validate_instance(list[i], i))) return rc;
+    int rc = validate_instances(list, count);
+    if (rc) return rc;
     TuneCfg cfg;
     if ((rc = tune_choice(choice, &cfg))) return rc;
     tune_store(key_batch(solver, dtype, list, count), cfg);

@@ -198,7 +198,8 @@ int closure_stress(const gd_grid *g, const void *ubar, const void *ustar, void *
     if (g->dtype != GD_F32 && g->dtype != GD_F64) return fail(GD_EINVAL, "dtype must be GD_F32 or GD_F64");
     const int64_t nx = g->n[0], ny = g->n[1], nz = g->ndim == 3 ? g->n[2] : 1;
     if (nx < 1 || ny < 1 || nz < 1 || g->batch < 1) return fail(GD_EINVAL, "sizes must be >= 1");
-    if (nx >= (1 << 30) || ny >= (1 << 30) || nz >= (1 << 30) || nx * ny * nz > (int64_t(1) << 36))
+    const int64_t npts = gd::checked_points(g->n, g->ndim, int64_t(1) << 36);
+    if (nx >= (1 << 30) || ny >= (1 << 30) || nz >= (1 << 30) || npts < 0 || g->batch > gd::kMaxTotalPoints / npts)
         return fail(GD_EINVAL, "field too large");
     if (!ubar || !ustar || !tau) return fail(GD_EINVAL, "ubar, ustar and tau must be non-NULL");
     const size_t ts = g->dtype == GD_F32 ? 4 : 8;

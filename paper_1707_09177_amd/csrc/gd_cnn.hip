@@ -43,6 +43,7 @@
 
 namespace gd {
 void set_error_text(const char *msg);
+int64_t checked_points(const int64_t *n, int ndim, int64_t cap);
 }
 
 namespace gdcnn {
@@ -672,9 +673,10 @@ int check_grid(const gd_cnn *net, const gd_grid *g) {
     if (g->dtype != GD_F32 && g->dtype != GD_F64) return fail(GD_EINVAL, "dtype must be GD_F32 or GD_F64");
     if (g->n[0] < 1 || g->n[1] < 1 || g->batch < 1 || (g->ndim == 3 && g->n[2] < 1))
         return fail(GD_EINVAL, "sizes must be >= 1");
-    const int64_t planes = planes_of(g);
-    if (g->n[0] * g->n[1] >= (int64_t(1) << 31) || g->n[0] * g->n[1] * planes > (int64_t(1) << 34) ||
-        g->batch > 65535 || planes > (int64_t(1) << 24))
+    // bound the factors before multiplying them
+    if (g->batch > 65535 || (g->ndim == 3 && g->n[2] > (int64_t(1) << 24))) return fail(GD_EINVAL, "field too large");
+    const int64_t planes = planes_of(g), n01 = gd::checked_points(g->n, 2, (int64_t(1) << 31) - 1);
+    if (n01 < 0 || planes > (int64_t(1) << 24) || planes > (int64_t(1) << 34) / n01)
         return fail(GD_EINVAL, "field too large");
     return GD_OK;
 }

@@ -206,6 +206,12 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
 int tune_uniform(int solver, const gd_grid *g, const void *ubar, void *u, void *work, size_t wb, gd_info *info,
                  void *stream, gd_tune_info *out, const SpecParams *spec);
 int validate_grid(const gd_grid *g);
+// n[0] * ... * n[ndim - 1] when every extent is >= 1 and the product is at
+// most cap, else -1 (computed without overflow for any extents)
+int64_t checked_points(const int64_t *n, int ndim, int64_t cap);
+// largest batch * points a grid may describe: keeps every byte count of a
+// call (fields, workspace) far from overflowing 64 bits
+constexpr int64_t kMaxTotalPoints = int64_t(1) << 46;
 double grid_weight(const gd_grid *g);
 // error text for gd_last_error, then the code; every entry point reports through it
 int fail(int code, const char *fmt, ...);

@@ -209,3 +209,41 @@ def test_binding_output_check_on_host():
     for bad in (torch.zeros(2, 2), torch.zeros(3, 2), torch.zeros(2, 3, dtype=torch.float64)):
         with pytest.raises(ValueError):
             gdecon._out(bad, (2, 3), x)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgdecon.so not built")
+def test_sizes_that_would_overflow_are_rejected():
+    """Extents whose product passes 2^63, and batches whose byte counts would
+    pass it, are refused on the host: no size computation wraps round."""
+    from paper_1707_09177_amd import gdecon
+    lib = gdecon.load()
+
+    def grid(n, batch=1, ndim=3):
+        g = gdecon.Grid()
+        g.ndim, g.dtype, g.batch = ndim, 1, batch
+        for d in range(3):
+            g.n[d] = n[d]
+        return g
+
+    for n, b in [((2, 1 << 62, 2), 1), ((1 << 20, 1 << 40, 1 << 20), 1), ((1024, 1024, 1), 1 << 30)]:
+        g = grid(n, b)
+        assert lib.deconvolve_workspace_bytes(ctypes.byref(g), 2) == 0
+        assert lib.filter_apply(ctypes.byref(g), 4096, 8192, None) == -1
+        assert "too large" in lib.gd_last_error().decode()
+    g = grid((1 << 29, 1 << 29, 1 << 29))
+    assert lib.closure_stress(ctypes.byref(g), 1 << 20, 2 << 20, 3 << 20, None) == -1
+    assert "too large" in lib.gd_last_error().decode()
+    net = gdecon.Cnn()
+    net.ndim, net.channels, net.layers, net.params = 2, 32, 6, 4096
+    assert lib.warmstart_workspace_bytes(ctypes.byref(net), ctypes.byref(grid((1 << 40, 1 << 40, 1), ndim=2)), 0) == 0
+    assert lib.warmstart_workspace_bytes(ctypes.byref(net), ctypes.byref(grid((64, 64, 1), 1 << 40, 2)), 0) == 0
+    assert lib.warmstart_workspace_bytes(ctypes.byref(net), ctypes.byref(grid((64, 64, 1), 4, 2)), 0) > 0
+
+    def instances(k):
+        lst = (gdecon.Instance * k)()
+        for i in range(k):
+            lst[i].ndim = 2
+            lst[i].n[0], lst[i].n[1], lst[i].n[2] = 1 << 20, 1 << 20, 1
+        return lst
+    assert lib.deconvolve_batch_workspace_bytes(2, 1, instances(64), 64) > 0   # 2^46 points in all
+    assert lib.deconvolve_batch_workspace_bytes(2, 1, instances(65), 65) == 0
