@@ -313,8 +313,10 @@ int warmstart_train_step(const gd_cnn *net, const gd_grid *grid, const void *uba
  * that stops inside a sweep has that sweep recomputed with the exact pass
  * count, so pass counts, statuses and histories match the one-pass solve.
  * Any grid size.  vancittert_blocked_passes() gives K (8 in 2D, 2 in 3D).
- * The call is a sequence of ceil(max_iter / K) + 4 stream-ordered launches;
- * a launch after every field has stopped costs one state read per tile.
+ * The call is a sequence of 2 ceil(max_iter / K) + 7 stream-ordered launches
+ * (one more with a history), so max_iter is limited to 2^20 (GD_EINVAL
+ * above); a launch after every field has stopped costs one state read per
+ * tile.
  */
 size_t vancittert_blocked_workspace_bytes(const gd_grid *grid);
 int32_t vancittert_blocked_passes(const gd_grid *grid);

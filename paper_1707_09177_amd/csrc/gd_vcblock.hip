@@ -454,8 +454,8 @@ __global__ __launch_bounds__(256) void k_vcb_finish_reduce(Args A, double hw_sqr
 
 // history entries are norms without the spacing weight until scaled here
 __global__ void k_vcb_hist_scale(double *hist, int64_t n, double w) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) hist[i] *= w;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        hist[i] *= w;
 }
 
 __global__ void k_vcb_prep(VState *st, Global *glob, int64_t nfields) {
@@ -480,6 +480,9 @@ void tiles_of(const gd_grid *g, int64_t &tx, int64_t &ty, int64_t &tz) {
     ty = (g->n[1] + S::TY - 1) / S::TY;
     tz = NDIM == 3 ? (g->n[2] + S::TZ - 1) / S::TZ : 1;
 }
+
+// the host issues two launches per sweep of K passes, up to max_iter passes
+constexpr int kMaxBlockedIter = 1 << 20;
 
 struct Layout {
     size_t glob, st, part, r0, r1, u1, total;
@@ -567,8 +570,8 @@ int run(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *wor
     hipLaunchKernelGGL(k_vcb_finish_reduce, per_field, dim3(256), 0, st, A, sqrt(hw));
     if (o->history) {
         const int64_t nh = g->batch * (int64_t)(o->max_iter + 1);
-        hipLaunchKernelGGL(k_vcb_hist_scale, dim3((unsigned)((nh + 255) / 256)), dim3(256), 0, st, o->history, nh,
-                           sqrt(hw));
+        hipLaunchKernelGGL(k_vcb_hist_scale, dim3((unsigned)std::min<int64_t>((nh + 255) / 256, 4096)), dim3(256), 0,
+                           st, o->history, nh, sqrt(hw));
     }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GD_OK : fail(GD_EHIP, "blocked Van Cittert launch: %s", hipGetErrorString(e));
@@ -597,6 +600,8 @@ int deconvolve_vancittert_blocked(const gd_grid *g, const void *ubar, void *u, c
     int rc = gd::validate_grid(g);
     if (rc) return rc;
     if ((rc = gd::validate_opts(o))) return rc;
+    if (o->max_iter > kMaxBlockedIter)
+        return fail(GD_EINVAL, "max_iter must be at most %d (the host launches every sweep)", kMaxBlockedIter);
     if (!ubar || !u || !info) return fail(GD_EINVAL, "ubar, u and info must be non-NULL");
     if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
     if ((uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be 256-byte aligned");

@@ -247,3 +247,17 @@ def test_sizes_that_would_overflow_are_rejected():
         return lst
     assert lib.deconvolve_batch_workspace_bytes(2, 1, instances(64), 64) > 0   # 2^46 points in all
     assert lib.deconvolve_batch_workspace_bytes(2, 1, instances(65), 65) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgdecon.so not built")
+def test_blocked_vancittert_limits_max_iter():
+    """The blocked Van Cittert issues its sweeps from the host, so max_iter is
+    bounded (2^20); the check comes before any launch."""
+    from paper_1707_09177_amd import gdecon
+    lib = gdecon.load()
+    g = gdecon.make_grid((64, 32), 2, gdecon.torch.float32)
+    ws = lib.vancittert_blocked_workspace_bytes(ctypes.byref(g))
+    o = gdecon._make_opts((1 << 20) + 1, 0.0, "ubar", "r0ubar", None, 0)
+    assert lib.deconvolve_vancittert_blocked(ctypes.byref(g), 1 << 20, 2 << 20, ctypes.byref(o), 4 << 20, ws,
+                                             8 << 20, None) == -1
+    assert "max_iter" in lib.gd_last_error().decode()
