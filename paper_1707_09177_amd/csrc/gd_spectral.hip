@@ -542,18 +542,22 @@ __global__ __launch_bounds__(256) void k_spectrum_part(const T *X, double *part,
 
 // out[b][s] = sum over chunks in chunk order
 __global__ void k_spectrum_reduce(const double *part, double *out, int64_t nchunks, int64_t nshells, int64_t batch) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= batch * nshells) return;
-    const int64_t b = t / nshells, sh = t % nshells;
-    double acc = 0.0;
-    for (int64_t c = 0; c < nchunks; ++c) acc += part[(b * nchunks + c) * nshells + sh];
-    out[t] = acc;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < batch * nshells;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = t / nshells, sh = t % nshells;
+        double acc = 0.0;
+        for (int64_t c = 0; c < nchunks; ++c) acc += part[(b * nchunks + c) * nshells + sh];
+        out[t] = acc;
+    }
 }
 
 __global__ void k_zero_i64(int64_t *p, int64_t n) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) p[t] = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = 0;
 }
+
+// blocks of 256 threads for a grid-stride loop over n items
+unsigned stride_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
 
 // PDF bin counts: LDS counters per workgroup (one field's chunk), then one
 // global integer atomic per nonzero bin.
@@ -733,8 +737,7 @@ int energy_spectrum(const gd_grid *g, double kpow, const void *x, double *out, v
                            part, rows, rpc, nch, ns, s, kpow);
     }
     const int64_t tot = s.batch * ns;
-    hipLaunchKernelGGL(k_spectrum_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, out, nch, ns,
-                       s.batch);
+    hipLaunchKernelGGL(k_spectrum_reduce, dim3(stride_blocks(tot)), dim3(256), 0, st, part, out, nch, ns, s.batch);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GD_OK : fail(GD_EHIP, "spectrum launch: %s", hipGetErrorString(e));
 }
@@ -751,7 +754,7 @@ int pdf_counts(const gd_grid *g, double lo, double hi, int32_t nbins, const void
         return fail(GD_EINVAL, "counts overlaps x");
     hipStream_t st = (hipStream_t)stream;
     const int64_t nc = g->batch * nbins;
-    hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, counts, nc);
+    hipLaunchKernelGGL(k_zero_i64, dim3(stride_blocks(nc)), dim3(256), 0, st, counts, nc);
     const int64_t chunk = std::max<int64_t>(4096, (npts * g->batch + 2047) / 2048);
     const int64_t nch = (npts + chunk - 1) / chunk;
     const double scale = (double)nbins / (hi - lo);
