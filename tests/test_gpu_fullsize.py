@@ -1,0 +1,66 @@
+"""The headline solves at full size, in the launch configuration the
+benchmark times: the autotuned persistent launch, BiCGSTAB, FP32 storage,
+max_iter 500, relative residual 1e-6, on 16 fields of 2048^2 (E ~ k^-3) and
+on the 3 components of a 256^3 velocity (E ~ k^-5/3).
+
+The oracle (FP64, one thread) cannot solve every field within a test, so
+- every field: status CONVERGED, with the true relative residual the library
+  reports within twice the tolerance (the FP32 rounding floor: the updates
+  are FP32, so the recurrence's residual and the true one part at about
+  1e-7 of r_ref);
+- sampled fields: the oracle's pass count to the same tolerance, within one
+  pass (FP32 rounding can move a residual that sits on the threshold across
+  it); where the counts agree, u against the oracle's, relative L2 within
+  1e-5 (the FP32 tolerance of the small-size tests); and the true residual
+  ||ubar - G u|| recomputed by the oracle in FP64 from the GPU's u, within
+  twice the tolerance.
+ubar is the oracle's FP64 filter of the fields, rounded to FP32 once.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import filtered_input, rel_l2, to_dev
+from paper_1707_09177_amd import gdecon, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+MAX_ITER = 500
+F32_TOL = 1e-5
+
+# (ndim, grid size, fields, fields checked against the oracle)
+CASES = {"2048sq_x16": (2, 2048, 16, (0, 15)), "256cube_x3": (3, 256, 3, (2,))}
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("case", list(CASES))
+def test_headline_workload_at_full_size(case):
+    nd, n, count, sampled = CASES[case]
+    u = synth.config_fields(nd, n=n, count=count, dtype=np.float32)
+    ub = filtered_input(u.astype(np.float64), nd, torch.float32)
+    del u
+    dub = to_dev(ub, torch.float32)
+    out = torch.empty_like(dub)
+    tune = gdecon.autotune("bicgstab", dub, ndim=nd, out=out)
+    assert tune["candidates"] > 1
+    d = gdecon.Deconvolver(dub.shape, nd, torch.float32, "bicgstab")
+    infos = d.solve(dub, MAX_ITER, TOL, out=out).info()
+    print(case, "launch", gdecon.last_launch(), "passes", [i["iters"] for i in infos])
+    for b, inf in enumerate(infos):
+        assert inf["status_name"] == "CONVERGED", (b, inf)
+        assert inf["r_true"] <= 2 * TOL * inf["r_ref"], (b, inf)
+    got = out.double().cpu().numpy()
+    del dub, out
+    for b in sampled:
+        want, winf, _ = oracle.solve("bicgstab", ub[b], nd, MAX_ITER, tol=TOL)
+        assert winf[0]["status_name"] == "CONVERGED"
+        assert abs(infos[b]["iters"] - winf[0]["iters"]) <= 1, (b, infos[b]["iters"], winf[0]["iters"])
+        if infos[b]["iters"] == winf[0]["iters"]:   # same passes and the same exit: u agrees to FP32 rounding
+            e = rel_l2(got[b], want)
+            print(case, "field", b, "rel L2 vs oracle %.2e" % e)
+            assert e <= F32_TOL
+        r_ref = np.linalg.norm(ub[b] - oracle.filter(ub[b], nd))
+        r = np.linalg.norm(ub[b] - oracle.filter(got[b], nd))
+        assert r <= 2 * TOL * r_ref, (b, r / r_ref)
