@@ -261,3 +261,33 @@ def test_blocked_vancittert_limits_max_iter():
     assert lib.deconvolve_vancittert_blocked(ctypes.byref(g), 1 << 20, 2 << 20, ctypes.byref(o), 4 << 20, ws,
                                              8 << 20, None) == -1
     assert "max_iter" in lib.gd_last_error().decode()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libgdecon.so not built")
+def test_empty_inputs_are_rejected():
+    """An empty batch or a zero extent is an argument error (GD_EINVAL) for
+    every entry point, reported before any launch; workspace queries give 0."""
+    from paper_1707_09177_amd import gdecon
+    lib = gdecon.load()
+    o = gdecon._make_opts(3, 0.0, "ubar", "r0ubar", None, 0)
+    info = ctypes.c_void_p(0x1000)
+    for shape, batch in [((0, 64), 1), ((64, 0), 1), ((64, 64), 0), ((0, 8, 8), 1), ((8, 8, 0), 1)]:
+        g = gdecon.Grid()
+        g.ndim, g.dtype, g.batch = len(shape), 1, batch
+        for d in range(3):
+            g.n[d] = shape[::-1][d] if d < len(shape) else 1
+        gr = ctypes.byref(g)
+        assert lib.deconvolve_workspace_bytes(gr, 2) == 0
+        assert lib.germano_workspace_bytes(gr, 2) == 0
+        assert lib.spectrum_workspace_bytes(gr) == 0
+        assert lib.vancittert_blocked_workspace_bytes(gr) == 0
+        for rc in (lib.filter_apply(gr, 1 << 20, 2 << 20, None),
+                   lib.deconvolve_bicgstab(gr, 1 << 20, 2 << 20, ctypes.byref(o), 4 << 20, 1 << 30, info, None),
+                   lib.deconvolve_vancittert_blocked(gr, 1 << 20, 2 << 20, ctypes.byref(o), 4 << 20, 1 << 30, info,
+                                                     None),
+                   lib.deconvolve_germano(2, gr, 0.1, 1 << 20, 2 << 20, ctypes.byref(o), 4 << 20, 1 << 30, info, None),
+                   lib.germano_filter_apply(gr, 0.1, 1 << 20, 2 << 20, 4 << 20, 1 << 30, None),
+                   lib.energy_spectrum(gr, 0.0, 1 << 20, 2 << 20, 4 << 20, 1 << 30, None),
+                   lib.pdf_counts(gr, -1.0, 1.0, 10, 1 << 20, 2 << 20, None)):
+            assert rc == -1, (shape, batch, lib.gd_last_error().decode())
+        assert ">= 1" in lib.gd_last_error().decode()
