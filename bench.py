@@ -178,10 +178,10 @@ def make_batch_inputs(w, torch, gd, dev):
     return sizes, shapes, us, ubars
 
 
-def time_batch(gd, torch, shapes, ubars, solver, steps, warmup, tol=1e-6, max_iter=500):
+def time_batch(gd, torch, shapes, ubars, solver, steps, warmup, tol=1e-6, max_iter=500, tune=True):
     b = gd.BatchDeconvolver(shapes, ubars[0].dtype, solver)
     outs = [torch.empty_like(x) for x in ubars]
-    tune = b.autotune(ubars, outs)           # first-call tuning, outside the timed region
+    tune = b.autotune(ubars, outs) if tune else None   # first-call tuning, outside the timed region
     for _ in range(warmup):
         b.solve(ubars, max_iter, tol, outs=outs)
     torch.cuda.synchronize()
@@ -226,10 +226,16 @@ def main_batch(args, w, torch, gd, dev):
     sizes, shapes, us, ubars = make_batch_inputs(w, torch, gd, dev)
     npts = int(sum(int(np.prod(s)) for s in shapes))
     itemsize = ubars[0].element_size()
+    solvers = [x for x in args.solvers.split(",") if x != "vcb"]   # uneven batches: the persistent solvers
+    if args.tune_only:
+        for s in solvers:
+            b = gd.BatchDeconvolver(shapes, ubars[0].dtype, s)
+            print(json.dumps({"solver": s, "tune": b.autotune(ubars, [torch.empty_like(x) for x in ubars])}))
+        return
     results = {}
-    for s in [x for x in args.solvers.split(",") if x != "vcb"]:   # uneven batches: the persistent solvers
+    for s in solvers:
         r = time_batch(gd, torch, shapes, ubars, s, args.steps if s == "bicgstab" else max(3, args.steps // 2),
-                       args.warmup)
+                       args.warmup, tune=not args.no_tune)
         iters = [i["iters"] for i in r["info"]]
         st = sorted({i["status_name"] for i in r["info"]})
         worst_true = max(i["r_true"] / i["r_ref"] for i in r["info"])
