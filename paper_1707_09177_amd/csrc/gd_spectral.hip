@@ -540,14 +540,24 @@ __global__ __launch_bounds__(256) void k_spectrum_part(const T *X, double *part,
     for (int64_t i = threadIdx.x; i < nshells; i += 256) dst[i] = bins[i];
 }
 
-// out[b][s] = sum over chunks in chunk order
-__global__ void k_spectrum_reduce(const double *part, double *out, int64_t nchunks, int64_t nshells, int64_t batch) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < batch * nshells;
-         t += (int64_t)gridDim.x * blockDim.x) {
+// out[b][s] = sum over the chunks' partial sums: one workgroup per (field,
+// shell), thread j adding chunks j, j + 256, ... in order, then a fixed tree
+// over the threads, so the result does not depend on timing.
+__global__ __launch_bounds__(256) void k_spectrum_reduce(const double *part, double *out, int64_t nchunks,
+                                                         int64_t nshells, int64_t batch) {
+    __shared__ double red[256];
+    for (int64_t t = blockIdx.x; t < batch * nshells; t += gridDim.x) {
         const int64_t b = t / nshells, sh = t % nshells;
         double acc = 0.0;
-        for (int64_t c = 0; c < nchunks; ++c) acc += part[(b * nchunks + c) * nshells + sh];
-        out[t] = acc;
+        for (int64_t c = threadIdx.x; c < nchunks; c += 256) acc += part[(b * nchunks + c) * nshells + sh];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[t] = red[0];
+        __syncthreads();
     }
 }
 
@@ -737,7 +747,8 @@ int energy_spectrum(const gd_grid *g, double kpow, const void *x, double *out, v
                            part, rows, rpc, nch, ns, s, kpow);
     }
     const int64_t tot = s.batch * ns;
-    hipLaunchKernelGGL(k_spectrum_reduce, dim3(stride_blocks(tot)), dim3(256), 0, st, part, out, nch, ns, s.batch);
+    hipLaunchKernelGGL(k_spectrum_reduce, dim3((unsigned)std::min<int64_t>(tot, 8192)), dim3(256), 0, st, part, out,
+                       nch, ns, s.batch);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GD_OK : fail(GD_EHIP, "spectrum launch: %s", hipGetErrorString(e));
 }
