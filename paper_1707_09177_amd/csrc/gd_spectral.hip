@@ -488,6 +488,17 @@ int64_t num_shells(const Spec &s) {
     return shell_of(a * a + b * b + c * c) + 1;
 }
 
+// |k|^kpow = (k^2)^(kpow/2) for k^2 >= 1.  For kpow/2 = ipow, an integer in
+// [-2, 2] (kIpowNone otherwise), the power is formed from the integer k^2 by
+// exact products and at most one correctly rounded division instead of pow().
+constexpr int kIpowNone = 99;
+__device__ __forceinline__ double kpow_of(int64_t k2, double kpow, int ipow) {
+    if (ipow == kIpowNone) return pow((double)k2, 0.5 * kpow);
+    const double x = (double)k2;  // k^2 < 2^26 here, so x * x is exact
+    const double r = (ipow == 2 || ipow == -2) ? x * x : x;
+    return ipow > 0 ? r : 1.0 / r;
+}
+
 // Partial shell sums of one chunk of rows of one field's stored spectrum:
 // 1/2 w(k_x) |X / N|^2 |k|^p per coefficient, accumulated per shell in LDS.
 // A wave takes whole rows; along a row |k| grows with k_x, so the lanes of a
@@ -496,7 +507,7 @@ int64_t num_shells(const Spec &s) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_spectrum_part(const T *X, double *part, int64_t rows_per_field,
                                                        int64_t rows_per_chunk, int64_t nchunks, int64_t nshells, Spec s,
-                                                       double kpow) {
+                                                       double kpow, int ipow) {
     using V = typename V2<T>::t;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     double *bins = reinterpret_cast<double *>(lds_raw);
@@ -520,7 +531,7 @@ __global__ __launch_bounds__(256) void k_spectrum_part(const T *X, double *part,
                 const int64_t k2 = kx * kx + kyz2;
                 const double w = (kx == 0 || 2 * kx == s.nx) ? 0.5 : 1.0;
                 double kp = 1.0;
-                if (kpow != 0.0) kp = k2 > 0 ? pow((double)k2, 0.5 * kpow) : 0.0;
+                if (kpow != 0.0) kp = k2 > 0 ? kpow_of(k2, kpow, ipow) : 0.0;
                 v = w * ((double)z.x * (double)z.x + (double)z.y * (double)z.y) * inv_n2 * kp;
                 key = shell_of(k2);
             }
@@ -735,16 +746,18 @@ int energy_spectrum(const gd_grid *g, double kpow, const void *x, double *out, v
     if ((size_t)ns * sizeof(double) > kLdsBudget) return fail(GD_EINVAL, "too many shells");
     hipStream_t st = (hipStream_t)stream;
     double *part = (double *)((char *)work + align_up_256((size_t)s.elems * s.tsize));
+    const double hp = 0.5 * kpow;
+    const int ipow = (hp == std::floor(hp) && std::fabs(hp) <= 2.0 && hp != 0.0) ? (int)hp : kIpowNone;
     const int64_t rows = s.ny * s.nz, rpc = (rows + nch - 1) / nch;
     const dim3 grid((unsigned)(s.batch * nch));
     if (g->dtype == GD_F32) {
         if ((rc = forward<float>(s, (const float *)x, (float *)work, MUL_NONE, 0.0, st))) return rc;
         hipLaunchKernelGGL(k_spectrum_part<float>, grid, dim3(256), ns * sizeof(double), st, (const float *)work, part,
-                           rows, rpc, nch, ns, s, kpow);
+                           rows, rpc, nch, ns, s, kpow, ipow);
     } else {
         if ((rc = forward<double>(s, (const double *)x, (double *)work, MUL_NONE, 0.0, st))) return rc;
         hipLaunchKernelGGL(k_spectrum_part<double>, grid, dim3(256), ns * sizeof(double), st, (const double *)work,
-                           part, rows, rpc, nch, ns, s, kpow);
+                           part, rows, rpc, nch, ns, s, kpow, ipow);
     }
     const int64_t tot = s.batch * ns;
     hipLaunchKernelGGL(k_spectrum_reduce, dim3((unsigned)std::min<int64_t>(tot, 8192)), dim3(256), 0, st, part, out,

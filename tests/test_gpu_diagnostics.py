@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("shape", [(8, 8), (2, 2), (16, 64), (256, 128), (4, 4, 4), (8, 16, 32), (2, 2, 2)])
-@pytest.mark.parametrize("kpow", [0.0, -2.0, 2.0])
+@pytest.mark.parametrize("kpow", [0.0, -2.0, 2.0, -4.0, -5.0 / 3.0, 1.0])
 def test_spectrum_matches_oracle(shape, dtype, kpow):
     nd = len(shape)
     x = np.random.default_rng(5 + len(shape)).standard_normal((3,) + shape)
