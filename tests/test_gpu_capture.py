@@ -1,8 +1,8 @@
 """Graph capture of the stream-ordered entry points added beside the solve:
 the differential-filter solve (FFTs + persistent solve), the blocked Van
 Cittert (its launch sequence, including the recomputation of a stopped
-sweep), the closure stress, the PDF counts (cleared by a kernel) and the
-energy spectrum.  Every replay, with unrelated eager work between replays,
+sweep), the closure stress, the PDF counts (cleared by a kernel), the
+energy spectrum, and the warm start's forward pass and Adam step.  Every replay, with unrelated eager work between replays,
 must reproduce the eager result: bit for bit, except the spectrum, whose
 per-workgroup shell sums are added by unordered LDS atomics (within 1e-12).
 """
@@ -89,3 +89,35 @@ def test_closure_pdf_spectrum_capture():
         assert torch.equal(tau, e_tau), rep
         assert torch.equal(c2, e_counts), rep
         assert torch.allclose(s2, e_spec, rtol=1e-12, atol=0), rep
+
+
+def test_warm_start_capture():
+    """The warm start's forward pass and one Adam step captured together: every
+    replay matches the same calls made eagerly on a twin network (same
+    parameters and step count), bit for bit: outputs, loss and parameters."""
+    from paper_1707_09177_amd import synth
+    p = synth.cnn_init_params(0)
+    g0 = torch.Generator(DEV).manual_seed(11)
+    x = torch.randn(2, 64, 96, device=DEV, generator=g0)
+    u = torch.randn(2, 64, 96, device=DEV, generator=g0)
+    eager, cap = gdecon.WarmStart(p, lr=1e-3), gdecon.WarmStart(p, lr=1e-3)
+    out_e, out_c = torch.empty_like(x), torch.empty_like(x)
+    for ws, out in ((eager, out_e), (cap, out_c)):     # workspaces are allocated here, outside the capture
+        ws.forward(x, out=out)
+        ws.train_step(x, u)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cap.forward(x, out=out_c)
+        cap.train_step(x, u)
+    for rep in range(3):
+        out_c.fill_(float("nan"))
+        (torch.randn(1 << 20, device=DEV) * 2).sum().item()
+        g.replay()
+        eager.forward(x, out=out_e)
+        eager.train_step(x, u)
+        torch.cuda.synchronize()
+        assert torch.equal(out_c, out_e), rep
+        assert torch.equal(cap.loss, eager.loss), rep
+        assert torch.equal(cap.params, eager.params), rep
+        assert torch.equal(cap.step, eager.step), rep
