@@ -276,6 +276,10 @@ class Deconvolver:
 
     ``solve`` only launches kernels on the stream (no allocation when ``out``
     and ``info`` buffers are reused), so it can be timed or graph-captured.
+    Each solve is one persistent launch that fills the GPU: run solves on one
+    GPU one after another (one stream, or a batch in one call), not
+    concurrently on several streams, where launches that split the GPU wait
+    at their grid barriers until the wait bound ends them (GD_TIMEOUT).
     """
 
     def __init__(self, field_shape, ndim: int, dtype: torch.dtype, solver: str, device=None, h=None):
