@@ -48,16 +48,20 @@ __device__ __forceinline__ void vld(const T *__restrict__ p, T (&v)[VW]) {
     }
 }
 
+// Non-temporal (streaming) stores.  A sweep's outputs are read again only in
+// the next sweep, long after they have left L2; streaming them measured
+// faster (2048^2 x 16 BiCGSTAB 4.99 -> 4.87 ms), most likely because less
+// dirty data is left for the grid barrier's release fence to write back.
 template <typename T, int VW>
 __device__ __forceinline__ void vst(T *__restrict__ p, const T (&v)[VW]) {
     if constexpr (VW == 1) {
-        *p = v[0];
+        __builtin_nontemporal_store(v[0], p);
     } else {
         typedef T vt __attribute__((ext_vector_type(VW)));
         vt x;
 #pragma unroll
         for (int k = 0; k < VW; ++k) x[k] = v[k];
-        *reinterpret_cast<vt *>(p) = x;
+        __builtin_nontemporal_store(x, reinterpret_cast<vt *>(p));
     }
 }
 
