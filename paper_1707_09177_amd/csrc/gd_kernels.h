@@ -143,7 +143,7 @@ __device__ __forceinline__ void spectral_tile(const Inst &I, int64_t lt, const O
 #pragma unroll
         for (int f = 0; f < Op::NI; ++f) vld<T, VW>(op.in[f] + i, vv[f]);
 #pragma unroll
-        for (int f = 0; f < Op::NO; ++f) vld<T, VW>(op.oin[f] + i, oo[f]);
+        for (int f = 0; f < Op::NO; ++f) vld_nt<T, VW>(op.oin[f] + i, oo[f]);
     };
     if (nrow_steps > 0) load(0, v, o);
     for (int64_t q = 0; q < nrow_steps; ++q) {
