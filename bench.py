@@ -31,12 +31,21 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "deconvolved grid points/s to rel. residual 1e-6; % HBM roofline; vs Van Cittert"
 
 # Algorithmic field accesses per grid point (one access = one full-field read
-# or write): init + passes + exit true residual.  Halo re-reads are not counted.
-#   VC:        init 3 (read ubar, write u, r) + 4 per pass + exit 2
-#   CG:        init 3 + 3 (first pass, p0 = r0 not re-read) + 8 per later pass + exit 2
-#   BiCGSTAB:  init 4 (read ubar, write u, r, f0) + 13 (first pass: p0 = q0 = 0 not read)
-#              + 15 per later pass + exit 2
+# or write), the method's own count of Algorithms 1-4 with every vector read or
+# written once per pass: per pass 4 (VC), 5 (SD), 8 (CG), 15 (BiCGSTAB), plus
+# init and the exit true residual: VC 4n + 5, SD 5n + 5, CG 8n + 6, BiCGSTAB
+# 15n + 6.  Halo re-reads are not counted.  The roofline fraction is priced on
+# these counts.
 def accesses(solver: str, iters: int) -> int:
+    per_pass, fixed = {"vc": (4, 5), "sd": (5, 5), "cg": (8, 6), "bicgstab": (15, 6)}[solver]
+    return per_pass * max(iters, 0) + fixed
+
+
+# The accesses the fused kernels actually make: the first CG pass does not
+# re-read p0 = r0 and the first BiCGSTAB pass does not read p0 = q0 = 0, and
+# the CG init writes no separate p0 (the counts above minus 2).  Reported
+# beside the method's count.
+def kernel_accesses(solver: str, iters: int) -> int:
     if iters <= 0:
         return 5 if solver != "bicgstab" else 6
     if solver == "vc":
@@ -165,11 +174,16 @@ def make_inputs(w, torch, gd, dev):
 
 
 def make_batch_inputs(w, torch, gd, dev):
+    from concurrent.futures import ThreadPoolExecutor
+
     from paper_1707_09177_amd import synth
     sizes = synth.batch_instances(count=w["count"])
+    # the fields are drawn on the host's cores (numpy's FFT runs outside the GIL)
+    with ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+        fields = list(ex.map(lambda a: synth.batch_field(a[1][0], a[1][1], a[0], dtype=np.float32), enumerate(sizes)))
     shapes, ubars, us = [], [], []
     for i, (nd, n) in enumerate(sizes):
-        u = synth.batch_field(nd, n, i, dtype=np.float32)
+        u = fields[i]
         ut = torch.from_numpy(u).to(dev)
         ubars.append(gd.filter_apply(ut, ndim=nd))
         shapes.append(tuple(u.shape))
@@ -200,6 +214,41 @@ def time_batch(gd, torch, shapes, ubars, solver, steps, warmup, tol=1e-6, max_it
     return dict(info=info, ms_events=float(np.mean(ms)), ms_min=float(np.min(ms)), wall_ms=wall * 1e3, tune=tune)
 
 
+def time_batch_graph(gd, torch, shapes, ubars, solver, steps, warmup, tol=1e-6, max_iter=500, tune=True):
+    """The uneven batch as one captured HIP graph (instance-table kernels, the
+    barrier-state prep and the persistent solve), timed as graph replays with
+    HIP events on the stream they run on.  Tuning is first-call work, outside
+    the graph and the timed region."""
+    b = gd.BatchDeconvolver(shapes, ubars[0].dtype, solver)
+    outs = [torch.empty_like(x) for x in ubars]
+    tune = b.autotune(ubars, outs) if tune else None
+    res = b.solve(ubars, max_iter, tol, outs=outs)
+    torch.cuda.synchronize()
+    eager_info = res.info()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.solve(ubars, max_iter, tol, outs=outs)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, e in evs:
+        a.record(stream)
+        g.replay()
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ms = [a.elapsed_time(e) for a, e in evs]
+    info = res.info()
+    same = [(i["iters"], i["status"]) for i in info] == [(i["iters"], i["status"]) for i in eager_info]
+    del g
+    return dict(info=info, ms_events=float(np.mean(ms)), ms_min=float(np.min(ms)), wall_ms=wall * 1e3, tune=tune,
+                replays_match_eager=same)
+
+
 def cpu_baseline_batch(sizes, us, tol=1e-6, budget_s=20.0):
     """FP64 oracle on a seeded subset of the batch (smallest instances first,
     until about `budget_s` of CPU time), scaled by point count."""
@@ -216,10 +265,29 @@ def cpu_baseline_batch(sizes, us, tol=1e-6, budget_s=20.0):
         done.append(f"{nd}D n={sizes[i][1]}:{infos[0]['iters']}")
         if dt > budget_s:
             break
-    return dict(value=pts / dt, unit="points/s", cores=1, kind="oracle",
+    return dict(value=pts / dt, unit="points/s", cores=1, kind="oracle", cpu_model=cpu_model(), nproc=os.cpu_count(),
                 sample=f"{len(done)} of {len(sizes)} instances, smallest first ({', '.join(done[:6])}"
                        f"{', ...' if len(done) > 6 else ''}), FP64 oracle BiCGSTAB to 1e-6, single thread, "
                        f"{dt:.1f} s, scaled by point count")
+
+
+def batch_result(gd, torch, shapes, ubars, s, steps, warmup, tune, npts, itemsize):
+    """One solver on the uneven batch, timed as replays of a captured graph."""
+    r = time_batch_graph(gd, torch, shapes, ubars, s, steps, warmup, tune=tune)
+    iters = [i["iters"] for i in r["info"]]
+    st = sorted({i["status_name"] for i in r["info"]})
+    worst_true = max(i["r_true"] / i["r_ref"] for i in r["info"])
+    algo = sum(int(np.prod(sh)) * itemsize * accesses(s, it) for sh, it in zip(shapes, iters))
+    kern = sum(int(np.prod(sh)) * itemsize * kernel_accesses(s, it) for sh, it in zip(shapes, iters))
+    gbs = algo / (r["ms_events"] * 1e-3) / 1e9
+    return dict(ms=r["ms_events"], ms_min=r["ms_min"], wall_ms=r["wall_ms"], timed_as="hipGraph replays",
+                replays_match_eager=r["replays_match_eager"],
+                iters_min=min(iters), iters_max=max(iters), status=st,
+                replaced=sum(i["replaced"] for i in r["info"]),
+                worst_true_rel_residual=worst_true, points_per_s=npts / (r["ms_events"] * 1e-3),
+                algorithmic_bytes=algo, algorithmic_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
+                kernel_bytes=kern, kernel_hbm_frac=kern / (r["ms_events"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                tune=r["tune"])
 
 
 def main_batch(args, w, torch, gd, dev):
@@ -234,18 +302,9 @@ def main_batch(args, w, torch, gd, dev):
         return
     results = {}
     for s in solvers:
-        r = time_batch(gd, torch, shapes, ubars, s, args.steps if s == "bicgstab" else max(3, args.steps // 2),
-                       args.warmup, tune=not args.no_tune)
-        iters = [i["iters"] for i in r["info"]]
-        st = sorted({i["status_name"] for i in r["info"]})
-        worst_true = max(i["r_true"] / i["r_ref"] for i in r["info"])
-        algo = sum(int(np.prod(sh)) * itemsize * accesses(s, it) for sh, it in zip(shapes, iters))
-        gbs = algo / (r["ms_events"] * 1e-3) / 1e9
-        results[s] = dict(ms=r["ms_events"], ms_min=r["ms_min"], wall_ms=r["wall_ms"],
-                          iters_min=min(iters), iters_max=max(iters), status=st,
-                          worst_true_rel_residual=worst_true, points_per_s=npts / (r["ms_events"] * 1e-3),
-                          algorithmic_bytes=algo, algorithmic_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
-                          tune=r["tune"])
+        results[s] = batch_result(gd, torch, shapes, ubars, s,
+                                  args.steps if s == "bicgstab" else max(3, args.steps // 2), args.warmup,
+                                  not args.no_tune, npts, itemsize)
     main_s = "bicgstab" if "bicgstab" in results else list(results)[0]
     m = results[main_s]
     out = {
@@ -259,7 +318,8 @@ def main_batch(args, w, torch, gd, dev):
                                       "unit": "GB/s",
                      "frac": m["hbm_frac"],
                      "traffic": measured_traffic(w["key"]) if main_s == "bicgstab" else None,
-                     "kernel": f"solve_kernel<float,{main_s}> (one persistent launch per batch solve)",
+                     "kernel": f"solve_kernel<float,{main_s}> (one persistent launch per batch solve, "
+                               f"captured with its table and prep kernels in one graph)",
                      "bytes_per_launch": m["algorithmic_bytes"]}, torch),
         "solvers": results,
     }
@@ -664,18 +724,49 @@ def time_solver(gd, torch, ubar, w, solver, steps, warmup, tol=1e-6, max_iter=50
                 tune=tuned, launch=gd.last_launch() if solver != "vcb" else None)
 
 
-def cpu_baseline(w, u32, tol=1e-6, sample_fields=12):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, u32, tol=1e-6, fields_1t=4, fields_all=16):
+    """The FP64 oracle's BiCGSTAB on a sample of the workload's fields: on one
+    thread (serial compensated sums), then on every core the host offers
+    (OpenMP over points, fixed-chunk compensated sums, the same result for
+    any thread count).  `value` is the all-core rate."""
     import oracle
-    fields = u32[:sample_fields].astype(np.float64)
-    ub = oracle.filter(fields, w["ndim"]).astype(np.float32).astype(np.float64)
-    t0 = time.perf_counter()
-    _, infos, _ = oracle.solve("bicgstab", ub, w["ndim"], 500, tol=tol)
-    dt = time.perf_counter() - t0
-    pts = fields.size
-    return dict(value=pts / dt, unit="points/s", cores=1, kind="oracle",
-                sample=f"{len(fields)} of {w['count']} fields ({'x'.join(str(s) for s in fields.shape[1:])}), "
-                       f"FP64 oracle BiCGSTAB to 1e-6, single thread, {dt:.1f} s, "
-                       f"iters {[i['iters'] for i in infos]}")
+    nd = w["ndim"]
+    procs = oracle.host_procs()
+
+    def run(nfields, threads):
+        fields = u32[:nfields].astype(np.float64)
+        ub = oracle.filter(fields, nd).astype(np.float32).astype(np.float64)
+        used = oracle.set_threads(threads)
+        try:
+            t0 = time.perf_counter()
+            _, infos, _ = oracle.solve("bicgstab", ub, nd, 500, tol=tol,
+                                       sum_mode=oracle.SUM_CHUNKED if used > 1 else 0)
+            dt = time.perf_counter() - t0
+        finally:
+            oracle.set_threads(1)
+        return fields.size / dt, dt, used, [i["iters"] for i in infos], len(fields)
+
+    v1, dt1, _, it1, n1 = run(min(fields_1t, len(u32)), 1)
+    va, dta, used, ita, na = run(min(fields_all, len(u32)), procs)
+    grid = "x".join(str(s) for s in u32.shape[1:])
+    return dict(value=va, unit="points/s", cores=used, kind="oracle",
+                sample=f"{na} of {w['count']} fields ({grid}), FP64 oracle BiCGSTAB to 1e-6, {used} threads "
+                       f"(every logical CPU of the host), {dta:.1f} s, iters {ita}",
+                cpu_model=cpu_model(), nproc=os.cpu_count(),
+                single_thread=dict(value=v1, unit="points/s", cores=1,
+                                   sample=f"{n1} of {w['count']} fields ({grid}), one thread, {dt1:.1f} s, "
+                                          f"iters {it1}"))
 
 
 def main():
@@ -685,6 +776,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default workload: skip the 3 x 256^3 and uneven-batch keys")
     ap.add_argument("--no-tune", action="store_true",
                     help="do not run the autotuner (choices come from the GD_TUNE_CACHE file when it is set, "
                          "else the defaults)")
@@ -740,18 +833,8 @@ def main():
 
     results = {}
     for s in args.solvers.split(","):
-        r = time_solver(gd, torch, ubar, w, s, args.steps if s == "bicgstab" else max(3, args.steps // 2),
-                        args.warmup, tune=not args.no_tune)
-        iters = [i["iters"] for i in r["info"]]
-        st = {i["status_name"] for i in r["info"]}
-        worst_true = max(i["r_true"] / i["r_ref"] for i in r["info"])
-        acc = accesses("vc" if s == "vcb" else s, max(iters))   # vcb: the one-pass solve's accesses, for comparison
-        gbs = npts * itemsize * acc / (r["ms_events"] * 1e-3) / 1e9
-        results[s] = dict(ms=r["ms_events"], ms_min=r["ms_min"], wall_ms=r["wall_ms"], iters=iters,
-                          status=sorted(st), worst_true_rel_residual=worst_true,
-                          points_per_s=npts / (r["ms_events"] * 1e-3), accesses_per_point=acc,
-                          algorithmic_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS, tune=r["tune"], launch=r["launch"])
-        del r
+        results[s] = uniform_result(gd, torch, ubar, w, s, args.steps if s == "bicgstab" else max(3, args.steps // 2),
+                                    args.warmup, not args.no_tune, npts, itemsize)
     main_s = "bicgstab" if "bicgstab" in results else list(results)[0]
     m = results[main_s]
     if "CONVERGED" not in m["status"] or len(m["status"]) != 1:
@@ -777,7 +860,10 @@ def main():
                      "frac": m["hbm_frac"],
                      "traffic": measured_traffic(w["key"]) if main_s == "bicgstab" else None,
                      "kernel": f"solve_kernel<float,{main_s}> (one persistent launch per solve)",
-                     "bytes_per_launch": npts * itemsize * m["accesses_per_point"]}, torch),
+                     "bytes_per_launch": npts * itemsize * m["accesses_per_point"],
+                     "accesses_per_point": m["accesses_per_point"],
+                     "kernel_accesses_per_point": m["kernel_accesses_per_point"],
+                     "kernel_frac": m["kernel_hbm_frac"]}, torch),
         "iterations": m["iters"][0] if len(set(m["iters"])) == 1 else m["iters"],
         "solvers": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
     }
@@ -787,7 +873,60 @@ def main():
         out["vs_vancittert_blocked"] = results["vcb"]["ms"] / m["ms"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, u32)
+    if args.workload == "c2" and not args.no_extra:
+        # the other headline workloads in the same run: 3 x 256^3 BiCGSTAB and
+        # the 200-instance uneven batch as graph replays
+        del ubar, u32
+        torch.cuda.empty_cache()
+        out["c3"] = extra_uniform(args, WORKLOADS["c3"], torch, gd, dev)
+        torch.cuda.empty_cache()
+        out["c4"] = extra_batch(args, WORKLOADS["c4"], torch, gd, dev)
     print(json.dumps(out))
+
+
+def uniform_result(gd, torch, ubar, w, s, steps, warmup, tune, npts, itemsize):
+    """One solver on a uniform batch: time, passes, and its algorithmic bytes
+    priced against the HBM peak (the method's access count, and beside it the
+    count the fused kernel actually makes)."""
+    r = time_solver(gd, torch, ubar, w, s, steps, warmup, tune=tune)
+    iters = [i["iters"] for i in r["info"]]
+    st = {i["status_name"] for i in r["info"]}
+    worst_true = max(i["r_true"] / i["r_ref"] for i in r["info"])
+    base = "vc" if s == "vcb" else s   # vcb: the one-pass solve's accesses, for comparison
+    acc = accesses(base, max(iters))
+    kacc = kernel_accesses(base, max(iters))
+    sec = r["ms_events"] * 1e-3
+    gbs = npts * itemsize * acc / sec / 1e9
+    return dict(ms=r["ms_events"], ms_min=r["ms_min"], wall_ms=r["wall_ms"], iters=iters,
+                status=sorted(st), worst_true_rel_residual=worst_true,
+                replaced=sum(i.get("replaced", 0) for i in r["info"]),
+                points_per_s=npts / sec, accesses_per_point=acc, kernel_accesses_per_point=kacc,
+                algorithmic_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
+                kernel_hbm_frac=npts * itemsize * kacc / sec / 1e9 / HBM_PEAK_GBS,
+                tune=r["tune"], launch=r["launch"])
+
+
+def extra_uniform(args, w, torch, gd, dev):
+    """BiCGSTAB on a second uniform workload, reported as an extra key."""
+    u32, ubar = make_inputs(w, torch, gd, dev)
+    npts, itemsize = int(ubar.numel()), ubar.element_size()
+    r = uniform_result(gd, torch, ubar, w, "bicgstab", args.steps, args.warmup, not args.no_tune, npts, itemsize)
+    del ubar, u32
+    return {"workload": w["desc"], "points": npts, "solver": "bicgstab", "points_per_s": r["points_per_s"],
+            "ms": r["ms"], "hbm_frac": r["hbm_frac"], "traffic": measured_traffic(w["key"]), **r}
+
+
+def extra_batch(args, w, torch, gd, dev):
+    """BiCGSTAB on the uneven batch, one captured graph per solve, reported as
+    an extra key."""
+    sizes, shapes, us, ubars = make_batch_inputs(w, torch, gd, dev)
+    npts = int(sum(int(np.prod(s)) for s in shapes))
+    r = batch_result(gd, torch, shapes, ubars, "bicgstab", max(5, args.steps // 2), args.warmup, not args.no_tune,
+                     npts, ubars[0].element_size())
+    del ubars, us
+    return {"workload": w["desc"], "instances": len(shapes), "instances_2d": sum(1 for s in sizes if s[0] == 2),
+            "points": npts, "solver": "bicgstab", "points_per_s": r["points_per_s"], "ms": r["ms"],
+            "hbm_frac": r["hbm_frac"], "traffic": measured_traffic(w["key"]), **r}
 
 
 if __name__ == "__main__":

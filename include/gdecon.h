@@ -46,9 +46,13 @@ enum { GD_F64 = 0, GD_F32 = 1 };
 /* solvers: Algorithms 1-4 of the paper */
 enum { GD_VANCITTERT = 0, GD_CG = 1, GD_BICGSTAB = 2, GD_STEEPEST_DESCENT = 3 };
 
-/* initial guess: the paper's u0 = ubar (Algorithms 1-4), zero, or the value
- * already in u (a warm start) */
-enum { GD_INIT_UBAR = 0, GD_INIT_ZERO = 1, GD_INIT_GIVEN = 2 };
+/* initial guess: the paper's u0 = ubar (Algorithms 1-4), zero, the value
+ * already in u (a warm start), or that value guarded by the paper's start:
+ * with GD_INIT_WARM the solve starts from the guess in u only where its
+ * residual ||ubar - G u0|| is finite and below ||ubar - G ubar||, and from
+ * u0 = ubar otherwise (decided per field on the device; gd_info.start says
+ * which start was used) */
+enum { GD_INIT_UBAR = 0, GD_INIT_ZERO = 1, GD_INIT_GIVEN = 2, GD_INIT_WARM = 3 };
 
 /* reference norm for the relative residual: ||ubar - G ubar|| (the paper's
  * initial residual, default) or ||ubar|| */
@@ -71,7 +75,11 @@ enum {
     GD_BREAKDOWN_OMEGA = 3,  /* BiCGSTAB: (t,t) == 0 with s != 0 */
     GD_NONFINITE = 4,        /* a NaN/Inf scalar (e.g. NaN in ubar) */
     GD_ZERO_REF = 5,         /* reference norm is zero: u = u0, no pass done */
-    GD_TIMEOUT = 6           /* the device-side grid barrier exceeded its wait bound */
+    GD_TIMEOUT = 6,          /* the device-side grid barrier exceeded its wait bound */
+    GD_STAGNATED = 7         /* the recursive residual met tol, but the true residual
+                                ||ubar - G u|| stayed above tol * r_ref after every
+                                residual replacement allowed (the rounding floor of
+                                the storage precision) */
 };
 
 typedef struct gd_grid {
@@ -88,10 +96,18 @@ typedef struct gd_opts {
     int32_t max_iter;   /* N: loop passes of Algorithms 1-4, >= 0 */
     int32_t init;       /* GD_INIT_* */
     int32_t norm_ref;   /* GD_REF_* */
-    int32_t reserved;   /* set to 0 */
-    double tol;         /* > 0: stop after the first pass with
-                           ||r_n|| <= tol * r_ref; <= 0: run exactly max_iter
-                           passes (unless a guard stops earlier) */
+    int32_t max_replace; /* residual replacements allowed per field: 0 = the
+                           default (2), < 0 = none, > 0 = that many (see tol) */
+    double tol;         /* > 0: after the first pass with ||r_n|| <= tol * r_ref
+                           (r_n the recursive residual of the algorithm), the
+                           true residual ||ubar - G u_n|| is evaluated in FP64
+                           arithmetic; the field stops with GD_CONVERGED if it is
+                           <= tol * r_ref too, else r is replaced by that true
+                           residual, CG and BiCGSTAB restart from u_n (p = r,
+                           BiCGSTAB's shadow f0 = r), and the iteration goes on.
+                           When no replacement is left, the field stops with
+                           GD_STAGNATED.  <= 0: run exactly max_iter passes
+                           (unless a guard stops earlier) */
     double *history;    /* NULL, or device [batch][max_iter + 1] doubles:
                            history[b][n] = ||r_n|| (recursive residual,
                            h-weighted) for n <= iters; later entries untouched */
@@ -100,14 +116,17 @@ typedef struct gd_opts {
                               GD_TIMEOUT in every info. */
 } gd_opts;
 
-/* one per field, written by the device at the end of a solve */
+/* one per field, written by the device at the end of a solve (48 bytes) */
 typedef struct gd_info {
     int32_t iters;   /* passes completed */
     int32_t status;  /* GD_CONVERGED ... */
     double r_ref;    /* reference norm */
-    double r0;       /* ||r_0|| */
+    double r0;       /* ||r_0|| of the start used */
     double r_final;  /* ||r_iters|| (recursive residual) */
     double r_true;   /* ||ubar - G u|| recomputed at exit, FP64 arithmetic */
+    int32_t start;   /* start used: GD_INIT_UBAR, GD_INIT_ZERO or GD_INIT_GIVEN
+                        (GD_INIT_WARM resolves to GIVEN or, on fallback, UBAR) */
+    int32_t replaced; /* residual replacements done */
 } gd_info;
 
 /*

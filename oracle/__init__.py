@@ -31,11 +31,12 @@ _APPLY = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no FP contraction)."""
+    """Compile the oracle with gcc (-O2, no FP contraction; OpenMP for the
+    timed multi-core mode only, see ``set_threads``)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                               "-std=c11", "-o", tmp, _SRC, "-lm"])
+                               "-std=c11", "-fopenmp", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -63,8 +64,29 @@ def _load():
         lib.or_solve.restype = ctypes.c_int
         lib.or_solve_with.argtypes = lib.or_solve.argtypes + [_APPLY]
         lib.or_solve_with.restype = ctypes.c_int
+        lib.or_set_threads.argtypes = [ctypes.c_int]
+        lib.or_set_threads.restype = ctypes.c_int
+        lib.or_host_procs.argtypes = []
+        lib.or_host_procs.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+# the summation mode whose result does not depend on the thread count
+SUM_CHUNKED = 3
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's loops (1 = serial, the default).  For timing on
+    the host's cores only: with n > 1, solve() needs sum_mode=SUM_CHUNKED
+    (fixed chunks summed in order), whose result is bitwise the same for any
+    n.  Returns the count in effect."""
+    return int(_load().or_set_threads(int(n)))
+
+
+def host_procs() -> int:
+    """Logical processors the host offers to the oracle's threads."""
+    return int(_load().or_host_procs())
 
 
 def _ptr(a: np.ndarray):
@@ -164,14 +186,42 @@ def dot(a: np.ndarray, b: np.ndarray, hw: float, sum_mode: int = 0) -> float:
     return float(lib.or_dot(_ptr(a), _ptr(b), a.size, hw, sum_mode))
 
 
+def warm_choice(ubar: np.ndarray, u0: np.ndarray, ndim: int, gamma=None, h=None, sum_mode: int = 0) -> list[str]:
+    """The start a guarded warm start takes per field: the guess u0 where its
+    residual ||ubar - G u0|| is finite and below that of the paper's start
+    u0 = ubar (Algorithms 1-4), ||ubar - G ubar||; ubar otherwise."""
+    ubar = np.asarray(ubar, dtype=np.float64)
+    nx, ny, nz = _grid(ubar.shape, ndim)
+    npts = nx * ny * nz
+    fshape = ubar.shape[-ndim:]
+    hw = spacing_weight(ubar.shape, ndim, h)
+    ub = ubar.reshape(-1, npts)
+    g0 = np.asarray(u0, dtype=np.float64).reshape(ub.shape)
+
+    def gf(x):
+        x = x.reshape(fshape)
+        return (filter(x, ndim) if gamma is None else germano_filter(x, ndim, gamma)).ravel()
+    out = []
+    for b in range(ub.shape[0]):
+        r_given = ub[b] - gf(g0[b])
+        r_ubar = ub[b] - gf(ub[b])
+        a = math.sqrt(dot(r_given, r_given, hw, sum_mode))
+        c = math.sqrt(dot(r_ubar, r_ubar, hw, sum_mode))
+        out.append("given" if math.isfinite(a) and a < c else "ubar")
+    return out
+
+
 def solve(solver: str, ubar: np.ndarray, ndim: int, max_iter: int, tol: float = 0.0, init: str = "ubar",
           u0: np.ndarray | None = None, norm_ref: str = "r0ubar", h=None, sum_mode: int = 0, gamma=None):
     """Run one of Algorithms 1-4 on every field of ``ubar`` (leading dims = batch).
 
     G is the trapezoidal stencil, or with ``gamma`` set the differential
-    filter of Sec. 4 (``germano_filter``).
-    Returns (u, infos, hist): u like ubar; infos a list of dicts; hist an array
-    (batch, max_iter+1) of ||r_k|| with NaN past the last pass.
+    filter of Sec. 4 (``germano_filter``).  init: 'ubar' (the paper's),
+    'zero', 'given' (u0), or 'warm' (u0 where ``warm_choice`` accepts it,
+    else ubar).
+    Returns (u, infos, hist): u like ubar; infos a list of dicts (with the
+    start used); hist an array (batch, max_iter+1) of ||r_k|| with NaN past
+    the last pass.
     """
     lib = _load()
     ubar = np.ascontiguousarray(ubar, dtype=np.float64)
@@ -181,10 +231,13 @@ def solve(solver: str, ubar: np.ndarray, ndim: int, max_iter: int, tol: float = 
     flat = ubar.reshape(-1, npts)
     B = flat.shape[0]
     u = np.zeros_like(flat)
-    if init == "given":
+    starts = [init] * B
+    if init in ("given", "warm"):
         if u0 is None:
-            raise ValueError("init='given' needs u0")
+            raise ValueError(f"init='{init}' needs u0")
         u[:] = np.asarray(u0, dtype=np.float64).reshape(B, npts)
+        if init == "warm":
+            starts = warm_choice(ubar, u0, ndim, gamma=gamma, h=h, sum_mode=sum_mode)
     hist = np.full((B, max_iter + 1), np.nan)
     infos = []
     for b in range(B):
@@ -193,7 +246,7 @@ def solve(solver: str, ubar: np.ndarray, ndim: int, max_iter: int, tol: float = 
         hb = np.full(max_iter + 1, np.nan)
         info = _Info()
         args = (SOLVERS[solver], ndim, nx, ny, nz, hw, _ptr(ub), _ptr(uo), int(max_iter), float(tol),
-                INITS[init], NORM_REFS[norm_ref], int(sum_mode), _ptr(hb), ctypes.byref(info))
+                INITS[starts[b]], NORM_REFS[norm_ref], int(sum_mode), _ptr(hb), ctypes.byref(info))
         if gamma is None:
             rc = lib.or_solve(*args)
         else:
@@ -210,5 +263,6 @@ def solve(solver: str, ubar: np.ndarray, ndim: int, max_iter: int, tol: float = 
         u[b] = uo
         hist[b] = hb
         infos.append({"iters": info.iters, "status": info.status, "status_name": STATUS[info.status],
-                      "r_ref": info.r_ref, "r0": info.r0, "r_final": info.r_final, "r_true": info.r_true})
+                      "r_ref": info.r_ref, "r0": info.r0, "r_final": info.r_final, "r_true": info.r_true,
+                      "start": starts[b]})
     return u.reshape(ubar.shape), infos, hist

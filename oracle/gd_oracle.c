@@ -39,12 +39,47 @@
  * Summation: dot products use Neumaier-compensated summation by default
  * (sum_mode 0).  sum_mode 1 is plain forward summation and sum_mode 2 is
  * pairwise summation; they exist only to measure the oracle's own rounding
- * sensitivity.
+ * sensitivity.  sum_mode 3 is the timed mode's: a fixed number of chunks,
+ * each Neumaier-summed, then the chunk sums Neumaier-summed in chunk order.
+ *
+ * Threads (or_set_threads): only for timing on the host's cores.  The filter
+ * and vector loops split over points, which changes no result; with more than
+ * one thread the dot products must use sum_mode 3, whose chunks do not depend
+ * on the thread count, so any thread count gives bitwise the same result.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int or_nthreads = 1;
+
+/* Threads the loops may use (1 = serial); returns the count in effect. */
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    or_nthreads = n < 1 ? 1 : n;
+#else
+    (void)n;
+    or_nthreads = 1;
+#endif
+    return or_nthreads;
+}
+
+/* Logical processors the host offers (1 without OpenMP). */
+int or_host_procs(void)
+{
+#ifdef _OPENMP
+    return omp_get_num_procs();
+#else
+    return 1;
+#endif
+}
+
+#define OR_PAR _Pragma("omp parallel for num_threads(or_nthreads) schedule(static) if (or_nthreads > 1)")
 
 /* status values, documented in the library header with the same numbers */
 enum {
@@ -79,6 +114,7 @@ void or_filter(int ndim, int64_t nx, int64_t ny, int64_t nz, const double *x, do
 {
     const double w[3] = {0.25, 0.5, 0.25};
     if (ndim == 2) {
+        OR_PAR
         for (int64_t j = 0; j < ny; ++j)
             for (int64_t i = 0; i < nx; ++i) {
                 double s = 0.0;
@@ -89,6 +125,7 @@ void or_filter(int ndim, int64_t nx, int64_t ny, int64_t nz, const double *x, do
             }
         return;
     }
+    OR_PAR
     for (int64_t k = 0; k < nz; ++k)
         for (int64_t j = 0; j < ny; ++j)
             for (int64_t i = 0; i < nx; ++i) {
@@ -113,24 +150,44 @@ static double sum_pairwise(const double *a, const double *b, int64_t n)
     return sum_pairwise(a, b, h) + sum_pairwise(a + h, b + h, n - h);
 }
 
+/* Neumaier-compensated sum of a_i b_i over [lo, hi) */
+static double sum_neumaier(const double *a, const double *b, int64_t lo, int64_t hi)
+{
+    double s = 0.0, c = 0.0;
+    for (int64_t i = lo; i < hi; ++i) {
+        double v = a[i] * b[i];
+        double t = s + v;
+        if (fabs(s) >= fabs(v)) c += (s - t) + v;
+        else c += (v - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+#define OR_CHUNKS 256
+
 /* (a, b) = hw * sum_i a_i b_i, hw = h_x h_y (h_z) */
 double or_dot(const double *a, const double *b, int64_t n, double hw, int sum_mode)
 {
     double s = 0.0;
-    if (sum_mode == 1) {
+    if (sum_mode == 3) {
+        double part[OR_CHUNKS];
+        OR_PAR
+        for (int k = 0; k < OR_CHUNKS; ++k) part[k] = sum_neumaier(a, b, n * k / OR_CHUNKS, n * (k + 1) / OR_CHUNKS);
+        double c = 0.0;
+        for (int k = 0; k < OR_CHUNKS; ++k) {
+            double t = s + part[k];
+            if (fabs(s) >= fabs(part[k])) c += (s - t) + part[k];
+            else c += (part[k] - t) + s;
+            s = t;
+        }
+        s += c;
+    } else if (sum_mode == 1) {
         for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
     } else if (sum_mode == 2) {
         s = sum_pairwise(a, b, n);
     } else {
-        double c = 0.0; /* Neumaier */
-        for (int64_t i = 0; i < n; ++i) {
-            double v = a[i] * b[i];
-            double t = s + v;
-            if (fabs(s) >= fabs(v)) c += (s - t) + v;
-            else c += (v - t) + s;
-            s = t;
-        }
-        s += c;
+        s = sum_neumaier(a, b, 0, n);
     }
     return hw * s;
 }
@@ -157,6 +214,7 @@ static double dot(const grid_t *g, const double *a, const double *b) { return or
 static double resnorm(const grid_t *g, const double *ubar, const double *x, double *tmp)
 {
     G(g, x, tmp);
+    OR_PAR
     for (int64_t i = 0; i < g->n; ++i) tmp[i] = ubar[i] - tmp[i];
     return sqrt(dot(g, tmp, tmp));
 }
@@ -183,6 +241,7 @@ int or_solve_with(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, doub
 {
     if ((ndim != 2 && ndim != 3) || nx < 1 || ny < 1 || (ndim == 3 && nz < 1) || max_iter < 0)
         return -1;
+    if (or_nthreads > 1 && sum_mode != 3) return -1; /* only the chunked sums are thread-count independent */
     grid_t g = {ndim, nx, ny, ndim == 3 ? nz : 1, 0, hw, sum_mode, apply};
     g.n = g.nx * g.ny * g.nz;
     const int64_t n = g.n;
@@ -202,6 +261,7 @@ int or_solve_with(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, doub
     if (init == OR_INIT_UBAR) memcpy(u, ubar, n * sizeof(double));
     else if (init == OR_INIT_ZERO) memset(u, 0, n * sizeof(double));
     G(&g, u, d);
+    OR_PAR
     for (int64_t i = 0; i < n; ++i) r[i] = ubar[i] - d[i];
     double rr = dot(&g, r, r);
     double r0 = sqrt(rr);
@@ -215,8 +275,10 @@ int or_solve_with(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, doub
     if (!stop && solver == OR_VC) {
         /* Algorithm 1 */
         while (iters < max_iter) {
+            OR_PAR
             for (int64_t i = 0; i < n; ++i) u[i] += r[i];   /* u_{n+1} = u_n + r_n */
             G(&g, r, d);                                     /* d_n = G r_n */
+            OR_PAR
             for (int64_t i = 0; i < n; ++i) r[i] -= d[i];    /* r_{n+1} = r_n - d_n */
             ++iters;
             rr = dot(&g, r, r);
@@ -231,6 +293,7 @@ int or_solve_with(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, doub
             if (!isfinite(rd)) { status = OR_NONFINITE; break; }
             if (rd == 0.0) { status = OR_BREAKDOWN_RHO; break; }
             double alpha = rr / rd;                          /* Eq. (sd-a) */
+            OR_PAR
             for (int64_t i = 0; i < n; ++i) {
                 u[i] += alpha * r[i];
                 r[i] -= alpha * d[i];
@@ -250,6 +313,7 @@ int or_solve_with(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, doub
             if (!isfinite(pd)) { status = OR_NONFINITE; break; }
             if (pd == 0.0) { status = OR_BREAKDOWN_RHO; break; }
             double alpha = rho / pd;
+            OR_PAR
             for (int64_t i = 0; i < n; ++i) {
                 u[i] += alpha * p[i];
                 r[i] -= alpha * d[i];
@@ -259,6 +323,7 @@ int or_solve_with(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, doub
             if (hist) hist[iters] = sqrt(rho_new);
             if (stop_check(sqrt(rho_new), tol, r_ref, iters, max_iter, &status)) break;
             double beta = rho_new / rho;
+            OR_PAR
             for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
             rho = rho_new;
         }
@@ -273,12 +338,14 @@ int or_solve_with(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, doub
             if (!isfinite(rho_new)) { status = OR_NONFINITE; break; }
             if (rho_new == 0.0) { status = OR_BREAKDOWN_RHO; break; }
             double beta = (alpha / omega) * (rho_new / rho);
+            OR_PAR
             for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * q[i]);
             G(&g, p, q);
             double fq = dot(&g, f0, q);
             if (!isfinite(fq)) { status = OR_NONFINITE; break; }
             if (fq == 0.0) { status = OR_BREAKDOWN_RHO; break; }
             alpha = rho_new / fq;
+            OR_PAR
             for (int64_t i = 0; i < n; ++i) s[i] = r[i] - alpha * q[i];
             G(&g, s, t);
             double ss = dot(&g, s, s), st = dot(&g, s, t), tt = dot(&g, t, t);
@@ -286,6 +353,7 @@ int or_solve_with(int solver, int ndim, int64_t nx, int64_t ny, int64_t nz, doub
             int half = (ss == 0.0) || (sqrt(ss) <= thr);
             if (!half && tt == 0.0) { status = OR_BREAKDOWN_OMEGA; break; }
             omega = half ? 0.0 : st / tt;
+            OR_PAR
             for (int64_t i = 0; i < n; ++i) {
                 u[i] += alpha * p[i] + omega * s[i];
                 r[i] = s[i] - omega * t[i];

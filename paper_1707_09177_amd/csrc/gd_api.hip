@@ -57,9 +57,16 @@ __global__ void prep_kernel(Params P) {
     if (i == 0) {
         P.sync->top = 0;
         P.sync->abort = 0;
-        P.sync->active = P.ninst;
+        Counts c;
+        memset(&c, 0, sizeof c);
+        c.active = P.ninst;
+        P.sync->live = c;
     }
-    if (i < 2) P.sync->snap[i].v = 0;
+    if (i < 2) {
+        Counts z;
+        memset(&z, 0, sizeof z);
+        P.sync->snap[i] = z;
+    }
     if (i < NGRP) {
         int64_t c = 0;  // claims in pool i (the kernel's pool layouts)
         const int64_t ng = P.npools, ntot = P.total_tiles, nb = P.big_total, ns = ntot - nb;
@@ -74,12 +81,14 @@ __global__ void prep_kernel(Params P) {
         State s;
         s.alpha = s.beta = s.omega = 1.0;
         s.rho = s.rr = s.r_ref = s.r0 = 0.0;
-        s.pad = 0.0;
+        s.r_ub = 0.0;
         s.iters = 0;
         s.status = GD_MAXITER;
         s.done = 0;
         s.half = 0;
         s.cnt = 0;
+        s.verify = s.replace = s.restart = s.fallback = s.tknown = s.nrep = 0;
+        s.start = P.init == GD_INIT_WARM ? GD_INIT_GIVEN : P.init;
         P.st[i] = s;
     }
 }
@@ -316,10 +325,16 @@ int64_t wait_ticks_of(const gd_opts *o) {
 int validate_opts(const gd_opts *o) {
     if (!o) return fail(GD_EINVAL, "opts is NULL");
     if (o->max_iter < 0) return fail(GD_EINVAL, "max_iter must be >= 0");
-    if (o->init < GD_INIT_UBAR || o->init > GD_INIT_GIVEN) return fail(GD_EINVAL, "bad init %d", o->init);
+    if (o->init < GD_INIT_UBAR || o->init > GD_INIT_WARM) return fail(GD_EINVAL, "bad init %d", o->init);
     if (o->norm_ref != GD_REF_R0UBAR && o->norm_ref != GD_REF_UBAR) return fail(GD_EINVAL, "bad norm_ref");
     if (std::isnan(o->tol)) return fail(GD_EINVAL, "tol is NaN");
     return GD_OK;
+}
+
+// residual replacements per instance that the options allow
+int32_t replacements_of(const gd_opts *o) {
+    constexpr int32_t kDefaultReplace = 2;
+    return o->max_replace == 0 ? kDefaultReplace : std::max<int32_t>(0, o->max_replace);
 }
 
 bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
@@ -486,6 +501,8 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
     P.norm_ref = o->norm_ref;
     P.max_iter = o->max_iter;
     P.hist_stride = o->max_iter + 1;
+    P.max_replace = replacements_of(o);
+    P.solver = solver;
     P.steal = kSteal;
     if (const char *e = getenv("GD_STEAL")) P.steal = std::max(0, atoi(e));
     P.interleave = cfg.ilv;
@@ -733,6 +750,8 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
     P.init = o->init;
     P.norm_ref = o->norm_ref;
     P.max_iter = o->max_iter;
+    P.max_replace = replacements_of(o);
+    P.solver = solver;
     P.steal = kSteal;
     if (const char *e = getenv("GD_STEAL")) P.steal = std::max(0, atoi(e));
     P.interleave = cfg.ilv;
@@ -1021,6 +1040,7 @@ const char *gd_status_string(int32_t code) {
     case GD_NONFINITE: return "GD_NONFINITE";
     case GD_ZERO_REF: return "GD_ZERO_REF";
     case GD_TIMEOUT: return "GD_TIMEOUT";
+    case GD_STAGNATED: return "GD_STAGNATED";
     default: return "unknown";
     }
 }

@@ -46,7 +46,9 @@ enum Phase : int {
     PH_BIC,            // Algorithm 4: u, r, (f0, r) (r, r)
     PH_SD1,            // Algorithm 2: (r, G r)
     PH_SD2,            // Algorithm 2: u, r, (r, r)
-    PH_TRUE            // ||ubar - G u||^2 in FP64, writes gd_info
+    PH_TRUE,           // ||ubar - G u||^2 in FP64, writes gd_info
+    PH_VERIFY,         // ||ubar - G u||^2 in FP64 once the recursive residual met tol
+    PH_REPLACE         // r = ubar - G u in FP64 arithmetic (stored), f0 = r, (r, r)
 };
 
 // Device descriptor of one field (instance) of a solve.
@@ -70,15 +72,22 @@ struct Inst {
     int32_t nxc, nxs, lnz, pad;
 };
 
-// FP64 scalars of one instance; written only by the barrier's last arriver.
 // FP64 scalars of one instance, written by the wave that completes the
 // instance's last tile of a sweep.  `cnt` counts the tiles of the current
-// sweep that have published their partial sums.
+// sweep that have published their partial sums.  The flags select which
+// instances the control sweeps work on: `verify` (the recursive residual met
+// tol: PH_VERIFY), `replace` (the true residual did not: PH_REPLACE),
+// `restart` (the next pass starts a fresh Krylov sequence), `fallback` (a
+// warm start's guess was rejected: PH_INIT_UBAR); `tknown` marks an instance
+// whose info record is already written (PH_TRUE skips it).
 struct alignas(128) State {
-    double alpha, beta, omega, rho, rr, r_ref, r0, pad;
+    double alpha, beta, omega, rho, rr, r_ref, r0;
+    double r_ub;  // ||ubar - G ubar||: the warm start's acceptance bound
     int32_t iters, status, done, half;
     uint32_t cnt;
+    int32_t verify, replace, restart, fallback, tknown, nrep, start;
 };
+static_assert(sizeof(State) == 128, "State is one 128-byte line");
 
 // Grid-barrier state.  Workgroups arrive in NGRP groups (workgroup b is in
 // group b % NGRP), each with its own counter and its own release flag on a
@@ -89,21 +98,31 @@ struct alignas(128) SyncLine {
     uint32_t v;
     uint32_t pad[31];
 };
+// Counters of instances in each control state, and their per-barrier
+// snapshot: every workgroup takes its loop decisions from the snapshot of the
+// barrier it has just passed, never from the live counters (which the next
+// sweep's reductions already change).
+struct alignas(128) Counts {
+    int32_t active;    // instances still iterating
+    int32_t verify;    // instances whose true residual is to be checked
+    int32_t replace;   // instances whose residual is to be replaced
+    int32_t fallback;  // warm starts rejected, to be restarted from ubar
+    int32_t ntrue;     // finished instances that still need the exit true residual
+    int32_t pad[27];
+};
 struct Sync {
     uint32_t top;    // groups complete at the current barrier
     uint32_t abort;  // set when a wait exceeded its bound
-    int32_t active;  // instances still iterating
-    uint32_t pad[29];
+    uint32_t pad[30];
+    Counts live;
     SyncLine cnt[NGRP];  // arrivals per group at the current barrier
     SyncLine gen[NGRP];  // completed barriers, one copy per group
     // tile pools of a sweep: the tiles are split into ng contiguous pools and
     // pool[par][p] counts the tiles of pool p taken so far in a sweep of
     // parity par (sweeps alternate between the two sets)
     SyncLine pool[2][NGRP];
-    // instances still active after barrier k, in slot k & 1: every workgroup
-    // takes its loop decision from this snapshot, never from `active` itself
-    // (which the next sweep's reductions already decrement)
-    SyncLine snap[2];
+    // the counters after barrier k, in slot k & 1
+    Counts snap[2];
     // claims in each tile pool (written by the prep kernel for the launch's
     // pool count), read when a workgroup looks for pools to steal from
     int64_t pcnt[NGRP];
@@ -134,7 +153,7 @@ struct Params {
     double tol;
     int32_t ninst, init, norm_ref, max_iter;
     int32_t hist_stride;
-    int32_t pad;
+    int32_t max_replace;  // residual replacements per instance (0: none)
     // optional diagnostics: per barrier k, trace[4k..4k+3] = first arrival,
     // last arrival, release, latest instance completion (wall-clock ticks)
     unsigned long long *trace;
@@ -143,6 +162,8 @@ struct Params {
     int32_t interleave;  // pool layout: 0 contiguous shares, 1 tiles pl, pl + ng, ...
     int32_t npools;      // tile pools of the launch: min(workgroups, NGRP)
     int32_t wave_claims; // 1: every wave claims its own tiles; 0: a workgroup claims for its waves
+    int32_t solver;      // GD_VANCITTERT ... (where a replaced residual is stored)
+    int32_t pad2;
 };
 
 // Launch configuration the autotuner chooses between: target tiles per

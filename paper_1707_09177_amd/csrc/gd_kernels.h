@@ -104,8 +104,11 @@ __device__ __forceinline__ void with_variant(const Inst &I, F &&f) {
 template <int PH> struct PhaseNacc { static constexpr int v = 1; };
 template <> struct PhaseNacc<PH_BIB> { static constexpr int v = 3; };
 template <> struct PhaseNacc<PH_BIC> { static constexpr int v = 2; };
+template <> struct PhaseNacc<PH_RREF_RES> { static constexpr int v = 2; };
 
-__host__ __device__ constexpr inline int phase_nacc(int ph) { return ph == PH_BIB ? 3 : (ph == PH_BIC ? 2 : 1); }
+__host__ __device__ constexpr inline int phase_nacc(int ph) {
+    return ph == PH_BIB ? 3 : ((ph == PH_BIC || ph == PH_RREF_RES) ? 2 : 1);
+}
 
 // Pointwise pass over a tile of a stored half spectrum (the differential
 // filter): G S = G_hat(k) S at every point, G_hat = 1 / (1 + |k|^2 / k_c^2).
@@ -200,12 +203,15 @@ __device__ __forceinline__ void g_tile(const Inst &I, int64_t lt, const Op &op, 
 
 // One tile of one sweep.
 template <typename T, int VS, int PH>
-__device__ __forceinline__ void tile_body(const Inst &I, const State *S, int it, int64_t lt, double (&acc)[NACC],
-                                          int lane) {
+__device__ __forceinline__ void tile_body(const Params &P, const Inst &I, const State *S, int it, int64_t lt,
+                                          double (&acc)[NACC], int lane) {
     const T alpha = T(ld_f64(&S->alpha));
     const T beta = T(ld_f64(&S->beta));
     const T omega = T(ld_f64(&S->omega));
     const bool odd = (it & 1) != 0;
+    // the first pass of a Krylov sequence: the solve's first, or the first
+    // after a residual replacement (the same value in every lane)
+    const bool first = it == 0 || __builtin_amdgcn_readfirstlane(ld_i32(&S->restart)) != 0;
     T *const V[NVEC] = {static_cast<T *>(I.vec[0]), static_cast<T *>(I.vec[1]), static_cast<T *>(I.vec[2]),
                         static_cast<T *>(I.vec[3]), static_cast<T *>(I.vec[4]), static_cast<T *>(I.vec[5]),
                         static_cast<T *>(I.vec[6])};
@@ -243,7 +249,7 @@ __device__ __forceinline__ void tile_body(const Inst &I, const State *S, int it,
             OpVC<T, T, VW> op{{X(V_R0)}, {u}, Y(V_R0), u};
             g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
         } else if constexpr (PH == PH_CG1) {
-            if (it == 0) {
+            if (first) {
                 OpCG1First<T, T, VW> op{{V[V_R0]}, {nullptr}, Y(V_P0)};
                 g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
             } else {
@@ -254,7 +260,7 @@ __device__ __forceinline__ void tile_body(const Inst &I, const State *S, int it,
             OpCG2<T, T, VW> op{{Y(V_P0)}, {u, V[V_R0]}, u, V[V_R0], alpha};
             g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
         } else if constexpr (PH == PH_BIA) {
-            if (it == 0) {
+            if (first) {
                 OpBiAFirst<T, T, VW> op{{X(V_R0)}, {V[V_F0]}, Y(V_P0), Y(V_Q0)};
                 g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
             } else {
@@ -273,21 +279,69 @@ __device__ __forceinline__ void tile_body(const Inst &I, const State *S, int it,
         } else if constexpr (PH == PH_SD2) {
             OpSD2<T, T, VW> op{{X(V_R0)}, {u}, Y(V_R0), u, alpha};
             g_tile<VS, NDIM, VW, R, T, T>(I, lt, op, acc, lane);
+        } else if constexpr (PH == PH_VERIFY) {
+            OpResNorm<T, double, VW> op{{u}, {ub}};
+            g_tile<VS, NDIM, VW, R, T, double>(I, lt, op, acc, lane);
+        } else if constexpr (PH == PH_REPLACE) {
+            // `it` is the index of the pass that follows: the residual goes
+            // where that pass reads it (CG updates r in place; the others
+            // ping-pong it)
+            T *rdst = P.solver == GD_CG ? V[V_R0] : X(V_R0);
+            OpInitGiven<T, double, VW> op{{u}, {ub}, rdst, V[V_F0]};
+            g_tile<VS, NDIM, VW, R, T, double>(I, lt, op, acc, lane);
         }
     });
 }
 
 // ------------------------------------------------ scalar recurrences (FP64)
+// Counters of the control states (Sync::live), changed by the single lane
+// that completes an instance's reduction.
+__device__ __forceinline__ void count(int32_t *c, int d) {
+    __hip_atomic_fetch_add(c, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The instance stops; its exit true residual is still to be computed (PH_TRUE).
 static __device__ __forceinline__ void finish(const Params &P, State *S, int status) {
     S->status = status;
     S->done = 1;
-    __hip_atomic_fetch_add(&P.sync->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    count(&P.sync->live.active, -1);
+    count(&P.sync->live.ntrue, 1);
 }
 
-// Stopping test after `n` completed passes with residual norm rn.
+// The instance stops with its true residual rt already known: its info
+// record is written here and PH_TRUE skips it.
+static __device__ __forceinline__ void finish_known(const Params &P, const Inst &I, State *S, int status, double rt) {
+    S->status = status;
+    S->done = 1;
+    S->tknown = 1;
+    count(&P.sync->live.active, -1);
+    gd_info out;
+    out.iters = S->iters;
+    out.status = status;
+    out.r_ref = S->r_ref;
+    out.r0 = S->r0;
+    out.r_final = sqrt(S->rr);
+    out.r_true = rt;
+    out.start = S->start;
+    out.replaced = S->nrep;
+    *I.info = out;
+}
+
+// Stopping test after `n` completed passes with residual norm rn.  When the
+// recursive residual meets the tolerance after a pass, the instance goes to
+// the true-residual check (PH_VERIFY) instead of stopping; the initial
+// residual (n = 0) is computed directly and needs no check.
 static __device__ __forceinline__ bool stop_check(const Params &P, State *S, double rn, int n) {
     if (!isfinite(rn)) { finish(P, S, GD_NONFINITE); return true; }
-    if (rn == 0.0 || (P.tol > 0.0 && rn <= P.tol * S->r_ref)) { finish(P, S, GD_CONVERGED); return true; }
+    if (rn == 0.0 || (P.tol > 0.0 && rn <= P.tol * S->r_ref)) {
+        if (n > 0 && P.tol > 0.0) {
+            S->verify = 1;
+            count(&P.sync->live.verify, 1);
+        } else {
+            finish(P, S, GD_CONVERGED);
+        }
+        return true;
+    }
     if (n >= P.max_iter) { finish(P, S, GD_MAXITER); return true; }
     return false;
 }
@@ -296,15 +350,30 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
     const double hw = I.hw;
     switch (ph) {
     case PH_RREF_UBAR:
-    case PH_RREF_RES:
         S->r_ref = sqrt(hw * sum[0]);
+        break;
+    case PH_RREF_RES:
+        // ||ubar - G ubar|| (the warm start's acceptance bound) and ||ubar||
+        S->r_ub = sqrt(hw * sum[0]);
+        S->r_ref = P.norm_ref == GD_REF_UBAR ? sqrt(hw * sum[1]) : S->r_ub;
         break;
     case PH_INIT_UBAR:
     case PH_INIT_ZERO:
     case PH_INIT_GIVEN: {
         const double rr = hw * sum[0];
         const double r0 = sqrt(rr);
+        if (ph == PH_INIT_GIVEN && P.init == GD_INIT_WARM && (!isfinite(r0) || !(r0 < S->r_ub))) {
+            // the guess is no better than the paper's start: restart from ubar
+            S->fallback = 1;
+            count(&P.sync->live.fallback, 1);
+            break;
+        }
+        if (ph == PH_INIT_UBAR && S->fallback) {
+            S->fallback = 0;
+            count(&P.sync->live.fallback, -1);
+        }
         if (ph == PH_INIT_UBAR && P.norm_ref == GD_REF_R0UBAR) S->r_ref = r0;
+        S->start = ph == PH_INIT_UBAR ? GD_INIT_UBAR : (ph == PH_INIT_ZERO ? GD_INIT_ZERO : GD_INIT_GIVEN);
         S->r0 = r0;
         S->rr = rr;
         S->iters = 0;
@@ -325,6 +394,7 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
         const double rr = hw * sum[0];
         S->iters += 1;
         S->rr = rr;
+        S->restart = 0;
         if (I.hist && S->iters <= P.max_iter) I.hist[S->iters] = sqrt(rr);
         stop_check(P, S, sqrt(rr), S->iters);
         break;
@@ -338,6 +408,7 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
     }
     case PH_CG1: {
         const double pd = hw * sum[0];
+        S->restart = 0;
         if (!isfinite(pd)) finish(P, S, GD_NONFINITE);
         else if (pd == 0.0) finish(P, S, GD_BREAKDOWN_RHO);
         else S->alpha = S->rho / pd;
@@ -356,6 +427,7 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
     }
     case PH_BIA: {
         const double fq = hw * sum[0];
+        S->restart = 0;
         if (!isfinite(fq)) finish(P, S, GD_NONFINITE);
         else if (fq == 0.0) finish(P, S, GD_BREAKDOWN_RHO);
         else S->alpha = S->rho / fq;  // rho holds rho_{n+1} = (f0, r_n)
@@ -383,7 +455,14 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
         S->rr = rr;
         if (I.hist && S->iters <= P.max_iter) I.hist[S->iters] = sqrt(rr);
         if (S->half) {
-            finish(P, S, isfinite(rr) ? GD_CONVERGED : GD_NONFINITE);
+            // s met the tolerance after the alpha half step: u += alpha p, r = s
+            if (!isfinite(rr)) finish(P, S, GD_NONFINITE);
+            else if (P.tol > 0.0) {
+                S->verify = 1;
+                count(&P.sync->live.verify, 1);
+            } else {
+                finish(P, S, GD_CONVERGED);
+            }
             break;
         }
         if (stop_check(P, S, sqrt(rr), S->iters)) break;
@@ -395,6 +474,37 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
         }
         break;
     }
+    case PH_VERIFY: {
+        // the true residual of the iterate whose recursive residual met tol
+        const double rt = sqrt(hw * sum[0]);
+        S->verify = 0;
+        count(&P.sync->live.verify, -1);
+        if (!isfinite(rt)) finish_known(P, I, S, GD_NONFINITE, rt);
+        else if (rt <= P.tol * S->r_ref) finish_known(P, I, S, GD_CONVERGED, rt);
+        else if (S->iters >= P.max_iter) finish_known(P, I, S, GD_MAXITER, rt);
+        else if (S->nrep >= P.max_replace) finish_known(P, I, S, GD_STAGNATED, rt);
+        else {
+            S->replace = 1;
+            count(&P.sync->live.replace, 1);
+        }
+        break;
+    }
+    case PH_REPLACE: {
+        // r (and BiCGSTAB's shadow f0) now hold ubar - G u: the Krylov
+        // sequence restarts from the current iterate, as from a given start
+        const double rr = hw * sum[0];
+        S->replace = 0;
+        count(&P.sync->live.replace, -1);
+        S->nrep += 1;
+        S->restart = 1;
+        S->half = 0;
+        S->rr = rr;
+        S->rho = rr;
+        S->alpha = 1.0;
+        S->omega = 1.0;
+        S->beta = 0.0;
+        break;
+    }
     case PH_TRUE: {
         gd_info out;
         out.iters = S->iters;
@@ -403,6 +513,8 @@ static __device__ __forceinline__ void update_scalars(const Params &P, const Ins
         out.r0 = S->r0;
         out.r_final = sqrt(S->rr);
         out.r_true = sqrt(hw * sum[0]);
+        out.start = S->start;
+        out.replaced = S->nrep;
         *I.info = out;
         break;
     }
@@ -433,6 +545,18 @@ static __device__ void complete_instance(const Params &P, const Inst &I, State *
     }
 }
 
+// Whether sweep PH leaves instance S alone: the control sweeps work only on
+// the instances flagged for them, PH_TRUE on those without a known true
+// residual, the others on the instances still iterating.
+template <int PH>
+__device__ __forceinline__ bool skip_instance(const Params &P, const State *S) {
+    if constexpr (PH == PH_TRUE) return ld_i32(&S->tknown) != 0;
+    else if constexpr (PH == PH_VERIFY) return ld_i32(&S->verify) == 0;
+    else if constexpr (PH == PH_REPLACE) return ld_i32(&S->replace) == 0;
+    else if constexpr (PH == PH_INIT_UBAR) return P.init == GD_INIT_WARM ? ld_i32(&S->fallback) == 0 : ld_i32(&S->done) != 0;
+    else return ld_i32(&S->done) != 0;
+}
+
 // One tile of a sweep: march it, publish its partials, count it done, and
 // finish the instance's reduction if it was the instance's last tile.
 template <typename T, int VS, int PH>
@@ -442,8 +566,8 @@ __device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch
     int64_t lt = 0;
     const int i = locate<var_table(VS)>(P, t, lt);
     State *S = &P.st[i];
-    // finished instances skip their tiles (a wave-uniform decision)
-    if (PH != PH_TRUE && __builtin_amdgcn_readfirstlane(ld_i32(&S->done)) != 0) return;
+    // instances the sweep does not work on skip their tiles (a wave-uniform decision)
+    if (__builtin_amdgcn_readfirstlane(skip_instance<PH>(P, S) ? 1 : 0) != 0) return;
     const Inst I = get_inst<var_table(VS)>(P, i);
     // diagnostics: count the claims of every (sweep, tile) pair
     const bool trc = P.trace && kTraceClaims + 4 * ((int64_t)epoch * ntot + t) + 3 < P.trace_cap;
@@ -455,7 +579,7 @@ __device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch
         c[2] = wall_clock64();
     }
     double acc[NACC] = {0.0, 0.0, 0.0};
-    tile_body<T, VS, PH>(I, S, it, lt, acc, lane);
+    tile_body<T, VS, PH>(P, I, S, it, lt, acc, lane);
     if (lane == 0 && trc) P.trace[kTraceClaims + 4 * ((int64_t)epoch * ntot + t) + 3] = wall_clock64();
     // publish this tile's partials, then count the tile done
 #pragma unroll
@@ -584,9 +708,16 @@ static __device__ __forceinline__ void mark_timeout(const Params &P) {
 // still streaming), and issues one agent-scope acquire fence after the wait.
 // The workgroup's other waves share the CU's caches and are ordered behind
 // thread 0 by the workgroup barrier.
+// The counters of the control states after a barrier (the snapshot every
+// workgroup reads, so that all take the same path).
+struct Snap {
+    int active, verify, replace, fallback, ntrue;
+};
+
 template <bool TABLE>
-static __device__ __forceinline__ int grid_sync(const Params &P, uint32_t &epoch) {
-    __shared__ int s_last, s_abort, s_act;
+static __device__ __forceinline__ int grid_sync(const Params &P, uint32_t &epoch, Snap &sn) {
+    __shared__ int s_last, s_abort;
+    __shared__ Snap s_snap;
     __syncthreads();
     const uint32_t nb = gridDim.x;
     const uint32_t ng = nb < (uint32_t)NGRP ? nb : (uint32_t)NGRP;
@@ -641,18 +772,32 @@ static __device__ __forceinline__ int grid_sync(const Params &P, uint32_t &epoch
         wait_vm_stores();
         s_last = last;
         s_abort = ab;
-        if (!last && !ab)
-            s_act = (int)__hip_atomic_load(&sy->snap[epoch & 1].v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!last && !ab) {
+            const Counts *c = &sy->snap[epoch & 1];
+            s_snap.active = __hip_atomic_load(&c->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_snap.verify = __hip_atomic_load(&c->verify, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_snap.replace = __hip_atomic_load(&c->replace, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_snap.fallback = __hip_atomic_load(&c->fallback, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_snap.ntrue = __hip_atomic_load(&c->ntrue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     __syncthreads();
     if (s_abort) return -1;
     if (s_last && threadIdx.x < WAVE) {
         // every workgroup has arrived: every tile of the sweep and every
-        // instance reduction is done, so `active` is final for this barrier
+        // instance reduction is done, so the counters are final for this barrier
         if (threadIdx.x == 0) {
-            const int a = __hip_atomic_load(&sy->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sy->snap[epoch & 1].v, (uint32_t)a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_act = a;
+            Counts *c = &sy->snap[epoch & 1];
+            auto take = [&](int32_t *live, int32_t *snap) {
+                const int v = __hip_atomic_load(live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(snap, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return v;
+            };
+            s_snap.active = take(&sy->live.active, &c->active);
+            s_snap.verify = take(&sy->live.verify, &c->verify);
+            s_snap.replace = take(&sy->live.replace, &c->replace);
+            s_snap.fallback = take(&sy->live.fallback, &c->fallback);
+            s_snap.ntrue = take(&sy->live.ntrue, &c->ntrue);
             if (P.trace && 4 * (int64_t)epoch + 3 < P.trace_cap) P.trace[4 * epoch + 2] = wall_clock64();
         }
         // the sweep just finished is done with its pool set; the sweep after
@@ -663,9 +808,15 @@ static __device__ __forceinline__ int grid_sync(const Params &P, uint32_t &epoch
         for (uint32_t k = threadIdx.x; k < ng; k += WAVE)
             __hip_atomic_store(&sy->gen[k].v, epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();  // s_act is set; no wave of this workgroup runs ahead
+    __syncthreads();  // s_snap is set; no wave of this workgroup runs ahead
+    // uniform values (scalar registers), read in every later loop decision
+    sn.active = __builtin_amdgcn_readfirstlane(s_snap.active);
+    sn.verify = __builtin_amdgcn_readfirstlane(s_snap.verify);
+    sn.replace = __builtin_amdgcn_readfirstlane(s_snap.replace);
+    sn.fallback = __builtin_amdgcn_readfirstlane(s_snap.fallback);
+    sn.ntrue = __builtin_amdgcn_readfirstlane(s_snap.ntrue);
     ++epoch;
-    return s_act;
+    return sn.active;
 }
 
 // Waves per SIMD the kernels of a variant must reach: the FP32 table-driven
@@ -679,48 +830,71 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kMinWaves
     Params P) {
     constexpr bool TB = var_table(VS);
     uint32_t epoch = 0;
-    int act;
-    // reference norm when it is not the initial residual itself
-    if (P.norm_ref == GD_REF_UBAR) {
+    Snap sn;
+    // reference norm when it is not the initial residual itself (a warm start
+    // also needs ||ubar - G ubar||, its acceptance bound)
+    if (P.norm_ref == GD_REF_UBAR && P.init != GD_INIT_WARM) {
         run_phase<T, VS, PH_RREF_UBAR>(P, 0, epoch);
-        if (grid_sync<TB>(P, epoch) < 0) return;
+        if (grid_sync<TB>(P, epoch, sn) < 0) return;
     } else if (P.init != GD_INIT_UBAR) {
         run_phase<T, VS, PH_RREF_RES>(P, 0, epoch);
-        if (grid_sync<TB>(P, epoch) < 0) return;
+        if (grid_sync<TB>(P, epoch, sn) < 0) return;
     }
     // initial guess and residual
     if (P.init == GD_INIT_UBAR) run_phase<T, VS, PH_INIT_UBAR>(P, 0, epoch);
     else if (P.init == GD_INIT_ZERO) run_phase<T, VS, PH_INIT_ZERO>(P, 0, epoch);
     else run_phase<T, VS, PH_INIT_GIVEN>(P, 0, epoch);
-    act = grid_sync<TB>(P, epoch);
+    int act = grid_sync<TB>(P, epoch, sn);
     if (act < 0) return;
-    // every workgroup sees the same `act` after each barrier, so all take the
-    // same path through the loop
-    for (int it = 0; it < P.max_iter && act > 0; ++it) {
-        if constexpr (SOLVER == GD_VANCITTERT) {
-            run_phase<T, VS, PH_VC>(P, it, epoch);
-            if ((act = grid_sync<TB>(P, epoch)) < 0) return;
-        } else if constexpr (SOLVER == GD_CG) {
-            run_phase<T, VS, PH_CG1>(P, it, epoch);
-            if (grid_sync<TB>(P, epoch) < 0) return;
-            run_phase<T, VS, PH_CG2>(P, it, epoch);
-            if ((act = grid_sync<TB>(P, epoch)) < 0) return;
-        } else if constexpr (SOLVER == GD_BICGSTAB) {
-            run_phase<T, VS, PH_BIA>(P, it, epoch);
-            if (grid_sync<TB>(P, epoch) < 0) return;
-            run_phase<T, VS, PH_BIB>(P, it, epoch);
-            if (grid_sync<TB>(P, epoch) < 0) return;
-            run_phase<T, VS, PH_BIC>(P, it, epoch);
-            if ((act = grid_sync<TB>(P, epoch)) < 0) return;
-        } else {
-            run_phase<T, VS, PH_SD1>(P, it, epoch);
-            if (grid_sync<TB>(P, epoch) < 0) return;
-            run_phase<T, VS, PH_SD2>(P, it, epoch);
-            if ((act = grid_sync<TB>(P, epoch)) < 0) return;
+    // warm starts no better than ubar restart from ubar
+    if (sn.fallback > 0) {
+        run_phase<T, VS, PH_INIT_UBAR>(P, 0, epoch);
+        if ((act = grid_sync<TB>(P, epoch, sn)) < 0) return;
+    }
+    // every workgroup sees the same snapshot after each barrier, so all take
+    // the same path through the loops
+    int it = 0;
+    for (;;) {
+        while (it < P.max_iter && act > 0) {
+            if constexpr (SOLVER == GD_VANCITTERT) {
+                run_phase<T, VS, PH_VC>(P, it, epoch);
+                if ((act = grid_sync<TB>(P, epoch, sn)) < 0) return;
+            } else if constexpr (SOLVER == GD_CG) {
+                run_phase<T, VS, PH_CG1>(P, it, epoch);
+                if (grid_sync<TB>(P, epoch, sn) < 0) return;
+                run_phase<T, VS, PH_CG2>(P, it, epoch);
+                if ((act = grid_sync<TB>(P, epoch, sn)) < 0) return;
+            } else if constexpr (SOLVER == GD_BICGSTAB) {
+                run_phase<T, VS, PH_BIA>(P, it, epoch);
+                if (grid_sync<TB>(P, epoch, sn) < 0) return;
+                run_phase<T, VS, PH_BIB>(P, it, epoch);
+                if (grid_sync<TB>(P, epoch, sn) < 0) return;
+                run_phase<T, VS, PH_BIC>(P, it, epoch);
+                if ((act = grid_sync<TB>(P, epoch, sn)) < 0) return;
+            } else {
+                run_phase<T, VS, PH_SD1>(P, it, epoch);
+                if (grid_sync<TB>(P, epoch, sn) < 0) return;
+                run_phase<T, VS, PH_SD2>(P, it, epoch);
+                if ((act = grid_sync<TB>(P, epoch, sn)) < 0) return;
+            }
+            ++it;
+            if (sn.verify > 0) break;
+        }
+        if (sn.verify == 0) break;
+        // instances whose recursive residual met tol: their true residual
+        // decides; where it is above tol, the residual is replaced by it
+        run_phase<T, VS, PH_VERIFY>(P, it, epoch);
+        if ((act = grid_sync<TB>(P, epoch, sn)) < 0) return;
+        if (sn.replace > 0) {
+            run_phase<T, VS, PH_REPLACE>(P, it, epoch);
+            if ((act = grid_sync<TB>(P, epoch, sn)) < 0) return;
         }
     }
-    run_phase<T, VS, PH_TRUE>(P, 0, epoch);
-    grid_sync<TB>(P, epoch);
+    // exit true residual of the instances that stopped otherwise
+    if (sn.ntrue > 0) {
+        run_phase<T, VS, PH_TRUE>(P, 0, epoch);
+        grid_sync<TB>(P, epoch, sn);
+    }
 }
 
 // filter_apply: one wave per tile, no reduction.

@@ -37,7 +37,8 @@ struct OpFilter {
     }
 };
 
-// acc0 += (ubar - G x)^2  (true residual; reference norm ||ubar - G ubar||)
+// acc0 += (ubar - G x)^2  (true residual; reference norm ||ubar - G ubar||),
+// acc1 += ubar^2 (read only by the reference sweep, which needs both norms)
 template <typename T, typename C, int VW>
 struct OpResNorm {
     static constexpr int NI = 1, NO = 1;
@@ -49,6 +50,7 @@ struct OpResNorm {
         for (int k = 0; k < VW; ++k) {
             const double d = double(o[0][k]) - double(g[k]);
             acc[0] += d * d;
+            acc[1] += double(o[0][k]) * double(o[0][k]);
         }
     }
 };

@@ -503,22 +503,27 @@ __device__ __forceinline__ double kpow_of(int64_t k2, double kpow, int ipow) {
 // 1/2 w(k_x) |X / N|^2 |k|^p per coefficient, accumulated per shell in LDS.
 // A wave takes whole rows; along a row |k| grows with k_x, so the lanes of a
 // wave hold nondecreasing shells, summed by a segmented scan before one LDS
-// atomic per segment.
+// update per segment.  Every wave of the workgroup (blockDim.x / 64 of them)
+// has its own bins, which no other wave touches, and adds into them in
+// program order; the waves' bins are then summed in wave order.  So the
+// result does not depend on timing.
 template <typename T>
 __global__ __launch_bounds__(256) void k_spectrum_part(const T *X, double *part, int64_t rows_per_field,
                                                        int64_t rows_per_chunk, int64_t nchunks, int64_t nshells, Spec s,
                                                        double kpow, int ipow) {
     using V = typename V2<T>::t;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    double *bins = reinterpret_cast<double *>(lds_raw);
-    for (int64_t i = threadIdx.x; i < nshells; i += 256) bins[i] = 0.0;
+    const int nwaves = (int)(blockDim.x >> 6);
+    double *all_bins = reinterpret_cast<double *>(lds_raw);
+    for (int64_t i = threadIdx.x; i < nwaves * nshells; i += blockDim.x) all_bins[i] = 0.0;
     __syncthreads();
     const int64_t b = blockIdx.x / nchunks, ch = blockIdx.x % nchunks;
     const int64_t row0 = ch * rows_per_chunk, row1 = std::min(rows_per_field, row0 + rows_per_chunk);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double *bins = all_bins + wave * nshells;
     const V *F = reinterpret_cast<const V *>(X) + b * rows_per_field * s.nxh;
     const double inv_n2 = 1.0 / ((double)(s.nx * s.ny * s.nz) * (double)(s.nx * s.ny * s.nz));
-    for (int64_t row = row0 + wave; row < row1; row += 4) {
+    for (int64_t row = row0 + wave; row < row1; row += nwaves) {
         const int64_t ky = row % s.ny, kz = row / s.ny;
         const int64_t a = ky <= s.ny / 2 ? ky : ky - s.ny, c = kz <= s.nz / 2 ? kz : kz - s.nz;
         const int64_t kyz2 = a * a + c * c;
@@ -542,13 +547,18 @@ __global__ __launch_bounds__(256) void k_spectrum_part(const T *X, double *part,
                 const int64_t ok = __shfl_up(key, off, 64);
                 if (lane >= off && ok == key) v += ov;
             }
+            // one lane per segment: distinct bins within this update
             const int64_t next = __shfl_down(key, 1, 64);
-            if (key >= 0 && (lane == 63 || next != key)) atomicAdd(&bins[key], v);
+            if (key >= 0 && (lane == 63 || next != key)) bins[key] += v;
         }
     }
     __syncthreads();
     double *dst = part + (b * nchunks + ch) * nshells;
-    for (int64_t i = threadIdx.x; i < nshells; i += 256) dst[i] = bins[i];
+    for (int64_t i = threadIdx.x; i < nshells; i += blockDim.x) {
+        double acc = all_bins[i];
+        for (int w = 1; w < nwaves; ++w) acc += all_bins[w * nshells + i];
+        dst[i] = acc;
+    }
 }
 
 // out[b][s] = sum over the chunks' partial sums: one workgroup per (field,
@@ -674,7 +684,7 @@ int deconvolve_germano(int32_t solver, const gd_grid *g, double gamma, const voi
     rc = f32 ? forward<float>(s, (const float *)ubar, (float *)UB, MUL_C, ik, st)
              : forward<double>(s, (const double *)ubar, (double *)UB, MUL_C, ik, st);
     if (rc) return rc;
-    if (o->init == GD_INIT_GIVEN) {
+    if (o->init == GD_INIT_GIVEN || o->init == GD_INIT_WARM) {
         rc = f32 ? forward<float>(s, (const float *)u, (float *)U, MUL_C, ik, st)
                  : forward<double>(s, (const double *)u, (double *)U, MUL_C, ik, st);
         if (rc) return rc;
@@ -744,6 +754,9 @@ int energy_spectrum(const gd_grid *g, double kpow, const void *x, double *out, v
     if (gd::ranges_overlap(x, fb, work, need) || gd::ranges_overlap(out, (size_t)s.batch * ns * 8, work, need))
         return fail(GD_EINVAL, "a buffer overlaps the workspace");
     if ((size_t)ns * sizeof(double) > kLdsBudget) return fail(GD_EINVAL, "too many shells");
+    // waves per workgroup: up to four, each with its own bins within the LDS budget
+    const int nw = (int)std::max<int64_t>(1, std::min<int64_t>(4, (int64_t)(kLdsBudget / ((size_t)ns * sizeof(double)))));
+    const size_t lds = (size_t)nw * ns * sizeof(double);
     hipStream_t st = (hipStream_t)stream;
     double *part = (double *)((char *)work + align_up_256((size_t)s.elems * s.tsize));
     const double hp = 0.5 * kpow;
@@ -752,12 +765,12 @@ int energy_spectrum(const gd_grid *g, double kpow, const void *x, double *out, v
     const dim3 grid((unsigned)(s.batch * nch));
     if (g->dtype == GD_F32) {
         if ((rc = forward<float>(s, (const float *)x, (float *)work, MUL_NONE, 0.0, st))) return rc;
-        hipLaunchKernelGGL(k_spectrum_part<float>, grid, dim3(256), ns * sizeof(double), st, (const float *)work, part,
-                           rows, rpc, nch, ns, s, kpow, ipow);
+        hipLaunchKernelGGL(k_spectrum_part<float>, grid, dim3(64 * nw), lds, st, (const float *)work, part, rows, rpc,
+                           nch, ns, s, kpow, ipow);
     } else {
         if ((rc = forward<double>(s, (const double *)x, (double *)work, MUL_NONE, 0.0, st))) return rc;
-        hipLaunchKernelGGL(k_spectrum_part<double>, grid, dim3(256), ns * sizeof(double), st, (const double *)work,
-                           part, rows, rpc, nch, ns, s, kpow, ipow);
+        hipLaunchKernelGGL(k_spectrum_part<double>, grid, dim3(64 * nw), lds, st, (const double *)work, part, rows,
+                           rpc, nch, ns, s, kpow, ipow);
     }
     const int64_t tot = s.batch * ns;
     hipLaunchKernelGGL(k_spectrum_reduce, dim3((unsigned)std::min<int64_t>(tot, 8192)), dim3(256), 0, st, part, out,

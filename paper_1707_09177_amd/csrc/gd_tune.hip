@@ -1,4 +1,4 @@
-// gd_tune.cpp -- tile-shape selection for the stencil sweeps.
+// gd_tune.hip -- tile-shape selection for the stencil sweeps.
 //
 // A tile is one wavefront's unit of work: 64 lanes x vw columns, R rows (3D)
 // and L planes along the march axis.  Wider lanes (16-byte loads) need nx to be

@@ -4,8 +4,9 @@
 // k < kTwN / 2, in FP64.  A transform of length n <= kTwN uses the entries at
 // stride kTwN / n.  The table is evaluated by the compiler from Taylor series
 // on [0, pi/4], with the exact integer reduction k -> (quadrant, octant), so it
-// needs no initialisation at run time.  Plain C++ (also compiled by the host
-// test that checks it against the C library's sin and cos).
+// needs no initialisation at run time.  Plain C++: tests/test_twiddle_table.py
+// compiles it with the host compiler and checks it against the C library's
+// sin and cos.
 #pragma once
 
 namespace gdtw {

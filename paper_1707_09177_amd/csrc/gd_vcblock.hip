@@ -450,6 +450,8 @@ __global__ __launch_bounds__(256) void k_vcb_finish_reduce(Args A, double hw_sqr
     I.r0 = st->r0 * hw_sqrt;
     I.r_final = st->r_last * hw_sqrt;
     I.r_true = sqrt(tsq) * hw_sqrt;
+    I.start = A.init;
+    I.replaced = 0;
 }
 
 // history entries are norms without the spacing weight until scaled here
@@ -600,6 +602,7 @@ int deconvolve_vancittert_blocked(const gd_grid *g, const void *ubar, void *u, c
     int rc = gd::validate_grid(g);
     if (rc) return rc;
     if ((rc = gd::validate_opts(o))) return rc;
+    if (o->init == GD_INIT_WARM) return fail(GD_EINVAL, "the blocked Van Cittert takes the ubar, zero or given start");
     if (o->max_iter > kMaxBlockedIter)
         return fail(GD_EINVAL, "max_iter must be at most %d (the host launches every sweep)", kMaxBlockedIter);
     if (!ubar || !u || !info) return fail(GD_EINVAL, "ubar, u and info must be non-NULL");

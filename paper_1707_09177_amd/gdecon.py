@@ -23,10 +23,11 @@ LIB_PATH = os.path.join(_HERE, "libgdecon.so")
 
 F64, F32 = 0, 1
 SOLVERS = {"vc": 0, "cg": 1, "bicgstab": 2, "sd": 3}
-INITS = {"ubar": 0, "zero": 1, "given": 2}
+INITS = {"ubar": 0, "zero": 1, "given": 2, "warm": 3}
+START_NAMES = {0: "ubar", 1: "zero", 2: "given"}
 NORM_REFS = {"r0ubar": 0, "ubar": 1}
 STATUS = {0: "CONVERGED", 1: "MAXITER", 2: "BREAKDOWN_RHO", 3: "BREAKDOWN_OMEGA", 4: "NONFINITE", 5: "ZERO_REF",
-          6: "TIMEOUT"}
+          6: "TIMEOUT", 7: "STAGNATED"}
 ERRORS = {-1: "GD_EINVAL", -2: "GD_EWORKSPACE", -3: "GD_EHIP", -4: "GD_EALIGN"}
 
 
@@ -43,7 +44,7 @@ class Grid(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("init", ctypes.c_int32), ("norm_ref", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("tol", ctypes.c_double), ("history", ctypes.c_void_p),
+                ("max_replace", ctypes.c_int32), ("tol", ctypes.c_double), ("history", ctypes.c_void_p),
                 ("wait_limit_us", ctypes.c_int64)]
 
 
@@ -74,7 +75,7 @@ class Cnn(ctypes.Structure):
                 ("step", ctypes.c_void_p)]
 
 
-INFO_BYTES = 40  # gd_info: int32 iters, int32 status, 4 doubles
+INFO_BYTES = 48  # gd_info: int32 iters, int32 status, 4 doubles, int32 start, int32 replaced
 
 EXPORTS = ["filter_apply", "deconvolve_workspace_bytes", "deconvolve_vancittert", "deconvolve_cg",
            "deconvolve_bicgstab", "deconvolve_steepest_descent", "gd_status_string", "gd_last_error",
@@ -248,15 +249,17 @@ def workspace_bytes(field_shape, ndim: int, dtype: torch.dtype, solver: str) -> 
 
 
 def decode_info(raw: np.ndarray) -> list[dict]:
-    """raw: uint8 array of batch*40 bytes copied from the device info buffer."""
+    """raw: uint8 array of batch*48 bytes copied from the device info buffer."""
     out = []
     b = raw.reshape(-1, INFO_BYTES)
     for row in b:
         i32 = row[:8].view(np.int32)
-        f64 = row[8:].view(np.float64)
+        f64 = row[8:40].view(np.float64)
+        tail = row[40:48].view(np.int32)
         out.append({"iters": int(i32[0]), "status": int(i32[1]), "status_name": STATUS.get(int(i32[1]), "?"),
                     "r_ref": float(f64[0]), "r0": float(f64[1]), "r_final": float(f64[2]),
-                    "r_true": float(f64[3])})
+                    "r_true": float(f64[3]), "start": START_NAMES.get(int(tail[0]), "?"),
+                    "replaced": int(tail[1])})
     return out
 
 
@@ -308,19 +311,19 @@ class Deconvolver:
 
     def solve(self, ubar: torch.Tensor, max_iter: int, tol: float = 0.0, init: str = "ubar",
               out: torch.Tensor | None = None, norm_ref: str = "r0ubar", history: torch.Tensor | None = None,
-              wait_limit_us: int = 0, stream=None) -> SolveResult:
+              wait_limit_us: int = 0, max_replace: int = 0, stream=None) -> SolveResult:
+        """init: 'ubar' (the paper's start), 'zero', 'given' (the guess in
+        ``out``) or 'warm' (the guess in ``out`` where its residual is below
+        the ubar start's, else ubar).  max_replace: residual replacements
+        allowed after the recursive residual meets tol (0: the library's
+        default, negative: none)."""
         if tuple(ubar.shape) != self.shape or ubar.dtype != self.dtype or ubar.device != self.work.device:
             raise ValueError(f"ubar must have shape {self.shape} and dtype {self.dtype} on {self.work.device}")
-        if init == "given" and out is None:
-            raise ValueError("init='given' reads the initial guess from `out`")
+        if init in ("given", "warm") and out is None:
+            raise ValueError(f"init='{init}' reads the initial guess from `out`")
         u = _out(out, self.shape, ubar)
-        o = Opts()
-        o.max_iter = int(max_iter)
-        o.init = INITS[init]
-        o.norm_ref = NORM_REFS[norm_ref]
-        o.tol = float(tol)
-        o.history = _dev_ptr(history) if history is not None else None
-        o.wait_limit_us = int(wait_limit_us)
+        o = _make_opts(max_iter, tol, init, norm_ref, _dev_ptr(history) if history is not None else None,
+                       wait_limit_us, max_replace)
         if history is not None and (history.dtype != torch.float64 or history.numel() < self.batch * (max_iter + 1)
                                     or history.device != ubar.device):
             raise ValueError("history must be float64 with batch*(max_iter+1) entries, on ubar's device")
@@ -428,9 +431,9 @@ def deconvolve_germano(solver: str, ubar: torch.Tensor, max_iter: int, gamma: fl
     (u, infos, history or None); synchronises the stream."""
     d = GermanoDeconvolver(ubar.shape, ndim, ubar.dtype, solver, gamma, device=ubar.device, h=h)
     out = None
-    if init == "given":
+    if init in ("given", "warm"):
         if u0 is None:
-            raise ValueError("init='given' needs u0")
+            raise ValueError(f"init='{init}' needs u0")
         out = u0.clone()
     hist = None
     if history:
@@ -440,11 +443,12 @@ def deconvolve_germano(solver: str, ubar: torch.Tensor, max_iter: int, gamma: fl
     return res.u, res.info(), hist
 
 
-def _make_opts(max_iter, tol, init, norm_ref, history, wait_limit_us) -> Opts:
+def _make_opts(max_iter, tol, init, norm_ref, history, wait_limit_us, max_replace=0) -> Opts:
     o = Opts()
     o.max_iter = int(max_iter)
     o.init = INITS[init]
     o.norm_ref = NORM_REFS[norm_ref]
+    o.max_replace = int(max_replace)
     o.tol = float(tol)
     o.history = history
     o.wait_limit_us = int(wait_limit_us)
@@ -550,9 +554,9 @@ class BatchDeconvolver:
             self.list[i].history = _dev_ptr(histories[i]) if histories is not None else None
 
     def solve(self, ubars, max_iter: int, tol: float = 0.0, init: str = "ubar", outs=None, norm_ref: str = "r0ubar",
-              histories=None, wait_limit_us: int = 0, stream=None) -> BatchResult:
-        if init == "given" and outs is None:
-            raise ValueError("init='given' reads the initial guesses from `outs`")
+              histories=None, wait_limit_us: int = 0, max_replace: int = 0, stream=None) -> BatchResult:
+        if init in ("given", "warm") and outs is None:
+            raise ValueError(f"init='{init}' reads the initial guesses from `outs`")
         us = [torch.empty_like(b) for b in ubars] if outs is None else list(outs)
         if histories is not None:
             if len(histories) != self.count:
@@ -561,7 +565,7 @@ class BatchDeconvolver:
                 if hst.dtype != torch.float64 or hst.numel() < max_iter + 1:
                     raise ValueError("each history must be float64 with max_iter+1 entries")
         self._bind(ubars, us, histories)
-        o = _make_opts(max_iter, tol, init, norm_ref, None, wait_limit_us)
+        o = _make_opts(max_iter, tol, init, norm_ref, None, wait_limit_us, max_replace)
         _check(self.lib.deconvolve_batch(SOLVERS[self.solver], self.dt, self.list, self.count, ctypes.byref(o),
                                          self.work.data_ptr(), self.work.numel(), self.info_dev.data_ptr(),
                                          _stream_handle(stream)))
@@ -591,9 +595,9 @@ def deconvolve_batch(solver: str, ubars, max_iter: int, tol: float = 0.0, init: 
     dtype.  Returns (list of u, infos, list of histories or None)."""
     b = BatchDeconvolver([t.shape for t in ubars], ubars[0].dtype, solver, device=ubars[0].device)
     outs = None
-    if init == "given":
+    if init in ("given", "warm"):
         if u0s is None:
-            raise ValueError("init='given' needs u0s")
+            raise ValueError(f"init='{init}' needs u0s")
         outs = [t.clone() for t in u0s]
     hists = None
     if history:
@@ -702,22 +706,22 @@ def closure_stress(ubar: torch.Tensor, ustar: torch.Tensor, ndim: int, out: torc
 
 def deconvolve(solver: str, ubar: torch.Tensor, max_iter: int, tol: float = 0.0, ndim: int = 2, init: str = "ubar",
                u0: torch.Tensor | None = None, norm_ref: str = "r0ubar", history: bool = False, h=None,
-               wait_limit_us: int = 0, stream=None):
+               wait_limit_us: int = 0, max_replace: int = 0, stream=None):
     """One-shot solve of G u = ubar.  Returns (u, infos, history or None).
 
     Synchronises the stream to read the per-field info records.
     """
     d = Deconvolver(ubar.shape, ndim, ubar.dtype, solver, device=ubar.device, h=h)
     out = None
-    if init == "given":
+    if init in ("given", "warm"):
         if u0 is None:
-            raise ValueError("init='given' needs u0")
+            raise ValueError(f"init='{init}' needs u0")
         out = u0.clone()
     hist = None
     if history:
         hist = torch.full((d.batch, max_iter + 1), float("nan"), dtype=torch.float64, device=ubar.device)
     res = d.solve(ubar, max_iter, tol, init=init, out=out, norm_ref=norm_ref, history=hist,
-                  wait_limit_us=wait_limit_us, stream=stream)
+                  wait_limit_us=wait_limit_us, max_replace=max_replace, stream=stream)
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     return res.u, res.info(), hist
 

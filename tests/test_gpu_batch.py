@@ -123,27 +123,41 @@ def test_batch_deterministic_and_given_start():
         assert inf["status_name"] in ("CONVERGED", "ZERO_REF") and inf["iters"] <= 1, (i, inf)
 
 
-def test_batch_large_uneven_workload_sampled():
-    """A slice of the 200-instance workload at its real sizes: pass counts
-    against the oracle on the smallest instances, convergence and the true
-    residual on all."""
+@pytest.mark.timeout(600)
+def test_batch_large_uneven_workload_every_instance():
+    """A 24-instance slice of the 200-instance workload at its real sizes (2D
+    up to 1856^2, 3D up to 144^3), in one launch of the table-driven kernel:
+    every instance converges with its true residual within tol, and every
+    instance's u is compared with the oracle's solution to the same
+    tolerance, element by element (relative L2 within the FP32 tolerance:
+    both are within 1e-6 of r_ref of the exact answer).  The oracle runs in
+    its multi-core mode (fixed-chunk sums, the same result on any thread
+    count)."""
     sizes = synth.batch_instances(count=24)
     shapes = [((n, n) if nd == 2 else (n, n, n)) for nd, n in sizes]
+    assert any(nd == 3 and n >= 128 for nd, n in sizes)
     fields = [synth.batch_field(nd, n, i).astype(np.float32) for i, (nd, n) in enumerate(sizes)]
     ubs = [gdecon.filter_apply(to_dev(f, torch.float32), ndim=f.ndim) for f in fields]
+    del fields
     bd = gdecon.BatchDeconvolver(shapes, torch.float32, "bicgstab")
     res = bd.solve(ubs, 200, tol=1e-6)
     infos = res.info()
+    assert gdecon.last_launch()["variant"] == 0          # the kernel that reads every instance's shape from the table
     for i, inf in enumerate(infos):
         assert inf["status_name"] == "CONVERGED", (i, shapes[i], inf)
-        assert inf["r_true"] <= 2e-6 * inf["r_ref"], (i, shapes[i], inf)
-    smallest = sorted(range(len(shapes)), key=lambda i: np.prod(shapes[i]))[:3]
-    for i in smallest:
-        ub = ubs[i].double().cpu().numpy()
-        _, winfo, _ = oracle.solve("bicgstab", ub, ub.ndim, 200, tol=1e-6)
-        assert abs(infos[i]["iters"] - winfo[0]["iters"]) <= 1, (i, shapes[i])
-        want, _, _ = oracle.solve("bicgstab", ub, ub.ndim, infos[i]["iters"], tol=0.0)
-        assert rel_l2(res.u[i].double().cpu().numpy(), want) <= F32_TOL
+        assert inf["r_true"] <= 1e-6 * inf["r_ref"], (i, shapes[i], inf)
+    oracle.set_threads(oracle.host_procs())
+    try:
+        for i in range(len(shapes)):
+            ub = ubs[i].double().cpu().numpy()
+            want, winfo, _ = oracle.solve("bicgstab", ub, ub.ndim, 200, tol=1e-6, sum_mode=oracle.SUM_CHUNKED)
+            assert winfo[0]["status_name"] == "CONVERGED"
+            assert abs(infos[i]["iters"] - winfo[0]["iters"]) <= 1 + infos[i]["replaced"], (i, shapes[i])
+            e = rel_l2(res.u[i].double().cpu().numpy(), want)
+            print(i, shapes[i], "passes", infos[i]["iters"], winfo[0]["iters"], "rel L2 %.2e" % e)
+            assert e <= F32_TOL, (i, shapes[i], e)
+    finally:
+        oracle.set_threads(1)
 
 
 def test_graph_capture_replays_match_eager():

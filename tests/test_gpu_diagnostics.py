@@ -76,3 +76,20 @@ def test_pdf_full_size_twice():
     assert lib.pdf_counts(gdecon.ctypes.byref(g), -5.0, 5.0, 200, t.data_ptr(), a.data_ptr(), None) == 0
     torch.cuda.synchronize()
     np.testing.assert_array_equal(a.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("shape", [(1024, 2048), (64, 64, 64), (4096, 4096)])
+def test_spectrum_bitwise_repeatable(shape):
+    """Each shell is summed in a fixed order (per-wave bins, then waves, then
+    chunks in order), so repeated calls, with unrelated work in between to
+    change the timing, give the same bits."""
+    nd = len(shape)
+    x = torch.randn((2,) + shape, dtype=torch.float32, device="cuda:0",
+                    generator=torch.Generator("cuda:0").manual_seed(3))
+    first = gdecon.energy_spectrum(x, nd, -2.0)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        (torch.randn(1 << 22, device="cuda:0") * 3).sum().item()
+        again = gdecon.energy_spectrum(x, nd, -2.0)
+        torch.cuda.synchronize()
+        assert torch.equal(again, first), rep

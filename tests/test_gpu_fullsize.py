@@ -5,15 +5,15 @@ on the 3 components of a 256^3 velocity (E ~ k^-5/3).
 
 The oracle (FP64, one thread) cannot solve every field within a test, so
 - every field: status CONVERGED, with the true relative residual the library
-  reports within twice the tolerance (the FP32 rounding floor: the updates
-  are FP32, so the recurrence's residual and the true one part at about
-  1e-7 of r_ref);
+  reports within the tolerance (a field stops CONVERGED only after its true
+  residual, evaluated in FP64, has met tol; where the FP32 recurrence had
+  drifted from it, the residual was replaced and the iteration went on);
 - sampled fields: the oracle's pass count to the same tolerance, within one
   pass (FP32 rounding can move a residual that sits on the threshold across
-  it); where the counts agree, u against the oracle's, relative L2 within
-  1e-5 (the FP32 tolerance of the small-size tests); and the true residual
-  ||ubar - G u|| recomputed by the oracle in FP64 from the GPU's u, within
-  twice the tolerance.
+  it) plus one per residual replacement; where the counts
+  agree, u against the oracle's, relative L2 within 1e-5 (the FP32
+  tolerance of the small-size tests); and the true residual ||ubar - G u||
+  recomputed by the oracle in FP64 from the GPU's u, within the tolerance.
 ubar is the oracle's FP64 filter of the fields, rounded to FP32 once.
 """
 import numpy as np
@@ -50,17 +50,17 @@ def test_headline_workload_at_full_size(case):
     print(case, "launch", gdecon.last_launch(), "passes", [i["iters"] for i in infos])
     for b, inf in enumerate(infos):
         assert inf["status_name"] == "CONVERGED", (b, inf)
-        assert inf["r_true"] <= 2 * TOL * inf["r_ref"], (b, inf)
+        assert inf["r_true"] <= TOL * inf["r_ref"], (b, inf)
     got = out.double().cpu().numpy()
     del dub, out
     for b in sampled:
         want, winf, _ = oracle.solve("bicgstab", ub[b], nd, MAX_ITER, tol=TOL)
         assert winf[0]["status_name"] == "CONVERGED"
-        assert abs(infos[b]["iters"] - winf[0]["iters"]) <= 1, (b, infos[b]["iters"], winf[0]["iters"])
+        assert abs(infos[b]["iters"] - winf[0]["iters"]) <= 1 + infos[b]["replaced"], (b, infos[b], winf[0]["iters"])
         if infos[b]["iters"] == winf[0]["iters"]:   # same passes and the same exit: u agrees to FP32 rounding
             e = rel_l2(got[b], want)
             print(case, "field", b, "rel L2 vs oracle %.2e" % e)
             assert e <= F32_TOL
         r_ref = np.linalg.norm(ub[b] - oracle.filter(ub[b], nd))
         r = np.linalg.norm(ub[b] - oracle.filter(got[b], nd))
-        assert r <= 2 * TOL * r_ref, (b, r / r_ref)
+        assert r <= TOL * r_ref * (1 + 1e-9), (b, r / r_ref)

@@ -116,8 +116,9 @@ def test_matches_one_pass_solver_and_zero_ref():
 
 def test_bench_size_converges_like_the_oracle():
     """2048^2 x 16 FP32 to 1e-6 (the bench's Van Cittert comparison): the
-    same pass counts as the one-pass GPU solve, true residuals within twice
-    the tolerance."""
+    same pass counts as the one-pass GPU solve (within one, plus one for each
+    residual replacement the one-pass solve made), true residuals within
+    twice the tolerance (the blocked solve stops on its recursive residual)."""
     from paper_1707_09177_amd import synth
     u = torch.from_numpy(synth.config_fields(2, dtype=np.float32)).cuda()
     ub = gdecon.filter_apply(u, ndim=2)
@@ -126,5 +127,5 @@ def test_bench_size_converges_like_the_oracle():
     info = res.info()
     _, oinf, _ = gdecon.deconvolve("vc", ub, 500, tol=1e-6)
     for gi, oi in zip(info, oinf):
-        assert gi["status_name"] == "CONVERGED" and abs(gi["iters"] - oi["iters"]) <= 1
+        assert gi["status_name"] == "CONVERGED" and abs(gi["iters"] - oi["iters"]) <= 1 + oi["replaced"]
         assert gi["r_true"] <= 2e-6 * gi["r_ref"]

@@ -361,3 +361,50 @@ def test_even_grid_nyquist_null_space():
     u, _, _ = oracle.solve("cg", ubar, 2, 6)
     uh = np.fft.fft2(u)
     assert np.max(np.abs(uh[4, :])) < 1e-12 and np.max(np.abs(uh[:, 4])) < 1e-12
+
+
+def test_threaded_timing_mode_is_thread_count_independent():
+    """The oracle's multi-core timing mode (fixed-chunk compensated sums,
+    loops split over points) gives bitwise the same result on one thread and
+    on every core, and agrees with the serial compensated sums to rounding."""
+    rng = np.random.default_rng(31)
+    ub = oracle.filter(rng.standard_normal((2, 96, 80)), 2)
+    one = oracle.solve("bicgstab", ub, 2, 12, sum_mode=oracle.SUM_CHUNKED)
+    used = oracle.set_threads(max(2, oracle.host_procs()))
+    try:
+        assert used >= 2
+        many = oracle.solve("bicgstab", ub, 2, 12, sum_mode=oracle.SUM_CHUNKED)
+        with pytest.raises(ValueError):            # only the chunked sums may run threaded
+            oracle.solve("bicgstab", ub, 2, 12)
+    finally:
+        oracle.set_threads(1)
+    assert np.array_equal(one[0], many[0]) and one[1] == many[1]
+    assert np.array_equal(one[2], many[2], equal_nan=True)
+    serial = oracle.solve("bicgstab", ub, 2, 12)
+    assert np.max(np.abs(serial[0] - one[0])) <= 1e-13 * np.max(np.abs(serial[0]))
+    # the chunked sum itself: exact on integer-valued data
+    a = rng.integers(-1000, 1000, 100003).astype(np.float64)
+    assert oracle.dot(a, a, 1.0, oracle.SUM_CHUNKED) == float(np.sum(a.astype(np.int64) ** 2))
+
+
+def test_warm_choice_rule():
+    """The guarded warm start keeps a guess only when its residual is finite
+    and strictly below that of the paper's start u0 = ubar."""
+    rng = np.random.default_rng(32)
+    u = rng.standard_normal((9, 11))                 # odd sizes: G is invertible
+    ub = oracle.filter(u, 2)
+    near = ub + 0.5 * (u - ub)                       # residual (1 - G/2 ... ) smaller than ubar's
+    nan = u.copy()
+    nan[3, 4] = np.nan
+    inf = u.copy()
+    inf[0, 0] = np.inf
+    picks = oracle.warm_choice(np.stack([ub] * 6), np.stack([u, near, ub, ub + 1.0, nan, inf]), 2)
+    assert picks == ["given", "given", "ubar", "ubar", "ubar", "ubar"]
+    # the solve from the accepted exact guess converges at once; the rejected
+    # ones run exactly the ubar start
+    x, infos, _ = oracle.solve("cg", np.stack([ub] * 3), 2, 5, tol=1e-12, init="warm",
+                               u0=np.stack([u, ub + 1.0, nan]))
+    assert [i["start"] for i in infos] == ["given", "ubar", "ubar"]
+    assert infos[0]["iters"] == 0 and infos[0]["status_name"] == "CONVERGED"
+    y, jinfos, _ = oracle.solve("cg", np.stack([ub] * 2), 2, 5, tol=1e-12)
+    assert np.array_equal(x[1:], y) and [i["iters"] for i in infos[1:]] == [i["iters"] for i in jinfos]
