@@ -178,6 +178,31 @@ int deconvolve_steepest_descent(const gd_grid *grid, const void *ubar, void *u, 
                                 void *work, size_t work_bytes, gd_info *info, void *stream);
 
 /*
+ * ---- The solve without a workspace argument -----------------------------------
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): the solve of
+ * deconvolve_vancittert / _cg / _bicgstab / _steepest_descent (solver =
+ * GD_VANCITTERT ... GD_STEEPEST_DESCENT) with its workspace (grid-barrier
+ * state, per-field scalars, partial sums, work vectors) in a fixed device
+ * array of deconvolve_noalloc_max_bytes() bytes (32 MiB) that the library
+ * holds on every GPU it runs on until the process ends.  The caller passes
+ * the inputs and outputs only; the arguments, results and info records are
+ * those of the solver's own entry point, bit for bit.  Nothing is allocated:
+ * the call launches the same kernels.  A solve whose workspace
+ * (deconvolve_workspace_bytes) exceeds the array is rejected with
+ * GD_EWORKSPACE before any launch: for BiCGSTAB that allows about 2^20 FP32
+ * or 2^19 FP64 points in the whole batch.  Every call on one GPU uses that
+ * GPU's one array, which keeps the last call's contents: calls that overlap
+ * on one GPU (different streams, or host threads) race and corrupt each
+ * other, so serialise them (one stream).  Errors: those of the solver's
+ * entry point, GD_EWORKSPACE (too large), GD_EHIP.
+ */
+size_t deconvolve_noalloc_max_bytes(void);
+int deconvolve_noalloc(int32_t solver, const gd_grid *grid, const void *ubar, void *u, const gd_opts *opts,
+                       gd_info *info, void *stream);
+
+/*
  * ---- Uneven batches: many independent fields of different sizes ----------
  *
  * One persistent launch solves every instance of the list, each with its own

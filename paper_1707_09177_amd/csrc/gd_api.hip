@@ -878,11 +878,57 @@ int tune_uniform(int solver, const gd_grid *g, const void *ubar, void *u, void *
     return GD_OK;
 }
 
+// ---- the solve without a workspace argument ------------------------------------
+
+// The workspace of deconvolve_noalloc: a fixed device array (one copy per GPU,
+// held until the process ends).  In host code `scratch` names a host-side
+// stand-in, not device memory: kernels get the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch;
+}  // namespace
+
+// Device address of this GPU's scratch array, looked up once per device.
+int scratch_address(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(GD_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return fail(GD_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        it = g_scratch.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return GD_OK;
+}
+
 }  // namespace gd
 
 using namespace gd;
 
 extern "C" {
+
+size_t deconvolve_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int deconvolve_noalloc(int32_t solver, const gd_grid *g, const void *ubar, void *u, const gd_opts *o, gd_info *info,
+                       void *stream) {
+    if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
+    int rc = validate_grid(g);
+    if (rc) return rc;
+    const size_t need = deconvolve_workspace_bytes(g, solver);
+    if (need == 0 || need > kScratchBytes)
+        return fail(GD_EWORKSPACE, "this solve needs %zu bytes of workspace; deconvolve_noalloc holds %zu", need,
+                    kScratchBytes);
+    void *work = nullptr;
+    if ((rc = scratch_address(&work))) return rc;
+    return solve_uniform(solver, g, ubar, u, o, work, kScratchBytes, info, stream, nullptr, nullptr);
+}
 
 int filter_apply(const gd_grid *g, const void *x, void *y, void *stream) {
     int rc = validate_grid(g);

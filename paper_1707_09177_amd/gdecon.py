@@ -82,7 +82,8 @@ EXPORTS = ["filter_apply", "deconvolve_workspace_bytes", "deconvolve_vancittert"
            "gd_last_launch", "gd_set_trace", "deconvolve_batch_workspace_bytes", "deconvolve_batch",
            "deconvolve_autotune", "deconvolve_batch_autotune", "gd_tune_reset", "gd_tune_set", "gd_tune_set_batch", "warmstart_param_count",
            "warmstart_workspace_bytes", "warmstart_forward", "warmstart_train_step", "closure_stress",
-           "germano_filter", "GermanoDeconvolver", "deconvolve_germano", "energy_spectrum", "pdf_counts", "BlockedVanCittert"]
+           "germano_filter", "GermanoDeconvolver", "deconvolve_germano", "energy_spectrum", "pdf_counts", "BlockedVanCittert",
+           "deconvolve_noalloc"]
 
 _lib = None
 
@@ -114,6 +115,10 @@ def load(path: str = LIB_PATH):
     lib.gd_set_trace.argtypes = [ctypes.c_void_p, ctypes.c_int64]
     lib.gd_set_trace.restype = ctypes.c_int
     ip, i32, tp = ctypes.POINTER(Instance), ctypes.c_int32, ctypes.POINTER(TuneInfo)
+    lib.deconvolve_noalloc_max_bytes.argtypes = []
+    lib.deconvolve_noalloc_max_bytes.restype = ctypes.c_size_t
+    lib.deconvolve_noalloc.argtypes = [i32, gp, vp, vp, op, vp, vp]
+    lib.deconvolve_noalloc.restype = ctypes.c_int
     lib.deconvolve_batch_workspace_bytes.argtypes = [i32, i32, ip, i32]
     lib.deconvolve_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.deconvolve_batch.argtypes = [i32, i32, ip, i32, op, vp, ctypes.c_size_t, vp, vp]
@@ -724,6 +729,27 @@ def deconvolve(solver: str, ubar: torch.Tensor, max_iter: int, tol: float = 0.0,
                   wait_limit_us=wait_limit_us, max_replace=max_replace, stream=stream)
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     return res.u, res.info(), hist
+
+
+def deconvolve_noalloc(solver: str, ubar: torch.Tensor, max_iter: int, info: torch.Tensor, tol: float = 0.0,
+                       ndim: int = 2, init: str = "ubar", out: torch.Tensor | None = None, norm_ref: str = "r0ubar",
+                       stream=None) -> torch.Tensor:
+    """The solve with the library's fixed device workspace (deconvolve_noalloc):
+    no allocation, no workspace argument.  ``info``: a device uint8 tensor of
+    batch * INFO_BYTES (decode with decode_info after synchronising); ``out``:
+    the result (read as the guess for init 'given' / 'warm').  Launch only.
+    Calls on one GPU share one workspace: run them one after another."""
+    lib = load()
+    g = make_grid(ubar.shape, ndim, ubar.dtype)
+    if info.dtype != torch.uint8 or info.numel() < int(g.batch) * INFO_BYTES or info.device != ubar.device:
+        raise ValueError(f"info must be uint8 with batch*{INFO_BYTES} bytes on ubar's device")
+    if init in ("given", "warm") and out is None:
+        raise ValueError(f"init='{init}' reads the initial guess from `out`")
+    u = _out(out, ubar.shape, ubar)
+    o = _make_opts(max_iter, tol, init, norm_ref, None, 0)
+    _check(lib.deconvolve_noalloc(SOLVERS[solver], ctypes.byref(g), _dev_ptr(ubar), _dev_ptr(u), ctypes.byref(o),
+                                  _dev_ptr(info), _stream_handle(stream)))
+    return u
 
 
 def deconvolve_vancittert(ubar, max_iter, **kw):
