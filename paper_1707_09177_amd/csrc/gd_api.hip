@@ -773,7 +773,10 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
 constexpr double kTuneMargin = 0.02;
 
 // Time each candidate with short fixed-length solves (4 Krylov or 10 Van
-// Cittert / steepest-descent passes; one warm-up, then the best of three) and return the index of the fastest; candidate 0 is the
+// Cittert / steepest-descent passes; one warm-up, then the best of three),
+// then time the four fastest again, round-robin, best of five more each (the
+// first round's noise is of the order of the differences between the leading
+// candidates), and return the index of the fastest; candidate 0 is the
 // untuned default.
 template <typename Launch>
 int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStream_t stream, gd_tune_info *out) {
@@ -783,35 +786,52 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
         (void)hipEventDestroy(e0);
         return fail(GD_EHIP, "hipEventCreate failed");
     }
-    int best = -1, rc = GD_OK;
-    double best_ms = 0, default_ms = 0;
+    int rc = GD_OK;
+    auto time_once = [&](size_t c, double &ms_out) -> int {
+        (void)hipEventRecord(e0, stream);
+        int r = launch(cands[c]);
+        if (r) return r;
+        (void)hipEventRecord(e1, stream);
+        if (hipEventSynchronize(e1) != hipSuccess) return fail(GD_EHIP, "hipEventSynchronize failed");
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms_out = ms;
+        return GD_OK;
+    };
+    std::vector<double> t(cands.size(), 1e30);
     for (size_t c = 0; c < cands.size() && rc == GD_OK; ++c) {
         if ((rc = launch(cands[c]))) break;
-        double ms_min = 1e30;
         for (int rep = 0; rep < 3 && rc == GD_OK; ++rep) {
-            (void)hipEventRecord(e0, stream);
-            if ((rc = launch(cands[c]))) break;
-            (void)hipEventRecord(e1, stream);
-            if (hipEventSynchronize(e1) != hipSuccess) {
-                rc = fail(GD_EHIP, "hipEventSynchronize failed");
-                break;
-            }
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            ms_min = std::min(ms_min, (double)ms);
-        }
-        if (rc) break;
-        if (c == 0) default_ms = ms_min;
-        // a later candidate must win by a clear margin: ties within the trial
-        // noise keep the earlier (default-like, contiguous-pool) configuration
-        if (best < 0 || ms_min < best_ms * (1.0 - kTuneMargin)) {
-            best = (int)c;
-            best_ms = ms_min;
+            double ms = 0;
+            if ((rc = time_once(c, ms)) == GD_OK) t[c] = std::min(t[c], ms);
         }
     }
+    const double default_first = t.empty() ? 0.0 : t[0];
+    // second round over the leaders (the default always among them)
+    std::vector<size_t> order(cands.size());
+    for (size_t c = 0; c < order.size(); ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return t[a] < t[b]; });
+    std::vector<size_t> lead(order.begin(), order.begin() + std::min<size_t>(4, order.size()));
+    if (std::find(lead.begin(), lead.end(), (size_t)0) == lead.end() && !cands.empty()) lead.push_back(0);
+    std::sort(lead.begin(), lead.end());
+    for (int rep = 0; rep < 5 && rc == GD_OK; ++rep)
+        for (size_t c : lead) {
+            double ms = 0;
+            if ((rc = time_once(c, ms))) break;
+            t[c] = std::min(t[c], ms);
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    // a later candidate must win by a clear margin: ties within the trial
+    // noise keep the earlier (default-like, contiguous-pool) configuration
+    int best = -1;
+    double best_ms = 0;
+    for (size_t c : lead)
+        if (best < 0 || t[c] < best_ms * (1.0 - kTuneMargin)) {
+            best = (int)c;
+            best_ms = t[c];
+        }
     if (out) {
         out->candidates = (int32_t)cands.size();
         out->best = best;
@@ -822,7 +842,7 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
         out->wave_claims = cands[best].wc;
         out->reserved = 0;
         out->best_ms = best_ms;
-        out->default_ms = default_ms;
+        out->default_ms = std::min(default_first, t.empty() ? 0.0 : t[0]);
     }
     return best;
 }

@@ -6,21 +6,19 @@
 // x values (16-byte lanes for the wide variant), so a wave reads 64*VW
 // contiguous elements of a row with one coalesced load per lane.  The filter
 // G = Gx Gy (Gz), with 1D weights (1/4, 1/2, 1/4), is evaluated separably:
-//   * x: each lane also loads its two outer neighbours (x0-1 and x0+VW, with
-//     periodic wrap); they sit in the cache lines the wave is already
-//     reading, so they cost L1/L2 bandwidth, not HBM bandwidth;
+//   * x: in 3D the neighbours x0-1 and x0+VW of a lane's points are the
+//     edge points of the lanes beside it, passed across by full-wave DPP
+//     shifts; only the wave's first lane and its last active lane load a
+//     point of their own (the periodic neighbour outside the wave's span).
+//     In 2D each lane loads its two neighbours itself (L1 hits);
 //   * y (3D only): a tile spans R rows; R+2 rows (one halo row each side) are
 //     x-filtered per plane and combined in registers;
 //   * the march axis: a rolling window of three x(y)-filtered planes.
-// All loads are branch-free (inactive lanes read a valid clamped address and
-// discard the value) and software-pipelined one plane ahead: the inputs of
-// plane m+1 and the centre-only fields of plane m are in flight while plane m
-// is filtered and plane m-1 is written.
-//
 // The stencil input S of a sweep need not be a stored field: the Krylov
 // sweeps evaluate it pointwise from several fields (for example
 // p_{n+1} = r_n + beta (p_n - omega q_n) in BiCGSTAB), so one fused pass both
-// forms p_{n+1} and applies G to it.
+// forms p_{n+1} and applies G to it.  Loads are branch-free (inactive lanes
+// read a valid clamped address and discard the value).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -136,16 +134,136 @@ __device__ __forceinline__ TilePos tile_pos(const Geo &g, int64_t lt, int lane) 
     return p;
 }
 
-// March one tile with the separable stencil.
-//   Op::NI stencil-input fields op.in[f]; op.mix(v[NI]) forms S at a point
-//   Op::NO centre-only fields op.oin[f], loaded for every output point
-//   op.out(idx, s[VW], g[VW], o[NO][VW], acc) consumes S, G S and the centre
-//   fields at VW consecutive output points
-// NDIM 2: R must be 1 (no in-plane y).
-template <int NDIM, int VW, int R, typename T, typename C, class Op>
-__device__ __forceinline__ void march_tile(const Geo &g, int64_t lt, const Op &op, double (&acc)[NACC], int lane) {
-    static_assert(NDIM == 3 || R == 1, "2D tiles are one row wide");
-    constexpr int HR = NDIM == 3 ? R + 2 : 1;
+// Full-wave DPP shifts by one lane (GFX9 wave_shr:1 / wave_shl:1): lane i
+// receives lane i-1's (from_left) or lane i+1's (from_right) value; the lane
+// without a source keeps `v`.  64-bit values move as two 32-bit halves.
+template <int CTRL, typename C>
+__device__ __forceinline__ C dpp_shift(C v) {
+    if constexpr (sizeof(C) == 4) {
+        const int x = __builtin_bit_cast(int, v);
+        return __builtin_bit_cast(C, __builtin_amdgcn_update_dpp(x, x, CTRL, 0xf, 0xf, false));
+    } else {
+        static_assert(sizeof(C) == 8, "32- or 64-bit lanes");
+        const long long x = __builtin_bit_cast(long long, v);
+        const int lo = (int)(x & 0xffffffffll), hi = (int)(x >> 32);
+        const int a = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+        const int b = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+        return __builtin_bit_cast(C, (long long)(((unsigned long long)(unsigned)b << 32) | (unsigned)a));
+    }
+}
+constexpr int kDppWaveShr1 = 0x138;  // lane i <- lane i - 1
+constexpr int kDppWaveShl1 = 0x130;  // lane i <- lane i + 1
+
+// 2D march (one row per plane): the x neighbours are per-lane loads of the
+// points beside the lane's vector (hits in L1: the neighbouring lanes load
+// the same lines), with the next plane's loads and the next output's centre
+// fields issued a whole step ahead.  In 2D this measured faster than the
+// cross-lane form below (2048^2 x 16 BiCGSTAB 4.47 vs 4.62 ms): a plane is a
+// single row, so the extra loads are few and the wave has registers to spare
+// for two planes in flight.
+template <int VW, typename T, typename C, class Op>
+__device__ __forceinline__ void march_row(const Geo &g, int64_t lt, const Op &op, double (&acc)[NACC], int lane) {
+    constexpr int NI = Arr<Op::NI>::n;
+    constexpr int NO = Arr<Op::NO>::n;
+    const TilePos p = tile_pos<VW, 1>(g, lt, lane);
+    auto wrapm = [&](int64_t m) -> int64_t { return m < 0 ? m + g.nmarch : (m >= g.nmarch ? m - g.nmarch : m); };
+
+    // raw stencil inputs of one plane: the lane's vector and its two x neighbours
+    T cv[NI][VW], cl[NI], cr[NI];
+    auto load_in = [&](int64_t mw, T (&v)[NI][VW], T (&l)[NI], T (&r)[NI]) {
+        const int64_t base = mw * g.plane;
+#pragma unroll
+        for (int f = 0; f < Op::NI; ++f) {
+            vld<T, VW>(op.in[f] + base + p.xc, v[f]);
+            l[f] = op.in[f][base + p.xl];
+            r[f] = op.in[f][base + p.xr];
+        }
+    };
+    T co[NO][VW];
+    auto load_out = [&](int64_t m, T (&o)[NO][VW]) {
+#pragma unroll
+        for (int f = 0; f < Op::NO; ++f) vld_nt<T, VW>(op.oin[f] + m * g.plane + p.xc, o[f]);
+    };
+
+    C W0[VW], W1[VW], W2[VW], S1[VW], S2[VW];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) W0[k] = W1[k] = W2[k] = S1[k] = S2[k] = C(0);
+#pragma unroll
+    for (int f = 0; f < NO; ++f)
+#pragma unroll
+        for (int k = 0; k < VW; ++k) co[f][k] = T(0);
+
+    load_in(wrapm(p.m0 - 1), cv, cl, cr);
+    for (int64_t m = p.m0 - 1; m <= p.m1; ++m) {
+        // prefetch: inputs of plane m+1, centre fields of plane m
+        T nv[NI][VW], nl[NI], nr[NI], no[NO][VW];
+        if (m < p.m1) load_in(wrapm(m + 1), nv, nl, nr);
+        if (m >= p.m0 && m < p.m1) load_out(m, no);
+
+        // x-filter plane m
+        C sc[VW], hx[VW], left, right;
+        {
+            T a[NI], b[NI];
+#pragma unroll
+            for (int f = 0; f < NI; ++f) {
+                a[f] = cl[f];
+                b[f] = cr[f];
+            }
+            left = op.mix(a);
+            right = op.mix(b);
+        }
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+            T a[NI];
+#pragma unroll
+            for (int f = 0; f < NI; ++f) a[f] = cv[f][k];
+            sc[k] = op.mix(a);
+        }
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+            const C l = k == 0 ? left : sc[k - 1];
+            const C rr = k == VW - 1 ? right : sc[k + 1];
+            hx[k] = C(0.5) * sc[k] + C(0.25) * (l + rr);
+        }
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+            W0[k] = W1[k];
+            W1[k] = W2[k];
+            W2[k] = hx[k];
+            S1[k] = S2[k];
+            S2[k] = sc[k];
+        }
+        // output plane m-1 (its centre fields were loaded one step ago)
+        if (m > p.m0 && p.act) {
+            C gv[VW];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) gv[k] = C(0.5) * W1[k] + C(0.25) * (W0[k] + W2[k]);
+            op.out((m - 1) * g.plane + p.x0, S1, gv, co, acc);
+        }
+        // rotate the prefetch buffers
+#pragma unroll
+        for (int f = 0; f < NI; ++f) {
+            cl[f] = nl[f];
+            cr[f] = nr[f];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) cv[f][k] = nv[f][k];
+        }
+#pragma unroll
+        for (int f = 0; f < NO; ++f)
+#pragma unroll
+            for (int k = 0; k < VW; ++k) co[f][k] = no[f][k];
+    }
+}
+
+// 3D march: a tile spans R rows of a plane, and R + 2 rows (one halo row
+// each side) are x-filtered per plane and combined in y in registers.  The x
+// neighbours cross lanes by DPP; S is formed as soon as a plane's loads have
+// arrived, and the registers of the raw loads then take the next plane's,
+// which are in flight while the plane is filtered (one raw plane of R + 2
+// rows per wave, not two).  Must be called by the whole wave.
+template <int VW, int R, typename T, typename C, class Op>
+__device__ __forceinline__ void march_slab(const Geo &g, int64_t lt, const Op &op, double (&acc)[NACC], int lane) {
+    constexpr int HR = R + 2;
     constexpr int NI = Arr<Op::NI>::n;
     constexpr int NO = Arr<Op::NO>::n;
     const TilePos p = tile_pos<VW, R>(g, lt, lane);
@@ -154,13 +272,9 @@ __device__ __forceinline__ void march_tile(const Geo &g, int64_t lt, const Op &o
     int64_t rowoff[HR];
 #pragma unroll
     for (int h = 0; h < HR; ++h) {
-        if constexpr (NDIM == 3) {
-            int64_t row = (p.row0 + h - 1) % g.nrows;
-            if (row < 0) row += g.nrows;
-            rowoff[h] = row * nx;
-        } else {
-            rowoff[h] = 0;
-        }
+        int64_t row = (p.row0 + h - 1) % g.nrows;
+        if (row < 0) row += g.nrows;
+        rowoff[h] = row * nx;
     }
     int64_t orow[R];  // output rows, clamped so that loads stay in the field
 #pragma unroll
@@ -169,28 +283,59 @@ __device__ __forceinline__ void march_tile(const Geo &g, int64_t lt, const Op &o
         orow[r] = (row < g.nrows ? row : g.nrows - 1) * nx;
     }
 
+    // the wave's x span: lanes 0 .. last hold field points (a field's last
+    // segment may be partial; nx is a multiple of VW)
+    const int64_t seg0 = p.x0 - (int64_t)lane * VW;
+    const int64_t nseg = nx - seg0 < (int64_t)WAVE * VW ? nx - seg0 : (int64_t)WAVE * VW;
+    const int last = (int)(nseg / VW) - 1;
+    // the periodic neighbours outside the span: lane 0 loads the left one,
+    // lane `last` the right one (when last == 0, lane 0 needs both: the right
+    // one is then loaded when the plane is formed)
+    const int64_t xleft = seg0 == 0 ? nx - 1 : seg0 - 1;
+    const int64_t xright = seg0 + nseg >= nx ? seg0 + nseg - nx : seg0 + nseg;
+    const int64_t xe = lane == 0 ? xleft : (lane == last ? xright : p.xc);
+
     auto wrapm = [&](int64_t m) -> int64_t { return m < 0 ? m + g.nmarch : (m >= g.nmarch ? m - g.nmarch : m); };
 
-    // raw stencil inputs of one plane: centre vector and the two x neighbours
-    T cv[HR][NI][VW], cl[HR][NI], cr[HR][NI];
-    auto load_in = [&](int64_t mw, T (&v)[HR][NI][VW], T (&l)[HR][NI], T (&r)[HR][NI]) {
+    // Loads address a plane as a uniform base (scalar registers) plus a
+    // 32-bit byte offset per lane (a plane holds less than 4 GiB; the host
+    // checks), so a lane keeps one offset per row, not a 64-bit address per
+    // row and field.
+    uint32_t vo[HR], eo[HR], oo[R];
 #pragma unroll
-        for (int h = 0; h < HR; ++h) {
-            const int64_t base = mw * g.plane + rowoff[h];
+    for (int h = 0; h < HR; ++h) {
+        vo[h] = (uint32_t)((rowoff[h] + p.xc) * (int64_t)sizeof(T));
+        eo[h] = (uint32_t)((rowoff[h] + xe) * (int64_t)sizeof(T));
+    }
 #pragma unroll
-            for (int f = 0; f < Op::NI; ++f) {
-                vld<T, VW>(op.in[f] + base + p.xc, v[h][f]);
-                l[h][f] = op.in[f][base + p.xl];
-                r[h][f] = op.in[f][base + p.xr];
+    for (int r = 0; r < R; ++r) oo[r] = (uint32_t)((orow[r] + p.xc) * (int64_t)sizeof(T));
+    auto at = [](const T *base, uint32_t byte_off) {
+        return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+    };
+
+    // raw stencil inputs of the plane in flight: the lane's vector and its edge point
+    T raw[HR][NI][VW], rawe[HR][NI];
+    auto load_in = [&](int64_t mw) {
+#pragma unroll
+        for (int f = 0; f < Op::NI; ++f) {
+            const T *pb = op.in[f] + mw * g.plane;
+#pragma unroll
+            for (int h = 0; h < HR; ++h) {
+                vld<T, VW>(at(pb, vo[h]), raw[h][f]);
+                // every lane loads (no exec-mask branch); lanes other than the
+                // two edge lanes read their own first point, already in L1
+                rawe[h][f] = *at(pb, eo[h]);
             }
         }
     };
-    T co[R][NO][VW];
-    auto load_out = [&](int64_t m, T (&o)[R][NO][VW]) {
+    T co[R][NO][VW];  // centre fields of the plane the next output comes from
+    auto load_out = [&](int64_t m) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+        for (int f = 0; f < Op::NO; ++f) {
+            const T *pb = op.oin[f] + m * g.plane;
 #pragma unroll
-            for (int f = 0; f < Op::NO; ++f) vld_nt<T, VW>(op.oin[f] + m * g.plane + orow[r] + p.xc, o[r][f]);
+            for (int r = 0; r < R; ++r) vld_nt<T, VW>(at(pb, oo[r]), co[r][f]);
+        }
     };
 
     C W0[R][VW], W1[R][VW], W2[R][VW], S1[R][VW], S2[R][VW];
@@ -205,41 +350,48 @@ __device__ __forceinline__ void march_tile(const Geo &g, int64_t lt, const Op &o
 #pragma unroll
             for (int k = 0; k < VW; ++k) co[r][f][k] = T(0);
 
-    load_in(wrapm(p.m0 - 1), cv, cl, cr);
+    load_in(wrapm(p.m0 - 1));
     for (int64_t m = p.m0 - 1; m <= p.m1; ++m) {
-        // prefetch: inputs of plane m+1, centre fields of plane m
-        T nv[HR][NI][VW], nl[HR][NI], nr[HR][NI];
-        T no[R][NO][VW];
-        if (m < p.m1) load_in(wrapm(m + 1), nv, nl, nr);
-        if (m >= p.m0 && m < p.m1) load_out(m, no);
-
-        // x(y)-filter plane m
-        C sc[HR][VW], hx[HR][VW];
+        // form S on plane m from its arrived loads (issued one step ago)
+        C sm[HR][VW], se[HR], sr[HR];
 #pragma unroll
         for (int h = 0; h < HR; ++h) {
-            C left, right;
-            {
-                T a[NI], b[NI];
-#pragma unroll
-                for (int f = 0; f < NI; ++f) {
-                    a[f] = cl[h][f];
-                    b[f] = cr[h][f];
-                }
-                left = op.mix(a);
-                right = op.mix(b);
-            }
 #pragma unroll
             for (int k = 0; k < VW; ++k) {
                 T a[NI];
 #pragma unroll
-                for (int f = 0; f < NI; ++f) a[f] = cv[h][f][k];
-                sc[h][k] = op.mix(a);
+                for (int f = 0; f < NI; ++f) a[f] = raw[h][f][k];
+                sm[h][k] = op.mix(a);
             }
+            se[h] = op.mix(rawe[h]);
+            sr[h] = se[h];
+        }
+        if (last == 0) {  // a one-lane span: lane 0's right neighbour, loaded now
+            const int64_t mw = wrapm(m);
+#pragma unroll
+            for (int h = 0; h < HR; ++h) {
+                T e[NI];
+#pragma unroll
+                for (int f = 0; f < NI; ++f) e[f] = op.in[f][mw * g.plane + rowoff[h] + xright];
+                sr[h] = op.mix(e);
+            }
+        }
+        // prefetch plane m+1 into the registers just freed
+        if (m < p.m1) load_in(wrapm(m + 1));
+
+        // x-filter the R + 2 rows of plane m
+        C hx[HR][VW];
+#pragma unroll
+        for (int h = 0; h < HR; ++h) {
+            C left = dpp_shift<kDppWaveShr1>(sm[h][VW - 1]);
+            C right = dpp_shift<kDppWaveShl1>(sm[h][0]);
+            if (lane == 0) left = se[h];
+            if (lane == last) right = sr[h];
 #pragma unroll
             for (int k = 0; k < VW; ++k) {
-                const C l = k == 0 ? left : sc[h][k - 1];
-                const C rr = k == VW - 1 ? right : sc[h][k + 1];
-                hx[h][k] = C(0.5) * sc[h][k] + C(0.25) * (l + rr);
+                const C l = k == 0 ? left : sm[h][k - 1];
+                const C rr = k == VW - 1 ? right : sm[h][k + 1];
+                hx[h][k] = C(0.5) * sm[h][k] + C(0.25) * (l + rr);
             }
         }
 #pragma unroll
@@ -248,21 +400,16 @@ __device__ __forceinline__ void march_tile(const Geo &g, int64_t lt, const Op &o
             for (int k = 0; k < VW; ++k) {
                 W0[r][k] = W1[r][k];
                 W1[r][k] = W2[r][k];
+                W2[r][k] = C(0.5) * hx[r + 1][k] + C(0.25) * (hx[r][k] + hx[r + 2][k]);
                 S1[r][k] = S2[r][k];
-                if constexpr (NDIM == 3) {
-                    W2[r][k] = C(0.5) * hx[r + 1][k] + C(0.25) * (hx[r][k] + hx[r + 2][k]);
-                    S2[r][k] = sc[r + 1][k];
-                } else {
-                    W2[r][k] = hx[0][k];
-                    S2[r][k] = sc[0][k];
-                }
+                S2[r][k] = sm[r + 1][k];
             }
         // output plane m-1 (its centre fields were loaded one step ago)
         if (m > p.m0) {
             const int64_t mo = m - 1;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (p.act && (NDIM == 2 || p.row0 + r < g.nrows)) {
+                if (p.act && p.row0 + r < g.nrows) {
                     C gv[VW];
 #pragma unroll
                     for (int k = 0; k < VW; ++k) gv[k] = C(0.5) * W1[r][k] + C(0.25) * (W0[r][k] + W2[r][k]);
@@ -270,23 +417,24 @@ __device__ __forceinline__ void march_tile(const Geo &g, int64_t lt, const Op &o
                 }
             }
         }
-        // rotate the prefetch buffers
-#pragma unroll
-        for (int h = 0; h < HR; ++h)
-#pragma unroll
-            for (int f = 0; f < NI; ++f) {
-                cl[h][f] = nl[h][f];
-                cr[h][f] = nr[h][f];
-#pragma unroll
-                for (int k = 0; k < VW; ++k) cv[h][f][k] = nv[h][f][k];
-            }
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int f = 0; f < NO; ++f)
-#pragma unroll
-                for (int k = 0; k < VW; ++k) co[r][f][k] = no[r][f][k];
+        // centre fields of plane m, for the next step's output
+        if (m >= p.m0 && m < p.m1) load_out(m);
     }
+}
+
+// March one tile with the separable stencil.
+//   Op::NI stencil-input fields op.in[f]; op.mix(v[NI]) forms S at a point
+//   Op::NO centre-only fields op.oin[f], loaded for every output point
+//   op.out(idx, s[VW], g[VW], o[NO][VW], acc) consumes S, G S and the centre
+//   fields at VW consecutive output points
+// NDIM 2: R must be 1 (no in-plane y).  Must be called by the whole wave.
+template <int NDIM, int VW, int R, typename T, typename C, class Op>
+__device__ __forceinline__ void march_tile(const Geo &g, int64_t lt, const Op &op, double (&acc)[NACC], int lane) {
+    static_assert(NDIM == 3 || R == 1, "2D tiles are one row wide");
+    if constexpr (NDIM == 2)
+        march_row<VW, T, C>(g, lt, op, acc, lane);
+    else
+        march_slab<VW, R, T, C>(g, lt, op, acc, lane);
 }
 
 // Pointwise pass over a tile (sweeps that need no stencil): only centre fields.

@@ -135,9 +135,6 @@ constexpr int kSteal = NGRP;
 constexpr int kTilesPerWave = 2;
 // Percent of every column's planes cut into short tiles (claimed last).
 constexpr int kTailPct = 15;
-// diagnostics buffer layout: 4 entries per barrier for the first 64 barriers,
-// then one claim counter per (sweep, tile)
-constexpr int64_t kTraceClaims = 256;
 
 struct Params {
     Inst tmpl;            // uniform batch: instance 0 (others offset by stride)

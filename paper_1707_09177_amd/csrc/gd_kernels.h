@@ -562,25 +562,14 @@ __device__ __forceinline__ bool skip_instance(const Params &P, const State *S) {
 template <typename T, int VS, int PH>
 __device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch, int64_t t, int lane) {
     constexpr int nacc = PhaseNacc<PH>::v;
-    const int64_t ntot = P.total_tiles;
     int64_t lt = 0;
     const int i = locate<var_table(VS)>(P, t, lt);
     State *S = &P.st[i];
     // instances the sweep does not work on skip their tiles (a wave-uniform decision)
     if (__builtin_amdgcn_readfirstlane(skip_instance<PH>(P, S) ? 1 : 0) != 0) return;
     const Inst I = get_inst<var_table(VS)>(P, i);
-    // diagnostics: count the claims of every (sweep, tile) pair
-    const bool trc = P.trace && kTraceClaims + 4 * ((int64_t)epoch * ntot + t) + 3 < P.trace_cap;
-    if (lane == 0 && trc) {
-        unsigned long long *c = &P.trace[kTraceClaims + 4 * ((int64_t)epoch * ntot + t)];
-        const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xf;
-        atomicAdd(&c[0], 1ull);
-        c[1] = ((unsigned long long)blockIdx.x << 16) | ((threadIdx.x >> 6) << 8) | xcc;
-        c[2] = wall_clock64();
-    }
     double acc[NACC] = {0.0, 0.0, 0.0};
     tile_body<T, VS, PH>(P, I, S, it, lt, acc, lane);
-    if (lane == 0 && trc) P.trace[kTraceClaims + 4 * ((int64_t)epoch * ntot + t) + 3] = wall_clock64();
     // publish this tile's partials, then count the tile done
 #pragma unroll
     for (int k2 = 0; k2 < nacc; ++k2) {
@@ -599,88 +588,111 @@ __device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch
     if (prev == (uint32_t)I.ntiles - 1) complete_instance<var_table(VS)>(P, I, S, PH, lane, epoch);
 }
 
-// One sweep.  With P.steal > 0 the workgroup takes tiles from the sweep's
-// pools, one per wave per round: thread 0 claims WPB consecutive tiles with one
-// atomic and hands them out through LDS, so the decision to stop is the same
-// for the whole workgroup.  With P.steal == 0, wave w takes tiles w, w + W,
+// One sweep.  With P.steal > 0 the tiles come from the sweep's pools: a
+// workgroup drains its own group's pool, then the others that still hold
+// tiles.  Per-workgroup claims (P.wave_claims == 0): thread 0 claims WPB
+// consecutive tiles with one atomic and hands them out through LDS, so the
+// decision to move on is the same for the whole workgroup; per-wave claims:
+// every wave claims its own.  With P.steal == 0, wave w takes tiles w, w + W,
 // ... (W waves).  A tile's result does not depend on which wave runs it.
+// Every mode feeds one call site of run_tile, so the tile body is inlined
+// once (16 x 2048^2 BiCGSTAB at fixed launch shapes: 4.51 ms, against 4.74 ms
+// with a loop and a call site per mode; in 3D and in uneven batches the body
+// is larger still).
 template <typename T, int VS, int PH>
 __device__ __forceinline__ void run_phase(const Params &P, int it, uint32_t epoch) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
     const int64_t ntot = P.total_tiles;
-    if (P.steal <= 0) {
-        const int64_t wave_gid = (int64_t)blockIdx.x * WPB + wave;
-        const int64_t nwaves = (int64_t)gridDim.x * WPB;
-        for (int64_t t = wave_gid; t < ntot; t += nwaves) run_tile<T, VS, PH>(P, it, epoch, t, lane);
-        return;
-    }
     __shared__ int64_t s_base;
+    __shared__ uint32_t s_left[NGRP];
     const uint32_t nb = gridDim.x;
     const uint32_t ng = nb < (uint32_t)NGRP ? nb : (uint32_t)NGRP;
     const uint32_t grp = blockIdx.x % NGRP;
     // Pool pl owns a contiguous share of the long tiles and a contiguous share
     // of the short ones and hands out its long tiles first: neighbouring tiles
     // (which share halo planes and rows) stay on one XCD and its L2, and the
-    // end of a sweep is made of short tiles.
+    // end of a sweep is made of short tiles.  Interleaved layout: pool pl
+    // hands out tiles pl, pl + ng, ... instead (spreads each field over every
+    // XCD, at the cost of halo reuse in L2).
     const int64_t nbig = P.big_total, nsmall = ntot - P.big_total;
-    // interleaved layout: pool pl hands out tiles pl, pl + ng, ... instead
-    // (spreads each field over every XCD, at the cost of halo reuse in L2)
     const bool ilv = P.interleave != 0;
-    auto pool_blo = [&](uint32_t pl) { return nbig * pl / ng; };
-    auto pool_bcnt = [&](uint32_t pl) { return nbig * (pl + 1) / ng - nbig * pl / ng; };
-    auto pool_slo = [&](uint32_t pl) { return nbig + nsmall * pl / ng; };
-    auto pool_cnt = [&](uint32_t pl) -> int64_t {  // claims in pool pl
-        return ilv ? (ntot - (int64_t)pl + ng - 1) / ng : pool_bcnt(pl) + (nsmall * (pl + 1) / ng - nsmall * pl / ng);
-    };
-    __shared__ uint32_t s_left[NGRP];
-    for (uint32_t h = 0; h < (uint32_t)P.steal && h < ng; ++h) {
-        const uint32_t pl = (grp + h) % ng;
-        if (h == 1) {
-            // Own pool empty: read every pool's counter at once (one round
-            // trip) and steal only from pools that still had tiles.  Counters
-            // only grow, so a pool seen empty stays empty and is skipped.
-            __syncthreads();
-            if (threadIdx.x < ng) {
-                const uint32_t q = threadIdx.x;
-                const uint32_t c = __hip_atomic_load(&P.sync->pool[epoch & 1][q].v, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                s_left[q] = (int64_t)c < P.sync->pcnt[q] ? 1u : 0u;
+    const bool dyn = P.steal > 0;
+    const bool wc = P.wave_claims != 0;
+    const uint32_t hmax = dyn ? ((uint32_t)P.steal < ng ? (uint32_t)P.steal : ng) : 0;
+    int64_t next = (int64_t)blockIdx.x * WPB + wave;  // static mode
+    const int64_t stride = (int64_t)gridDim.x * WPB;
+    uint32_t h = 0, pl = 0;  // pool being drained: the h-th visited
+    bool open = false;
+    int64_t blo = 0, bcnt = 0, slo = 0, cnt = 0;
+    for (;;) {
+        int64_t t;
+        if (!dyn) {
+            if (next >= ntot) break;
+            t = next;
+            next += stride;
+        } else {
+            if (!open) {
+                if (h >= hmax) break;
+                pl = (grp + h) % ng;
+                if (h == 1) {
+                    // Own pool empty: read every pool's counter at once (one
+                    // round trip) and steal only from pools that still had
+                    // tiles.  Counters only grow, so a pool seen empty stays
+                    // empty and is skipped.
+                    __syncthreads();
+                    if (threadIdx.x < ng) {
+                        const uint32_t q = threadIdx.x;
+                        const uint32_t c = __hip_atomic_load(&P.sync->pool[epoch & 1][q].v, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                        s_left[q] = (int64_t)c < P.sync->pcnt[q] ? 1u : 0u;
+                    }
+                    __syncthreads();
+                }
+                if (h > 0 && s_left[pl] == 0) {  // the flags do not change: the same choice in every wave
+                    ++h;
+                    continue;
+                }
+                blo = nbig * pl / ng;
+                bcnt = nbig * (pl + 1) / ng - blo;
+                slo = nbig + nsmall * pl / ng;
+                cnt = ilv ? (ntot - (int64_t)pl + ng - 1) / ng : bcnt + (nsmall * (pl + 1) / ng - nsmall * pl / ng);
+                open = true;
             }
-            __syncthreads();
-        }
-        if (h > 0 && s_left[pl] == 0) continue;  // the flags do not change: the same choice in every wave
-        const int64_t blo = pool_blo(pl), bcnt = pool_bcnt(pl), slo = pool_slo(pl), cnt = pool_cnt(pl);
-        uint32_t *ctr = &P.sync->pool[epoch & 1][pl].v;
-        if (P.wave_claims) {
-            // every wave claims its own tiles.  All lanes take part in the
-            // atomic (lane 0 adds 1, the others 0) and lane 0's result is the
-            // claim, so the loop has no lane-dependent branch: a claim taken
-            // under `if (lane == 0)` and broadcast was turned by the compiler
-            // into a loop that re-read an old claim.
-            for (;;) {
+            uint32_t *ctr = &P.sync->pool[epoch & 1][pl].v;
+            int64_t k;
+            if (wc) {
+                // All lanes take part in the atomic (lane 0 adds 1, the
+                // others 0) and lane 0's result is the claim, so the claim
+                // has no lane-dependent branch: one taken under
+                // `if (lane == 0)` and broadcast was turned by the compiler
+                // into a loop that re-read an old claim.
                 const uint32_t r = __hip_atomic_fetch_add(ctr, lane == 0 ? 1u : 0u, __ATOMIC_RELAXED,
                                                           __HIP_MEMORY_SCOPE_AGENT);
-                const int64_t k = (int64_t)__builtin_amdgcn_readfirstlane(r);
-                if (k >= cnt) break;  // same value in every lane
-                run_tile<T, VS, PH>(P, it, epoch, ilv ? (int64_t)pl + k * ng : (k < bcnt ? blo + k : slo + (k - bcnt)),
-                                    lane);
+                k = (int64_t)__builtin_amdgcn_readfirstlane(r);
+                if (k >= cnt) {  // same value in every lane
+                    open = false;
+                    ++h;
+                    continue;
+                }
+            } else {
+                __syncthreads();  // every wave has read the previous round's s_base
+                if (threadIdx.x == 0)
+                    s_base = (int64_t)__hip_atomic_fetch_add(ctr, (uint32_t)WPB, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                const int64_t base = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)s_base);
+                if (base >= cnt) {  // same decision in every wave of the workgroup
+                    open = false;
+                    ++h;
+                    continue;
+                }
+                k = base + wave;
+                if (k >= cnt) continue;  // no tile for this wave in this round
             }
-            continue;
+            t = ilv ? (int64_t)pl + k * ng : (k < bcnt ? blo + k : slo + (k - bcnt));
         }
-        for (;;) {
-            __syncthreads();  // every wave has read the previous round's s_base
-            if (threadIdx.x == 0)
-                s_base = (int64_t)__hip_atomic_fetch_add(ctr, (uint32_t)WPB, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-            __syncthreads();
-            const int64_t base = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)s_base);
-            if (base >= cnt) break;  // same decision in every wave of the workgroup
-            const int64_t k = base + wave;
-            if (k < cnt)
-                run_tile<T, VS, PH>(P, it, epoch, ilv ? (int64_t)pl + k * ng : (k < bcnt ? blo + k : slo + (k - bcnt)),
-                                    lane);
-        }
+        run_tile<T, VS, PH>(P, it, epoch, t, lane);
     }
 }
 

@@ -72,7 +72,9 @@ struct Args {
     double *hist;     // [field][max_iter + 1] or NULL
     gd_info *info;
     int64_t nx, ny, nz, npts;
-    int64_t tx, ty, tz, tiles;  // tiles per axis / per field
+    int64_t tx, ty, tz, tiles;  // tiles per axis / per field (init and exit kernels; 2D sweeps)
+    int64_t mx, my, mz, stiles; // 3D sweeps: column tiles per axis / per field (the z march)
+    int64_t pslots;             // partial-sum slots per field: max(tiles, stiles)
     int64_t nfields;
     double tol;
     int32_t max_iter, init, norm_ref, steps;
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(256) void k_vcb_init(Args A) {
         }
     }
     const double srr = block_sum(rr, red), srf = block_sum(rf, red);
-    double *pp = A.part + (f * A.tiles + t) * (kMaxK + 1);
+    double *pp = A.part + (f * A.pslots + t) * (kMaxK + 1);
     if (threadIdx.x == 0) {
         pp[0] = srr;
         pp[1] = srf;
@@ -241,8 +243,8 @@ __global__ __launch_bounds__(256) void k_vcb_init_reduce(Args A) {
     __shared__ double red[4];
     const int64_t f = blockIdx.x;
     VState *st = A.st + f;
-    const double r0sq = field_sum(A.part + f * A.tiles * (kMaxK + 1), A.tiles, 0, red);
-    const double rfsq = field_sum(A.part + f * A.tiles * (kMaxK + 1), A.tiles, 1, red);
+    const double r0sq = field_sum(A.part + f * A.pslots * (kMaxK + 1), A.tiles, 0, red);
+    const double rfsq = field_sum(A.part + f * A.pslots * (kMaxK + 1), A.tiles, 1, red);
     if (threadIdx.x != 0) return;
     const double r0 = sqrt(r0sq);
     const double r_ref = (A.norm_ref == GD_REF_R0UBAR && A.init == GD_INIT_UBAR) ? r0 : sqrt(rfsq);
@@ -347,10 +349,203 @@ __global__ __launch_bounds__(256) void k_vcb_sweep(Args A) {
                 uout[gi[q]] = uacc[q];
                 rout[gi[q]] = x[li[q]];
             }
-        double *pp = A.part + (f * A.tiles + t) * (kMaxK + 1);
+        double *pp = A.part + (f * A.pslots + t) * (kMaxK + 1);
         for (int j = 0; j < steps; ++j) {
             const double sj = block_sum(nrm[j], red);
             if (threadIdx.x == 0) pp[j] = sj;
+        }
+    }
+}
+
+// 3D sweeps march along z (2.5D blocking).  A workgroup owns a column of
+// TX x TY interior points and TZ interior planes; it loads r_n one plane at
+// a time with a K-point periodic halo in x and y (the planes K below and
+// above the chunk included), and every pass j = 1 .. K runs one plane behind
+// the pass before it: r_{n+j} on plane p needs r_{n+j-1} on planes p-1, p, p+1.
+// Per plane and pass, the x-y part of G (9 weights) is applied from LDS to
+// the previous pass's plane, and the z part from a window of three such
+// planes that each thread keeps in registers for the points it owns; so LDS
+// holds one plane per pass, not a 3D block with halo in z, and r is read
+// once (plus x-y halo) and written once per K passes.
+constexpr int kMarchThreads = 512;
+
+// sum over the march kernel's workgroup, waves in order
+__device__ __forceinline__ double march_block_sum(double v, double *red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kMarchThreads / 64; ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+template <typename T> struct MShape;
+template <> struct MShape<float> {
+    static constexpr int TX = 64, TY = 32, TZ = 32;
+};
+template <> struct MShape<double> {
+    static constexpr int TX = 32, TY = 32, TZ = 32;
+};
+
+template <typename T, bool REDO>
+__global__ __launch_bounds__(kMarchThreads) void k_vcb_march(Args A) {
+    using S = MShape<T>;
+    constexpr int K = Shape<T, 3>::K;
+    constexpr int RX = S::TX + 2 * K, RY = S::TY + 2 * K, NP = RX * RY;  // a loaded plane (interior + halo)
+    constexpr int CX = RX - 2, NC = CX * (RY - 2);                         // points a pass computes
+    constexpr int NT = kMarchThreads, PL = (NP + NT - 1) / NT, PC = (NC + NT - 1) / NT;
+    __shared__ T buf[K][NP];  // plane of r_{n+j} being consumed, j = 0 .. K-1
+    __shared__ double red[NT / 64];
+    __shared__ int skip, passes, par, any;
+    if (threadIdx.x == 0) any = REDO ? A.glob->redo : A.glob->active;
+    __syncthreads();
+    if (any <= 0) return;
+    const int tid = threadIdx.x;
+    const int64_t plane = A.nx * A.ny;
+    int64_t fcur = -1;
+    for (int64_t bt = blockIdx.x; bt < A.nfields * A.stiles; bt += gridDim.x) {
+        const int64_t f = bt / A.stiles, t = bt % A.stiles;
+        VState *st = A.st + f;
+        if (f != fcur) {
+            __syncthreads();
+            if (tid == 0) {
+                skip = REDO ? st->redo == 0 : st->done != 0;
+                passes = REDO ? st->redo : A.steps;
+                par = st->parity;
+            }
+            __syncthreads();
+            fcur = f;
+        }
+        if (skip) continue;
+        const int p = par;
+        const int steps = passes;
+        const T *rin = static_cast<const T *>(A.r[p]) + f * A.npts;
+        const T *uin = static_cast<const T *>(A.u[p]) + f * A.npts;
+        T *rout = static_cast<T *>(A.r[1 - p]) + f * A.npts;
+        T *uout = static_cast<T *>(A.u[1 - p]) + f * A.npts;
+        const int64_t x0 = (t % A.mx) * S::TX, y0 = ((t / A.mx) % A.my) * S::TY, z0 = (t / (A.mx * A.my)) * S::TZ;
+        const int64_t zlo = z0 - K;
+        // loaded points: in-plane offsets of the region (periodic; a plane
+        // holds fewer than 2^31 points, the host checks)
+        uint32_t lo[PL];
+#pragma unroll
+        for (int q = 0; q < PL; ++q) {
+            const int i = min(tid + NT * q, NP - 1);
+            lo[q] = (uint32_t)(wrapi(y0 + i / RX - K, A.ny) * A.nx + wrapi(x0 + i % RX - K, A.nx));
+        }
+        // computed points: LDS index, interior flag, in-plane offset
+        int li[PC];
+        bool in[PC];
+        uint32_t go[PC];
+#pragma unroll
+        for (int q = 0; q < PC; ++q) {
+            const int i = tid + NT * q;
+            const int cx = i % CX + 1, cy = i / CX + 1;  // region coordinates
+            li[q] = i < NC ? cy * RX + cx : RX + 1;
+            const int64_t gx = x0 + cx - K, gy = y0 + cy - K;
+            in[q] = i < NC && cx >= K && cx < K + S::TX && cy >= K && cy < K + S::TY && gx < A.nx && gy < A.ny;
+            go[q] = in[q] ? (uint32_t)(gy * A.nx + gx) : 0u;
+        }
+        // per pass j: the x-y filtered planes of r_{n+j-1} (window of three)
+        // and its values on the two latest planes, at the thread's points
+        T F[K][3][PC], Cv[K][2][PC];
+        T uacc[K + 1][PC];  // u_n + r_n + ... on the planes in flight (newest last)
+        double nrm[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            nrm[j] = 0.0;
+#pragma unroll
+            for (int q = 0; q < PC; ++q) F[j][0][q] = F[j][1][q] = F[j][2][q] = Cv[j][0][q] = Cv[j][1][q] = T(0);
+        }
+#pragma unroll
+        for (int k = 0; k <= K; ++k)
+#pragma unroll
+            for (int q = 0; q < PC; ++q) uacc[k][q] = T(0);
+        T pre[PL];
+        {
+            const T *src = rin + wrapi(zlo, A.nz) * plane;
+#pragma unroll
+            for (int q = 0; q < PL; ++q) pre[q] = src[lo[q]];
+        }
+        const int nstep = S::TZ + K + steps;  // the last interior plane leaves pass `steps` at step nstep - 1
+        for (int s = 0; s < nstep; ++s) {
+            const int64_t zs = zlo + s;  // plane entering as r_n
+            __syncthreads();             // every read of buf from the previous step is done
+#pragma unroll
+            for (int q = 0; q < PL; ++q)
+                if (tid + NT * q < NP) buf[0][tid + NT * q] = pre[q];
+            // u_n on this plane starts its accumulator
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int q = 0; q < PC; ++q) uacc[k][q] = uacc[k + 1][q];
+            {
+                const bool inz = zs >= z0 && zs < z0 + S::TZ && zs < A.nz;
+                const T *src = uin + (inz ? zs : 0) * plane;
+#pragma unroll
+                for (int q = 0; q < PC; ++q) uacc[K][q] = (inz && in[q]) ? src[go[q]] : T(0);
+            }
+            if (s + 1 < nstep) {  // prefetch the next plane of r_n
+                const T *src = rin + wrapi(zs + 1, A.nz) * plane;
+#pragma unroll
+                for (int q = 0; q < PL; ++q) pre[q] = src[lo[q]];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 1; j <= K; ++j) {
+                if (j > steps) break;
+                // pass j - 1 holds plane zs - (j - 1) in buf[j - 1] (from this step)
+                if (s < 2 * (j - 1)) break;  // ... from step 2 (j - 1) on
+#pragma unroll
+                for (int q = 0; q < PC; ++q) {
+                    const T *b = &buf[j - 1][li[q]];
+                    auto rowf = [&](int o) { return T(0.5) * b[o] + T(0.25) * (b[o - 1] + b[o + 1]); };
+                    F[j - 1][0][q] = F[j - 1][1][q];
+                    F[j - 1][1][q] = F[j - 1][2][q];
+                    F[j - 1][2][q] = T(0.5) * rowf(0) + T(0.25) * (rowf(-RX) + rowf(RX));
+                    Cv[j - 1][0][q] = Cv[j - 1][1][q];
+                    Cv[j - 1][1][q] = b[0];
+                }
+                if (s < 2 * j) break;  // the window of pass j - 1 is complete from step 2 j on
+                // r_{n+j} on plane pz = zs - j
+                const int64_t pz = zs - j;
+                const bool inz = pz >= z0 && pz < z0 + S::TZ && pz < A.nz;
+                T v[PC];
+#pragma unroll
+                for (int q = 0; q < PC; ++q) {
+                    const T c = Cv[j - 1][0][q];
+                    v[q] = c - (T(0.5) * F[j - 1][1][q] + T(0.25) * (F[j - 1][0][q] + F[j - 1][2][q]));
+                    if (inz && in[q]) {
+                        uacc[K - j][q] += c;  // u_{n+j} = u_{n+j-1} + r_{n+j-1}
+                        nrm[j - 1] += double(v[q]) * double(v[q]);
+                    }
+                }
+                if (j == steps) {
+                    if (inz) {
+#pragma unroll
+                        for (int q = 0; q < PC; ++q)
+                            if (in[q]) {
+                                rout[pz * plane + go[q]] = v[q];
+                                uout[pz * plane + go[q]] = uacc[K - j][q];
+                            }
+                    }
+                    break;
+                }
+                // buf[j] was last read in the previous step, before this step's first barrier
+#pragma unroll
+                for (int q = 0; q < PC; ++q)
+                    if (tid + NT * q < NC) buf[j][li[q]] = v[q];
+                __syncthreads();
+            }
+        }
+        double *pp = A.part + (f * A.pslots + t) * (kMaxK + 1);
+        for (int j = 0; j < steps; ++j) {
+            const double sj = march_block_sum(nrm[j], red);
+            if (tid == 0) pp[j] = sj;
         }
     }
 }
@@ -366,7 +561,7 @@ __global__ __launch_bounds__(256) void k_vcb_sweep_reduce(Args A) {
     if (REDO ? st->redo == 0 : st->done != 0) return;  // uniform across the workgroup
     const int steps = REDO ? st->redo : A.steps;
     double tot[kMaxK];
-    for (int j = 0; j < steps; ++j) tot[j] = field_sum(A.part + f * A.tiles * (kMaxK + 1), A.tiles, j, red);
+    for (int j = 0; j < steps; ++j) tot[j] = field_sum(A.part + f * A.pslots * (kMaxK + 1), A.stiles, j, red);
     if (threadIdx.x != 0) return;
     const int p = st->parity;
     if (REDO) {
@@ -434,14 +629,14 @@ __global__ __launch_bounds__(256) void k_vcb_finish(Args A, double hw_sqrt) {
         if (p != 0) uc[g] = a[c];  // the result ended in the workspace copy
     }
     const double ss = block_sum(s, red);
-    if (threadIdx.x == 0) A.part[(f * A.tiles + t) * (kMaxK + 1) + kMaxK] = ss;
+    if (threadIdx.x == 0) A.part[(f * A.pslots + t) * (kMaxK + 1) + kMaxK] = ss;
 }
 
 __global__ __launch_bounds__(256) void k_vcb_finish_reduce(Args A, double hw_sqrt) {
     __shared__ double red[4];
     const int64_t f = blockIdx.x;
     const VState *st = A.st + f;
-    const double tsq = field_sum(A.part + f * A.tiles * (kMaxK + 1), A.tiles, kMaxK, red);
+    const double tsq = field_sum(A.part + f * A.pslots * (kMaxK + 1), A.tiles, kMaxK, red);
     if (threadIdx.x != 0) return;
     gd_info &I = A.info[f];
     I.iters = st->iters;
@@ -488,8 +683,17 @@ constexpr int kMaxBlockedIter = 1 << 20;
 
 struct Layout {
     size_t glob, st, part, r0, r1, u1, total;
-    int64_t tiles;
+    int64_t tiles, stiles, pslots;
 };
+
+// column tiles of the 3D z march
+template <typename T>
+void march_tiles_of(const gd_grid *g, int64_t &mx, int64_t &my, int64_t &mz) {
+    using S = MShape<T>;
+    mx = (g->n[0] + S::TX - 1) / S::TX;
+    my = (g->n[1] + S::TY - 1) / S::TY;
+    mz = (g->n[2] + S::TZ - 1) / S::TZ;
+}
 
 Layout layout(const gd_grid *g) {
     Layout L;
@@ -502,6 +706,14 @@ Layout layout(const gd_grid *g) {
         else tiles_of<double, 3>(g, tx, ty, tz);
     }
     L.tiles = tx * ty * tz;
+    L.stiles = L.tiles;
+    if (g->ndim == 3) {
+        int64_t mx, my, mz;
+        if (g->dtype == GD_F32) march_tiles_of<float>(g, mx, my, mz);
+        else march_tiles_of<double>(g, mx, my, mz);
+        L.stiles = mx * my * mz;
+    }
+    L.pslots = std::max(L.tiles, L.stiles);
     const size_t ts = g->dtype == GD_F32 ? 4 : 8;
     const size_t fb = align_up_256((size_t)g->batch * g->n[0] * g->n[1] * (g->ndim == 3 ? g->n[2] : 1) * ts);
     size_t off = 0;
@@ -510,7 +722,7 @@ Layout layout(const gd_grid *g) {
     L.st = off;
     off = align_up_256(off + (size_t)g->batch * sizeof(VState));
     L.part = off;
-    off = align_up_256(off + (size_t)g->batch * L.tiles * (kMaxK + 1) * sizeof(double));
+    off = align_up_256(off + (size_t)g->batch * L.pslots * (kMaxK + 1) * sizeof(double));
     L.r0 = off;
     L.r1 = off + fb;
     L.u1 = off + 2 * fb;
@@ -541,30 +753,46 @@ int run(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *wor
     A.npts = A.nx * A.ny * A.nz;
     tiles_of<T, NDIM>(g, A.tx, A.ty, A.tz);
     A.tiles = L.tiles;
+    A.stiles = L.stiles;
+    A.pslots = L.pslots;
+    if constexpr (NDIM == 3) march_tiles_of<T>(g, A.mx, A.my, A.mz);
     A.nfields = g->batch;
     A.tol = o->tol;
     A.max_iter = o->max_iter;
     A.init = o->init;
     A.norm_ref = o->norm_ref;
-    const int64_t nblk = g->batch * A.tiles;
+    const int64_t nblk = g->batch * A.tiles, sblk = g->batch * A.stiles;
     if (nblk > 0x7fffffff) return fail(GD_EINVAL, "field too large");
     // resident workgroups of the sweep kernel: its persistent grid
+    auto sweep_fn = [] {
+        if constexpr (NDIM == 3) return k_vcb_march<T, false>;
+        else return k_vcb_sweep<T, NDIM, false>;
+    }();
     int dev = 0, ncu = 0, occ = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_vcb_sweep<T, NDIM, false>, 256, 0) != hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_fn, NDIM == 3 ? kMarchThreads : 256, 0) != hipSuccess)
         return fail(GD_EHIP, "device query failed");
-    const unsigned sweep_blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nblk, (int64_t)std::max(occ, 1) * ncu));
+    const unsigned sweep_blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(sblk, (int64_t)std::max(occ, 1) * ncu));
+    auto launch_sweep = [&](bool redo) {
+        if constexpr (NDIM == 3) {
+            if (redo) hipLaunchKernelGGL((k_vcb_march<T, true>), dim3(sweep_blocks), dim3(kMarchThreads), 0, st, A);
+            else hipLaunchKernelGGL((k_vcb_march<T, false>), dim3(sweep_blocks), dim3(kMarchThreads), 0, st, A);
+        } else {
+            if (redo) hipLaunchKernelGGL((k_vcb_sweep<T, NDIM, true>), dim3(sweep_blocks), dim3(256), 0, st, A);
+            else hipLaunchKernelGGL((k_vcb_sweep<T, NDIM, false>), dim3(sweep_blocks), dim3(256), 0, st, A);
+        }
+    };
     hipLaunchKernelGGL(k_vcb_prep, dim3((unsigned)((g->batch + 255) / 256)), dim3(256), 0, st, A.st, A.glob, g->batch);
     const dim3 per_field((unsigned)g->batch);
     hipLaunchKernelGGL((k_vcb_init<T, NDIM>), dim3((unsigned)nblk), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_vcb_init_reduce, per_field, dim3(256), 0, st, A);
     for (int done = 0; done < o->max_iter; done += S::K) {
         A.steps = std::min(S::K, o->max_iter - done);
-        hipLaunchKernelGGL((k_vcb_sweep<T, NDIM, false>), dim3(sweep_blocks), dim3(256), 0, st, A);
+        launch_sweep(false);
         hipLaunchKernelGGL(k_vcb_sweep_reduce<false>, per_field, dim3(256), 0, st, A);
     }
     A.steps = 0;
-    hipLaunchKernelGGL((k_vcb_sweep<T, NDIM, true>), dim3(sweep_blocks), dim3(256), 0, st, A);
+    launch_sweep(true);
     hipLaunchKernelGGL(k_vcb_sweep_reduce<true>, per_field, dim3(256), 0, st, A);
     // norms above are plain sums; the inner product carries the spacing weight h^d
     const double hw = gd::grid_weight(g);
@@ -610,6 +838,8 @@ int deconvolve_vancittert_blocked(const gd_grid *g, const void *ubar, void *u, c
     if ((uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be 256-byte aligned");
     for (int d = 0; d < g->ndim; ++d)
         if (g->n[d] >= (int64_t(1) << 30)) return fail(GD_EINVAL, "n[%d] must be below 2^30", d);
+    if (g->ndim == 3 && g->n[0] * g->n[1] >= (int64_t(1) << 31))
+        return fail(GD_EINVAL, "a 3D plane must hold fewer than 2^31 points");
     const Layout L = layout(g);
     if (wb < L.total) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", L.total, wb);
     const size_t fb = (size_t)g->batch * g->n[0] * g->n[1] * (g->ndim == 3 ? g->n[2] : 1) * (g->dtype == GD_F32 ? 4 : 8);
