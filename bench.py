@@ -67,9 +67,11 @@ WORKLOADS = {
                     "and 3D n=16*U{4..12} (k^-5/3 on 2<=k<=0.3125n) with probability 1/2, BiCGSTAB to rel. residual "
                     "1e-6 (FP32 storage, FP64 dots/scalars), launch autotuned before timing",
                cfg=4, count=200, key="uneven200", batch=True),
-    "c5": dict(desc="learned warm start: 2D CNN trained on the GPU (Adam, 128^2 crops of 512^2 k^-3 fields), "
-                    "evaluated on 64 held-out 1024^2 fields (k^-3 on 4<=k<=256): BiCGSTAB to rel. residual 1e-6 "
-                    "from the CNN start (network forward included) vs the ubar and zero starts",
+    "c5": dict(desc="learned warm start: 2D CNN trained on the GPU (Adam) on 4096 seeded (ubar, u) pairs of "
+                    "periodic 512^2 k^-3 fields (4<=k<=128), evaluated on 64 held-out 1024^2 fields (k^-3 on "
+                    "4<=k<=256): BiCGSTAB to rel. residual 1e-6 from the guarded CNN start (network forward "
+                    "included) vs the ubar and zero starts and Van Cittert; trapezoidal filter (value) and the "
+                    "paper's differential filter at gamma = 0.1",
                cfg=5, count=64, n=1024, key="warmstart64", warm=True),
     "c3": dict(desc="3D periodic 256^3 x 3 velocity components, E(k)~k^-5/3 on 2<=k<=80, divergence-free, "
                     "BiCGSTAB per component to rel. residual 1e-6 (FP32 storage, FP64 dots/scalars)",
@@ -271,16 +273,21 @@ def cpu_baseline_batch(sizes, us, tol=1e-6, budget_s=20.0):
                        f"{dt:.1f} s, scaled by point count")
 
 
-def batch_result(gd, torch, shapes, ubars, s, steps, warmup, tune, npts, itemsize):
-    """One solver on the uneven batch, timed as replays of a captured graph."""
-    r = time_batch_graph(gd, torch, shapes, ubars, s, steps, warmup, tune=tune)
+def batch_result(gd, torch, shapes, ubars, s, steps, warmup, tune, npts, itemsize, graph=True):
+    """One solver on the uneven batch, timed as replays of a captured graph
+    (or, for counter collection, as eager calls)."""
+    if graph:
+        r = time_batch_graph(gd, torch, shapes, ubars, s, steps, warmup, tune=tune)
+    else:
+        r = dict(time_batch(gd, torch, shapes, ubars, s, steps, warmup, tune=tune), replays_match_eager=None)
     iters = [i["iters"] for i in r["info"]]
     st = sorted({i["status_name"] for i in r["info"]})
     worst_true = max(i["r_true"] / i["r_ref"] for i in r["info"])
     algo = sum(int(np.prod(sh)) * itemsize * accesses(s, it) for sh, it in zip(shapes, iters))
     kern = sum(int(np.prod(sh)) * itemsize * kernel_accesses(s, it) for sh, it in zip(shapes, iters))
     gbs = algo / (r["ms_events"] * 1e-3) / 1e9
-    return dict(ms=r["ms_events"], ms_min=r["ms_min"], wall_ms=r["wall_ms"], timed_as="hipGraph replays",
+    return dict(ms=r["ms_events"], ms_min=r["ms_min"], wall_ms=r["wall_ms"],
+                timed_as="hipGraph replays" if graph else "eager calls",
                 replays_match_eager=r["replays_match_eager"],
                 iters_min=min(iters), iters_max=max(iters), status=st,
                 replaced=sum(i["replaced"] for i in r["info"]),
@@ -304,7 +311,7 @@ def main_batch(args, w, torch, gd, dev):
     for s in solvers:
         results[s] = batch_result(gd, torch, shapes, ubars, s,
                                   args.steps if s == "bicgstab" else max(3, args.steps // 2), args.warmup,
-                                  not args.no_tune, npts, itemsize)
+                                  not args.no_tune, npts, itemsize, graph=not args.no_graph)
     main_s = "bicgstab" if "bicgstab" in results else list(results)[0]
     m = results[main_s]
     out = {
@@ -570,131 +577,172 @@ def main_table1(args, w, torch, gd, dev):
     print(json.dumps(out))
 
 
-def main_warm(args, w, torch, gd, dev):
-    """Train the warm-start network, then time BiCGSTAB from three starts."""
+def event_ms(torch, fn, reps):
+    """Mean ms of fn() over reps calls (one untimed call first), HIP events
+    on the current stream."""
+    stream = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, e in evs:
+        a.record(stream)
+        fn()
+        e.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(e) for a, e in evs]))
+
+
+def train_warm_start(gd, torch, ub, u, ndim, steps, batch, smooth, lr=1e-3, seed=0):
+    """Adam on the pairs (ub[i], u[i]) in shuffled minibatches (a seeded
+    permutation per epoch); the learning rate drops 10x for the last third.
+    Returns the network and a training record."""
     from paper_1707_09177_amd import synth
-    crops = synth.training_pairs(256, n=512, crop=128)
-    ut = torch.from_numpy(np.stack(crops)).to(dev)
-    ubt = gd.filter_apply(ut, ndim=2)
-    net = gd.WarmStart(synth.cnn_init_params(0), lr=1e-3)
-    steps_train, batch = args.train_steps, 32
+    net = gd.WarmStart(synth.cnn_init_params(seed, ndim=ndim), lr=lr, ndim=ndim, smooth=smooth)
+    g = torch.Generator(device="cpu").manual_seed(1707 + seed)
+    count = ub.shape[0]
+    perm, pos = torch.randperm(count, generator=g), 0
+    losses = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    first = None
-    for k in range(steps_train):
-        lo = (k * batch) % len(crops)
-        loss = net.train_step(ubt[lo:lo + batch], ut[lo:lo + batch])
-        if k == 0:
-            first = loss.item()
-        if k == (2 * steps_train) // 3:
-            net.set_lr(3e-4)
+    for k in range(steps):
+        if pos + batch > count:
+            perm, pos = torch.randperm(count, generator=g), 0
+        idx = perm[pos:pos + batch].to(ub.device)
+        pos += batch
+        loss = net.train_step(ub.index_select(0, idx), u.index_select(0, idx))
+        if k == (2 * steps) // 3:
+            net.set_lr(lr / 10)
+        if k % max(1, steps // 8) == 0 or k == steps - 1:
+            losses.append(float(loss.item()))
     torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    last = loss.item()
-    fields = np.stack([synth.field_2d(w["n"], synth.spectrum_kraichnan, 4.0, w["n"] / 4.0,
-                                      synth.rng_for(5, 50000 + i), np.float32) for i in range(w["count"])])
-    u_eval = torch.from_numpy(fields).to(dev)
-    ubar = gd.filter_apply(u_eval, ndim=2)
-    npts = int(ubar.numel())
-    d = gd.Deconvolver(ubar.shape, 2, ubar.dtype, "bicgstab")
-    out = torch.empty_like(ubar)
-    stream = torch.cuda.current_stream()
+    return net, {"steps": steps, "batch": batch, "fields": int(count), "grid": list(ub.shape[1:]), "smooth": smooth,
+                 "seconds": time.perf_counter() - t0, "loss": losses}
 
-    def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-        for a, e in evs:
-            a.record(stream)
-            fn()
-            e.record(stream)
-        torch.cuda.synchronize()
-        return float(np.mean([a.elapsed_time(e) for a, e in evs]))
 
+def warm_starts(gd, torch, net, ubar, make_solver, reps, solvers=("bicgstab", "vc"), band_in_solve=False):
+    """BiCGSTAB to rel. residual 1e-6 from the ubar, zero and network starts
+    (the network's start guarded: a field whose predicted start is no better
+    than ubar starts from ubar), and Van Cittert from ubar, on the same
+    fields.  The network start is timed as forward pass + band projection +
+    solve, and each part on its own; `cnn_unprojected` is the same network
+    without the band projection.  band_in_solve: the solver projects a warm
+    start itself (the differential filter's, on its Fourier coefficients), so
+    the network's output goes to it unprojected."""
     res = {}
+    d = make_solver("bicgstab")
+    out = torch.empty_like(ubar)
     for start in ("ubar", "zero"):
-        ms = timed(lambda: d.solve(ubar, 500, 1e-6, init=start, out=out), args.steps)
+        ms = event_ms(torch, lambda: d.solve(ubar, 500, 1e-6, init=start, out=out), reps)
         inf = d.solve(ubar, 500, 1e-6, init=start, out=out).info()
         res[start] = dict(ms=ms, iters_mean=float(np.mean([i["iters"] for i in inf])),
-                          status=sorted({i["status_name"] for i in inf}),
+                          iters=sorted({i["iters"] for i in inf}), status=sorted({i["status_name"] for i in inf}),
                           worst_true_rel_residual=max(i["r_true"] / i["r_ref"] for i in inf))
     u0 = torch.empty_like(ubar)
+    nd = net.ndim
 
-    def cnn_solve():
-        net.forward(ubar, out=u0)
+    def record(inf, **kw):
+        given = [i for i in inf if i["start"] == "given"]
+        return dict(iters_mean=float(np.mean([i["iters"] for i in inf])), iters=sorted({i["iters"] for i in inf}),
+                    status=sorted({i["status_name"] for i in inf}),
+                    fallbacks=sum(1 for i in inf if i["start"] == "ubar"),
+                    worst_true_rel_residual=max(i["r_true"] / i["r_ref"] for i in inf),
+                    r0_over_ref_mean=float(np.mean([i["r0"] / i["r_ref"] for i in given])) if given else None, **kw)
+
+    ms_fwd = event_ms(torch, lambda: net.forward(ubar, out=u0, band=False), reps)
+    net.forward(ubar, out=u0, band=False)
+    if not band_in_solve:
         out.copy_(u0)
-        d.solve(ubar, 500, 1e-6, init="given", out=out)
+        res["cnn_unprojected"] = record(d.solve(ubar, 500, 1e-6, init="warm", out=out).info())
+        bwork = torch.empty(int(gd.load().band_project_workspace_bytes(gd.make_grid(ubar.shape, nd, ubar.dtype))),
+                            dtype=torch.uint8, device=ubar.device)
+        ms_band = event_ms(torch, lambda: (out.copy_(u0), gd.band_project(ubar, out, nd, work=bwork)), reps) - \
+            event_ms(torch, lambda: out.copy_(u0), reps)
+    else:
+        out.copy_(u0)
+        res["cnn_unprojected"] = record(d.solve(ubar, 500, 1e-6, init="given", out=out).info())
+        ms_band = 0.0  # inside the solve
+    net.forward(ubar, out=u0, band=not band_in_solve)
 
-    ms_fwd = timed(lambda: net.forward(ubar, out=u0), args.steps)
-    ms_total = timed(cnn_solve, args.steps)
-    net.forward(ubar, out=out)
-    inf = d.solve(ubar, 500, 1e-6, init="given", out=out).info()
-    res["cnn"] = dict(ms=ms_total, ms_forward=ms_fwd, iters_mean=float(np.mean([i["iters"] for i in inf])),
-                      status=sorted({i["status_name"] for i in inf}),
-                      worst_true_rel_residual=max(i["r_true"] / i["r_ref"] for i in inf),
-                      r0_over_ref_mean=float(np.mean([i["r0"] / i["r_ref"] for i in inf])))
-    m = res["cnn"]
-    res3 = warm_3d(gd, torch, dev, synth, timed, args)
-    out_line = {
-        "metric": METRIC, "value": npts / (m["ms"] * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": 1, "ms_per_step": m["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+bf16", "data": "synthetic",
-        "config": {"workload": w["desc"], "fields": w["count"], "grid": [w["n"], w["n"]], "points": npts,
-                   "solver": "bicgstab", "tol": 1e-6, "train_steps": steps_train, "train_batch": batch},
-        "warmstart": {"train_seconds": train_s, "loss_first": first, "loss_last": last, "starts": res,
-                      "cnn_vs_ubar_time": res["ubar"]["ms"] / m["ms"]},
-        "warmstart_3d": res3,
-    }
-    print(json.dumps(out_line))
+    def solve_from_u0():
+        out.copy_(u0)
+        d.solve(ubar, 500, 1e-6, init="warm", out=out)
+    ms_solve = event_ms(torch, solve_from_u0, reps) - event_ms(torch, lambda: out.copy_(u0), reps)
+    ms_total = event_ms(torch, lambda: (net.forward(ubar, out=out, band=not band_in_solve),
+                                        d.solve(ubar, 500, 1e-6, init="warm", out=out)), reps)
+    net.forward(ubar, out=out, band=not band_in_solve)
+    res["cnn"] = record(d.solve(ubar, 500, 1e-6, init="warm", out=out).info(), ms=ms_total, ms_forward=ms_fwd,
+                        ms_band_project=ms_band, ms_solve=ms_solve)
+    if "vc" in solvers:
+        dv = make_solver("vc")
+        ms = event_ms(torch, lambda: dv.solve(ubar, 20000, 1e-6, out=out), max(2, reps // 4))
+        inf = dv.solve(ubar, 20000, 1e-6, out=out).info()
+        res["vc"] = dict(ms=ms, iters_mean=float(np.mean([i["iters"] for i in inf])),
+                         status=sorted({i["status_name"] for i in inf}))
+    res["cnn_vs_ubar_passes"] = res["ubar"]["iters_mean"] / res["cnn"]["iters_mean"]
+    res["cnn_vs_zero_passes"] = res["zero"]["iters_mean"] / res["cnn"]["iters_mean"]
+    res["cnn_vs_ubar_time"] = res["ubar"]["ms"] / res["cnn"]["ms"]
+    res["cnn_vs_zero_time"] = res["zero"]["ms"] / res["cnn"]["ms"]
+    if "vc" in res:
+        res["cnn_vs_vc_time"] = res["vc"]["ms"] / res["cnn"]["ms"]
+    return res
 
 
-def warm_3d(gd, torch, dev, synth, timed, args, n_train=64, n_eval=128, count_eval=8):
-    """3D network: trained on 64^3 k^-5/3 fields (batches of 4), evaluated on
-    held-out 128^3 fields (k^-5/3 on 2 <= k <= 40): BiCGSTAB passes and time
-    from the ubar, zero and CNN starts."""
-    fields = synth.training_pairs_3d(16, n=n_train)
-    ut = torch.from_numpy(np.stack(fields)).to(dev)
-    ubt = gd.filter_apply(ut, ndim=3)
-    net = gd.WarmStart(synth.cnn_init_params(0, ndim=3), lr=1e-3, ndim=3)
-    steps = max(1, args.train_steps // 3)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    first = None
-    for k in range(steps):
-        lo = (k * 4) % len(fields)
-        loss = net.train_step(ubt[lo:lo + 4], ut[lo:lo + 4])
-        if k == 0:
-            first = loss.item()
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    last = loss.item()
+def main_warm(args, w, torch, gd, dev):
+    """Config 5: the warm-start network trained on the GPU on 4096 seeded
+    (ubar, u) pairs of periodic 512^2 k^-3 fields, evaluated on 64 held-out
+    1024^2 fields; with the trapezoidal filter (the path's G) and with the
+    paper's differential filter at gamma = 0.1 (its Table 1 setting, where
+    the plain solve needs many passes); plus the 3D network on 128^3."""
+    from paper_1707_09177_amd import synth
+    U = torch.from_numpy(synth.training_fields(args.train_fields, n=512)).to(dev)
+    ev = torch.from_numpy(np.stack([synth.field_2d(w["n"], synth.spectrum_kraichnan, 4.0, w["n"] / 4.0,
+                                                   synth.rng_for(5, 50000 + i), np.float32)
+                                    for i in range(w["count"])])).to(dev)
+    npts = int(ev.numel())
+    out = {"metric": METRIC, "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
+           "data": "synthetic"}
+    regimes = {}
+    # the path's filter: G = the trapezoidal stencil
+    ubt = gd.filter_apply(U, ndim=2)
+    net, rec = train_warm_start(gd, torch, ubt, U, 2, args.train_steps, 8, args.smooth)
+    del ubt
+    ubar = gd.filter_apply(ev, ndim=2)
+    regimes["trapezoidal"] = dict(training=rec, starts=warm_starts(
+        gd, torch, net, ubar, lambda s: gd.Deconvolver(ubar.shape, 2, ubar.dtype, s), args.steps))
+    del net, ubar
+    # the paper's filter G = (I - delta^2 lap)^-1, gamma = 0.1
+    gamma = 0.1
+    ubt = gd.germano_filter(U, gamma, ndim=2)
+    net, rec = train_warm_start(gd, torch, ubt, U, 2, args.train_steps, 8, args.smooth, seed=1)
+    del ubt, U
+    ubar = gd.germano_filter(ev, gamma, ndim=2)
+    regimes["differential_gamma0.1"] = dict(training=rec, starts=warm_starts(
+        gd, torch, net, ubar, lambda s: gd.GermanoDeconvolver(ubar.shape, 2, ubar.dtype, s, gamma, device=dev),
+        args.steps, band_in_solve=True))
+    del net, ubar
+    m = regimes["trapezoidal"]["starts"]["cnn"]
+    out.update(value=npts / (m["ms"] * 1e-3), ms_per_step=m["ms"],
+               config={"workload": w["desc"], "fields": w["count"], "grid": [w["n"], w["n"]], "points": npts,
+                       "solver": "bicgstab", "tol": 1e-6, "train_fields": args.train_fields,
+                       "train_steps": args.train_steps, "train_batch": 8, "smooth": args.smooth},
+               warmstart=regimes, warmstart_3d=warm_3d(gd, torch, dev, synth, args))
+    print(json.dumps(out))
+
+
+def warm_3d(gd, torch, dev, synth, args, n_train=64, n_eval=128, count_eval=8):
+    """3D network: trained on 64^3 k^-5/3 fields, evaluated on held-out
+    128^3 fields (k^-5/3 on 2 <= k <= 40): BiCGSTAB passes and time from the
+    ubar, zero and network starts, trapezoidal filter."""
+    U = torch.from_numpy(np.stack(synth.training_pairs_3d(64, n=n_train))).to(dev)
+    ubt = gd.filter_apply(U, ndim=3)
+    net, rec = train_warm_start(gd, torch, ubt, U, 3, max(1, args.train_steps // 3), 4, args.smooth)
+    del U, ubt
     ev = np.stack([synth.scalar_3d(n_eval, synth.spectrum_kolmogorov, 2.0, 0.3125 * n_eval,
                                    synth.rng_for(6, 60000 + i), np.float32) for i in range(count_eval)])
     ubar = gd.filter_apply(torch.from_numpy(ev).to(dev), ndim=3)
-    d = gd.Deconvolver(ubar.shape, 3, ubar.dtype, "bicgstab")
-    out = torch.empty_like(ubar)
-    res = {}
-    for start in ("ubar", "zero"):
-        ms = timed(lambda: d.solve(ubar, 500, 1e-6, init=start, out=out), args.steps)
-        inf = d.solve(ubar, 500, 1e-6, init=start, out=out).info()
-        res[start] = dict(ms=ms, iters_mean=float(np.mean([i["iters"] for i in inf])),
-                          status=sorted({i["status_name"] for i in inf}))
-    u0 = torch.empty_like(ubar)
-
-    def cnn_solve():
-        net.forward(ubar, out=u0)
-        out.copy_(u0)
-        d.solve(ubar, 500, 1e-6, init="given", out=out)
-
-    ms_fwd = timed(lambda: net.forward(ubar, out=u0), args.steps)
-    ms_total = timed(cnn_solve, args.steps)
-    net.forward(ubar, out=out)
-    inf = d.solve(ubar, 500, 1e-6, init="given", out=out).info()
-    res["cnn"] = dict(ms=ms_total, ms_forward=ms_fwd, iters_mean=float(np.mean([i["iters"] for i in inf])),
-                      status=sorted({i["status_name"] for i in inf}),
-                      r0_over_ref_mean=float(np.mean([i["r0"] / i["r_ref"] for i in inf])))
-    return {"train_steps": steps, "train_seconds": train_s, "loss_first": first, "loss_last": last,
-            "eval": f"{count_eval} x {n_eval}^3", "starts": res}
+    res = warm_starts(gd, torch, net, ubar, lambda s: gd.Deconvolver(ubar.shape, 3, ubar.dtype, s), args.steps)
+    return {"training": rec, "eval": f"{count_eval} x {n_eval}^3", "starts": res}
 
 
 def time_solver(gd, torch, ubar, w, solver, steps, warmup, tol=1e-6, max_iter=500, tune=True):
@@ -776,6 +824,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="uneven batch: time eager calls instead of graph replays (for counter collection)")
     ap.add_argument("--no-extra", action="store_true",
                     help="default workload: skip the 3 x 256^3 and uneven-batch keys")
     ap.add_argument("--no-tune", action="store_true",
@@ -786,7 +836,12 @@ def main():
                          "choices are saved for later --no-tune runs, e.g. under a profiler)")
     ap.add_argument("--solvers", default="bicgstab,cg,vc,vcb",
                     help="vcb: Van Cittert with several passes per sweep (same iterates, less traffic)")
-    ap.add_argument("--train-steps", type=int, default=1500, help="warm-start workload: Adam steps")
+    ap.add_argument("--train-steps", type=int, default=2048,
+                    help="warm-start workload: Adam steps (batches of 8 fields: 4 passes over 4096 fields)")
+    ap.add_argument("--train-fields", type=int, default=4096, help="warm-start workload: 512^2 training fields")
+    ap.add_argument("--smooth", type=int, default=1,
+                    help="warm-start workload: applications of G to the network's output (1 measured best: with the "
+                         "band projection the start needed 4 BiCGSTAB passes at 1 and at 2, at a lower r0 with 1)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (x5): the reference kernel that scales "
                          "FETCH_SIZE / WRITE_SIZE counter readings to bytes")
@@ -922,7 +977,7 @@ def extra_batch(args, w, torch, gd, dev):
     sizes, shapes, us, ubars = make_batch_inputs(w, torch, gd, dev)
     npts = int(sum(int(np.prod(s)) for s in shapes))
     r = batch_result(gd, torch, shapes, ubars, "bicgstab", max(5, args.steps // 2), args.warmup, not args.no_tune,
-                     npts, ubars[0].element_size())
+                     npts, ubars[0].element_size(), graph=not args.no_graph)
     del ubars, us
     return {"workload": w["desc"], "instances": len(shapes), "instances_2d": sum(1 for s in sizes if s[0] == 2),
             "points": npts, "solver": "bicgstab", "points_per_s": r["points_per_s"], "ms": r["ms"],

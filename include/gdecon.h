@@ -292,17 +292,20 @@ void gd_tune_reset(void);
  *
  * The paper starts every deconvolution from u0 = ubar.  The warm start
  * predicts a better u0 with a small periodic convolutional network and hands
- * it to a solver with GD_INIT_GIVEN (the solver itself is unchanged; the
- * plain start stays the fallback):
+ * it to a solver with GD_INIT_WARM (the solver itself is unchanged; the
+ * paper's start stays the fallback: a field whose predicted start has a
+ * residual no smaller than ubar's, or a non-finite one, starts from ubar):
  *     s  = RMS of ubar over the field,  x0 = ubar / s,
- *     a_l = relu(conv_l(a_{l-1}))  for l = 1..5,   y = G conv_6(a_5),
+ *     a_l = relu(conv_l(a_{l-1}))  for l = 1..5,   y = G^m conv_6(a_5),
  *     u0 = ubar + s * y,
  * conv_l a periodic 3x3 (gd_cnn.ndim == 2) or 3x3x3 (ndim == 3)
  * cross-correlation with bias, channels 1 -> 32 -> 32 -> 32 -> 32 -> 32 -> 1,
- * G the deconvolution filter (so the correction lies in the range of G, like
- * the paper's start ubar).  Activations are bfloat16, the 32 -> 32 layers
- * run on the matrix cores with FP32 accumulation.  The grid's ndim must equal
- * the network's; batch = number of fields.
+ * G the trapezoidal deconvolution filter applied m = gd_cnn.smooth times (so
+ * the correction lies in the range of G, like the paper's start ubar, and
+ * the network's rounding noise is damped by G_hat^m where the fields have no
+ * content).  Activations are bfloat16, the 32 -> 32 layers run on the matrix
+ * cores with FP32 accumulation.  The grid's ndim must equal the network's;
+ * batch = number of fields.
  *
  * Parameters: one FP32 vector, layer by layer, each W[cout][tap][cin] with
  * tap = 3*(dy+1) + (dx+1) for the offset (dy, dx) in y and x (in 3D
@@ -312,7 +315,8 @@ typedef struct gd_cnn {
     int32_t ndim;      /* 2 or 3 */
     int32_t channels;  /* 32 */
     int32_t layers;    /* 6 */
-    int32_t reserved;  /* set to 0 */
+    int32_t smooth;    /* m, applications of G to the network's output, 1 .. 8
+                          (0 means 1) */
     float lr, beta1, beta2, eps;  /* Adam hyper-parameters (training only) */
     float *params;     /* device, warmstart_param_count() FP32 values (in/out) */
     float *grad;       /* device, same size, or NULL: the gradient of the last
@@ -390,8 +394,10 @@ int deconvolve_vancittert_blocked(const gd_grid *grid, const void *ubar, void *u
  *   info records as deconvolve_*.  The iteration runs on the Fourier
  *   coefficients (G diagonal there; inner products by Parseval's identity),
  *   between one forward FFT of ubar (and of u when opts->init is
- *   GD_INIT_GIVEN) and one inverse FFT of the result; r_true is evaluated
- *   there too.  Stream-ordered.
+ *   GD_INIT_GIVEN or GD_INIT_WARM) and one inverse FFT of the result; r_true
+ *   is evaluated there too.  A GD_INIT_WARM start is band-projected on its
+ *   coefficients first (band_project's P with tau = 1e-10, see below: free
+ *   here), then judged against the ubar start.  Stream-ordered.
  * Errors: GD_EINVAL (unsupported size, gamma <= 0, NULL, overlaps),
  * GD_EWORKSPACE, GD_EALIGN (workspace not 256-byte aligned), GD_EHIP.
  */
@@ -436,6 +442,31 @@ int pdf_counts(const gd_grid *grid, double lo, double hi, int32_t nbins, const v
                void *stream);
 
 /*
+ * ---- Band projection of a start ---------------------------------------------------
+ *
+ * G is diagonal in Fourier space for both filters (transfer functions
+ * prod_d cos^2(pi k_d / n_d) and Eq. df2), so the
+ * exact solution of G u = ubar has content only at the wavenumbers where ubar
+ * has.  A start u0 that puts content anywhere else (a learned start's error)
+ * leaves a residual there that the Krylov solvers remove slowly, because G_hat
+ * is small outside the band of a filtered field.  band_project removes it:
+ *     u0 <- ubar + P (u0 - ubar),
+ * P keeping the Fourier modes k of field b with |ubar_hat(k)|^2 > tau * E_b,
+ * E_b the mean of |ubar_hat(k)|^2 over all wavenumbers (Parseval: the mean of
+ * ubar^2 times the point count), and zeroing the others.  tau = 0 keeps every
+ * mode at which ubar is nonzero.  Computed by FFT (the differential filter's
+ * transforms), in grid->dtype with FP64 power sums; power-of-two sizes as for
+ * the differential filter.  ubar, u0: device fields of the grid (u0 in/out,
+ * not overlapping ubar); work of band_project_workspace_bytes() (0 for an
+ * unsupported grid).  Stream-ordered.
+ * Errors: GD_EINVAL (size, tau < 0 or not finite, NULL, overlaps),
+ * GD_EWORKSPACE, GD_EALIGN, GD_EHIP.
+ */
+size_t band_project_workspace_bytes(const gd_grid *grid);
+int band_project(const gd_grid *grid, double tau, const void *ubar, void *u0, void *work, size_t work_bytes,
+                 void *stream);
+
+/*
  * ---- Closure stress ----------------------------------------------------------
  *
  * The sub-filter stress of the filtered equations, tau_ij = ubar_i ubar_j -
@@ -472,11 +503,10 @@ int gd_last_launch(gd_launch_info *out);
 /* Diagnostics: while set, every solve records, for its k-th grid barrier,
  * buf[4k] = first arrival, buf[4k+1] = last arrival, buf[4k+2] = release and
  * buf[4k+3] = latest per-field reduction, in device wall-clock ticks
- * (hipDeviceAttributeWallClockRate kHz), for k < 64; from buf[256] on, one
- * counter per (sweep s, tile t) at buf[256 + s * tiles + t] counts how often
- * the tile was claimed in that sweep.  The caller initialises buf (first
- * arrival to UINT64_MAX, the others to 0) before each solve.  buf: device
- * memory of `capacity` uint64 entries; NULL switches recording off. */
+ * (hipDeviceAttributeWallClockRate kHz), for 4k + 3 < capacity.  The caller
+ * initialises buf (first arrival to UINT64_MAX, the others to 0) before each
+ * solve.  buf: device memory of `capacity` uint64 entries; NULL switches
+ * recording off. */
 int gd_set_trace(uint64_t *buf, int64_t capacity);
 
 #ifdef __cplusplus

@@ -179,6 +179,31 @@ def closure_stress(ubar: np.ndarray, ustar: np.ndarray, ndim: int) -> np.ndarray
     return np.stack(out, axis=-ndim - 1)
 
 
+WARM_BAND_TAU = 1e-10   # the differential-filter solve's band projection of a warm start
+
+
+def band_project(ubar: np.ndarray, u0: np.ndarray, ndim: int, tau: float) -> np.ndarray:
+    """u0 restricted to the Fourier support of ubar around ubar:
+    ubar + P (u0 - ubar), P keeping the modes k of each field with
+    |ubar_hat(k)|^2 > tau * E, E the mean of |ubar_hat(k)|^2 over all N
+    wavenumbers (ubar_hat the unnormalized DFT; by Parseval E = sum_x ubar^2).
+    The filters are diagonal in Fourier space, so G^-1 ubar has no content
+    outside that support.  Full complex DFTs over the last ndim axes."""
+    ubar = np.asarray(ubar, dtype=np.float64)
+    u0 = np.asarray(u0, dtype=np.float64)
+    fshape = ubar.shape[-ndim:]
+    ub = ubar.reshape((-1,) + fshape)
+    g0 = u0.reshape(ub.shape)
+    out = np.empty_like(ub)
+    for b in range(ub.shape[0]):
+        UB = np.fft.fftn(ub[b])
+        U0 = np.fft.fftn(g0[b])
+        power = np.abs(UB) ** 2
+        keep = power > tau * power.mean()
+        out[b] = ub[b] + np.real(np.fft.ifftn(np.where(keep, U0 - UB, 0.0)))
+    return out.reshape(ubar.shape)
+
+
 def dot(a: np.ndarray, b: np.ndarray, hw: float, sum_mode: int = 0) -> float:
     lib = _load()
     a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
@@ -218,7 +243,9 @@ def solve(solver: str, ubar: np.ndarray, ndim: int, max_iter: int, tol: float = 
     G is the trapezoidal stencil, or with ``gamma`` set the differential
     filter of Sec. 4 (``germano_filter``).  init: 'ubar' (the paper's),
     'zero', 'given' (u0), or 'warm' (u0 where ``warm_choice`` accepts it,
-    else ubar).
+    else ubar).  With ``gamma`` a warm u0 is first band-projected
+    (``band_project`` with WARM_BAND_TAU): with the differential filter the
+    solve works on Fourier coefficients, where the projection costs nothing.
     Returns (u, infos, hist): u like ubar; infos a list of dicts (with the
     start used); hist an array (batch, max_iter+1) of ||r_k|| with NaN past
     the last pass.
@@ -235,6 +262,8 @@ def solve(solver: str, ubar: np.ndarray, ndim: int, max_iter: int, tol: float = 
     if init in ("given", "warm"):
         if u0 is None:
             raise ValueError(f"init='{init}' needs u0")
+        if init == "warm" and gamma is not None:
+            u0 = band_project(ubar, u0, ndim, WARM_BAND_TAU)
         u[:] = np.asarray(u0, dtype=np.float64).reshape(B, npts)
         if init == "warm":
             starts = warm_choice(ubar, u0, ndim, gamma=gamma, h=h, sum_mode=sum_mode)

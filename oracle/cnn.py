@@ -15,14 +15,17 @@ u0 with a residual correction predicted by a small convolutional network:
     x0  = ubar / s                                   (1 channel)
     a_l = relu(conv_l(a_{l-1}))       l = 1 .. L-1   (C channels)
     z   = conv_L(a_{L-1})                            (1 channel, no activation)
-    y   = G z                                        (the deconvolution filter)
+    y   = G^m z                                      (the deconvolution filter, m >= 1 times)
     u0  = ubar + s * y
 
 conv_l is a periodic 3x3 cross-correlation with bias (the fields are periodic,
 like the filter G).  The final G keeps the correction in the range of G, as
 the paper's own start u0 = ubar is: without it, the correction carries
 content where G's transfer function nearly vanishes (next to the Nyquist
-planes), the one place where the Krylov solvers converge slowly.  Training
+planes), the one place where the Krylov solvers converge slowly.  Applied m
+times (`smooth`), it damps the network's rounding noise outside the band of
+the fields by G_hat^m while the network learns G^-m of the correction on the
+band, where G_hat is bounded below.  Training
 minimises the mean over all points of (y - t)^2 with t = (u - ubar) / s, the
 per-sample normalised correction, with Adam.
 
@@ -131,10 +134,17 @@ def rms(ubar: np.ndarray) -> np.ndarray:
     return np.where(s > 0, s, 1.0)
 
 
-def forward(params, ubar, channels=32, layers=6, emulate_bf16=False, ndim=2):
+def g_power(x: np.ndarray, ndim: int, m: int) -> np.ndarray:
+    """G^m x: the trapezoidal filter applied m times."""
+    for _ in range(m):
+        x = g_filter(x, ndim)
+    return x
+
+
+def forward(params, ubar, channels=32, layers=6, emulate_bf16=False, ndim=2, smooth=1):
     """Network forward on ubar (B, ny, nx) or (B, nz, ny, nx).  Returns a dict
     with the input scale s, the input x0, the stored activations a_1 ..
-    a_{L-1}, the output y and the warm start u0."""
+    a_{L-1}, the output y = G^smooth z and the warm start u0."""
     ubar = np.asarray(ubar, dtype=np.float64)
     P = unpack(np.asarray(params, dtype=np.float64), channels, layers, ndim)
     if emulate_bf16:
@@ -147,7 +157,7 @@ def forward(params, ubar, channels=32, layers=6, emulate_bf16=False, ndim=2):
     for li, (W, b) in enumerate(P):
         z = conv(a, W, b)
         if li == len(P) - 1:
-            y = g_filter(z[..., 0], ndim)
+            y = g_power(z[..., 0], ndim, smooth)
             break
         a = np.maximum(z, 0.0)
         if emulate_bf16:
@@ -157,16 +167,16 @@ def forward(params, ubar, channels=32, layers=6, emulate_bf16=False, ndim=2):
     return {"s": s, "x0": x0, "acts": acts, "y": y, "u0": u0, "P": P}
 
 
-def loss_and_grad(params, ubar, u, channels=32, layers=6, emulate_bf16=False, ndim=2):
+def loss_and_grad(params, ubar, u, channels=32, layers=6, emulate_bf16=False, ndim=2, smooth=1):
     """Training loss mean((y - t)^2), t = (u - ubar) / s, and its gradient
     with respect to the flat parameter vector (backpropagation)."""
-    f = forward(params, ubar, channels, layers, emulate_bf16, ndim)
+    f = forward(params, ubar, channels, layers, emulate_bf16, ndim, smooth)
     s = f["s"].reshape((-1,) + (1,) * ndim)
     t = (np.asarray(u, dtype=np.float64) - ubar) / s
     r = f["y"] - t
     n = r.size
     loss = float(np.sum(r * r) / n)
-    g = g_filter((2.0 / n) * r, ndim)[..., None]   # dL/dz = G dL/dy (G is symmetric)
+    g = g_power((2.0 / n) * r, ndim, smooth)[..., None]   # dL/dz = G^m dL/dy (G is symmetric)
     grads = [None] * len(f["P"])
     ins = [f["x0"]] + f["acts"]
     for li in range(len(f["P"]) - 1, -1, -1):

@@ -243,6 +243,223 @@ __global__ __launch_bounds__(256) void k_conv_mid(const bf16 *in, const bf16 *wm
     }
 }
 
+// ---------------------------------------------------------------- fused 2D forward
+//
+// Inference in 2D runs all six layers in one kernel, so no activation goes
+// through HBM.  A workgroup owns a strip of FV output columns and up to FY
+// rows of one sample and marches down it.  Layer l keeps the rows of its
+// input that its 3x3 taps need in an LDS ring (layers 2 .. 6; layer 1 reads
+// ubar / s from a ring of its own); at step s layer l computes row
+// ys + s - 2 (l - 1), two rows behind layer l - 1, so every input row a layer
+// reads was written in an earlier step, and the row it writes goes to the
+// fourth ring slot, which no layer reads in that step: one barrier per step.
+// Columns: a frame of FW = 64 columns starting 5 left of the strip.  Layer l's
+// row is needed on frame columns l - 1 .. FV + 10 - l, so with FV = 54 every
+// layer computes the frame's 64 columns (two MFMA tiles for the 32 -> 32
+// layers, one column per lane for layer 1) and layer 6 the strip's 54.
+// A wave's work in a step has no branch (a layer outside its rows computes
+// on stale ring rows and does not write), so the scheduler can interleave
+// the matrix products with the vector work of layers 1 and 6.
+constexpr int FW = 64, FV = FW - 10, FY = 256, FRC = FW + 2;  // frame, strip, rows per workgroup, ring columns
+constexpr int FTHREADS = 512;
+constexpr int RSL = 4;        // ring slots: three rows read, the fourth written in the same step
+constexpr int RTR = RSL;      // a fifth slot per ring takes the rows of layers outside their rows
+constexpr int URC = FRC;      // ubar ring columns: frame -1 .. FW
+constexpr int URS = 64;       // ubar ring rows
+constexpr int UBATCH = 16;    // ubar rows loaded together, every UBATCH steps
+constexpr size_t kRingBytes = (size_t)(NL - 1) * (RSL + 1) * FRC * PSTR * sizeof(bf16);
+constexpr size_t kFusedLds = kRingBytes + URS * URC * sizeof(float) + 2 * 8 * 64 * sizeof(float);
+static_assert(kFusedLds <= 160 * 1024, "LDS of one CU");
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// max(x, 0) as one integer max on the bits (a negative float is a negative
+// integer): fmaxf also quiets signalling NaNs, one more instruction per value
+__device__ __forceinline__ float relu_bits(float x) {
+    return __builtin_bit_cast(float, max(__builtin_bit_cast(int, x), 0));
+}
+
+// Workgroup barrier ordering LDS only: the fused kernel's threads share data
+// through LDS alone, and a full barrier would also wait for the global loads
+// it keeps in flight across steps.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <typename T>
+__global__ __launch_bounds__(FTHREADS) void k_fwd2d_fused(const T *ub, const double *s, const bf16 *wbf,
+                                                          const float *params, Offsets off, float *z, int H, int W) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char fused_lds[];
+    bf16 *ring = reinterpret_cast<bf16 *>(fused_lds);                  // [layer 2..6][slot RSL][FRC][PSTR]
+    float *uring = reinterpret_cast<float *>(fused_lds + kRingBytes);  // ubar / s: [row slot URS][URC]
+    float *zpart = uring + URS * URC;  // layer 6 partial sums [step parity][wave][column]
+    auto at = [&](int l, int slot, int col) { return ring + (((l - 2) * (RSL + 1) + slot) * FRC + col) * PSTR; };
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int b = blockIdx.z;
+    const int x0 = blockIdx.x * FV, y0 = blockIdx.y * FY;
+    const int rows = min(FY, H - y0);
+    const int ys = y0 - 5;  // first row of layer 1's output
+    const int64_t HW = (int64_t)H * W;
+    const T *ubs = ub + (int64_t)b * HW;
+    const float inv = (float)(1.0 / s[b]);
+    // clear the rings once: ring columns 0 and FRC - 1 are never written and
+    // feed only frame columns whose results are not needed
+    for (int i = tid; i < (int)(kRingBytes / 16); i += FTHREADS) reinterpret_cast<uint4 *>(fused_lds)[i] = uint4{0, 0, 0, 0};
+
+    // matrix-core role: wave w computes layer ML = 2 + w / 2, frame columns 32 (w % 2) ..
+    const int ML = 2 + (wave >> 1), mh = wave & 1;
+    const int j = lane & 31, kh = lane >> 5;
+    bf16x8 Wf[K / 16];
+    {
+        const bf16 *wm = wbf + off.W[ML - 1];
+#pragma unroll
+        for (int ks = 0; ks < K / 16; ++ks) Wf[ks] = *reinterpret_cast<const bf16x8 *>(wm + j * K + ks * 16 + kh * 8);
+    }
+    f32x16 mb;  // biases of the output channels this lane holds: the accumulator's start
+#pragma unroll
+    for (int v = 0; v < 16; ++v) mb[v] = params[off.b[ML - 1] + 8 * (v >> 2) + 4 * kh + (v & 3)];
+    // layers 1 and 6: wave w takes channels 4w .. 4w + 3, so their weights are
+    // uniform across the wave
+    const int q = __builtin_amdgcn_readfirstlane(wave);
+    float w1r[4][9], b1r[4];
+    bf16x2 w6p[9][2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        b1r[k] = params[off.b[0] + 4 * q + k];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) w1r[k][t] = (float)wbf[off.W[0] + (4 * q + k) * 9 + t];
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) w6p[t][h] = *reinterpret_cast<const bf16x2 *>(wbf + off.W[NL - 1] + t * C + 4 * q + 2 * h);
+    const float b6 = params[off.b[NL - 1]];
+
+    // ubar / s enters a ring of URS rows (row ys - 1 + rho in slot rho % URS)
+    // in batches of UBATCH rows, loaded a whole batch ahead: the loads of a
+    // batch are waited for once, not once per step
+    const int nu = rows + 12;  // rows rho = 0 .. rows + 11 feed layer 1
+    auto urow = [&](int rho) { return (int64_t)((((ys - 1 + rho) % H) + H) % H) * W; };
+    constexpr int UPT = (UBATCH * URC + FTHREADS - 1) / FTHREADS;  // loads per thread per batch
+    T ubuf[UPT];
+    auto ubatch_load = [&](int rho0) {  // rows rho0 .. rho0 + UBATCH - 1
+#pragma unroll
+        for (int k = 0; k < UPT; ++k) {
+            const int e = tid + FTHREADS * k, rho = rho0 + e / URC, col = e % URC;
+            ubuf[k] = (e < UBATCH * URC && rho < nu) ? ubs[urow(rho) + ((x0 - 6 + col) % W + W) % W] : T(0);
+        }
+    };
+    auto ubatch_store = [&](int rho0) {
+#pragma unroll
+        for (int k = 0; k < UPT; ++k) {
+            const int e = tid + FTHREADS * k, rho = rho0 + e / URC, col = e % URC;
+            if (e < UBATCH * URC && rho < nu) uring[(rho % URS) * URC + col] = (float)ubuf[k] * inv;
+        }
+    };
+    ubatch_load(0);
+    ubatch_store(0);
+    ubatch_load(UBATCH);
+    ubatch_store(UBATCH);
+    __syncthreads();
+
+    const int nstep = rows + 15;  // layer 6 computes rows y0 .. y0 + rows - 1 at steps 15 .. rows + 14
+    const int l6c = min(lane, FV - 1);  // layer 6: output frame column 5 + l6c
+    // z of layer 6's row at step st2: the 8 waves' partial sums, in wave order
+    auto zsum_out = [&](int st2) {
+        if (st2 >= 15 && tid < FV) {
+            const float *zp = zpart + (st2 & 1) * 8 * 64;
+            float zsum = b6;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) zsum += zp[w * 64 + tid];
+            const int x = x0 + tid;
+            if (x < W) z[(int64_t)b * HW + (int64_t)(ys + st2 - 10) * W + x] = zsum;
+        }
+    };
+    for (int st = 0; st < nstep; ++st) {
+        // ubar rows 2 UBATCH + st .. are loaded at the start of the step and
+        // stored at its end (layer 1 reads rows st .. st + 2 of the ring)
+        const bool ub_now = st % UBATCH == 0 && 2 * UBATCH + st < nu;
+        if (ub_now) ubatch_load(2 * UBATCH + st);
+        const int yM = ys + st - 2 * (ML - 1);
+        const bool mact = st >= 3 * ML - 3 && st < 3 * ML - 3 + rows + 2 * (NL - ML);
+        // ---- operand loads: layer ML's 18 fragments, layer 1's 9 ubar values,
+        // layer 6's 9 channel quads.  Slots are row & (RSL - 1), also for the
+        // (negative) rows of a layer before its first step; per input row one
+        // base address, the taps' column offsets are immediates.
+        const int rM = yM - 1 - ys;  // relative index of layer ML's first input row
+        bf16x8 Af[K / 16];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const bf16 *rb = at(ML, (rM + dy) & (RSL - 1), 32 * mh + j) + kh * 8;
+#pragma unroll
+            for (int k = 0; k < 6; ++k)  // taps (dy, dx = k / 2), channel halves k % 2
+                Af[6 * dy + k] = *reinterpret_cast<const bf16x8 *>(rb + (k >> 1) * PSTR + (k & 1) * 16);
+        }
+        float xv[9];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {  // ubar row ys + st + dy - 1 is rho = st + dy; frame column lane + dx - 1
+            const float *ur = uring + ((st + dy) & (URS - 1)) * URC + lane;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) xv[3 * dy + dx] = ur[dx];
+        }
+        bf16x2 a6[9][2];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {  // layer 6 reads rows ys + st - 11 .. ys + st - 9
+            const bf16 *rb = at(NL, (st - 11 + dy) & (RSL - 1), 5 + l6c) + 4 * q;  // frame column 5 + l6c + dx - 1
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                a6[3 * dy + dx][0] = *reinterpret_cast<const bf16x2 *>(rb + dx * PSTR);
+                a6[3 * dy + dx][1] = *reinterpret_cast<const bf16x2 *>(rb + dx * PSTR + 2);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);  // every load above is issued before the first product
+        // ---- products
+        f32x16 acc = mb;
+#pragma unroll
+        for (int ks = 0; ks < K / 16; ++ks) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wf[ks], Af[ks], acc, 0, 0, 0);
+        alignas(8) bf16 v1[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float a = b1r[k];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) a += w1r[k][t] * xv[t];
+            v1[k] = (bf16)relu_bits(a);
+        }
+        float zp = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) zp = __builtin_amdgcn_fdot2_f32_bf16(a6[t][h], w6p[t][h], zp, false);
+        // interleave: one matrix product, then a share of the vector work
+#pragma unroll
+        for (int i = 0; i < K / 16; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // VALU
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // ---- writes: rows for the next steps' readers, into this step's free
+        // slots (a layer outside its rows writes to the spare slot: no branch)
+        {
+            bf16 *dst = at(ML + 1, mact ? (yM - ys) & (RSL - 1) : RTR, 32 * mh + j + 1);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                alignas(8) bf16 v4[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v4[k] = (bf16)relu_bits(acc[4 * g + k]);
+                *reinterpret_cast<uint2 *>(dst + 8 * g + 4 * kh) = *reinterpret_cast<const uint2 *>(v4);
+            }
+        }
+        *reinterpret_cast<uint2 *>(at(2, st < rows + 10 ? st & (RSL - 1) : RTR, lane + 1) + 4 * q) =
+            *reinterpret_cast<const uint2 *>(v1);  // layer 1: frame column lane
+        zpart[(st & 1) * 8 * 64 + q * 64 + lane] = zp;
+        zsum_out(st - 1);  // the previous step's partial sums are complete (barrier below it)
+        if (ub_now) ubatch_store(2 * UBATCH + st);
+        lds_barrier();
+    }
+    zsum_out(nstep - 1);
+}
+
 // the last step of a 3D layer: out = relu(accb + bias) (forward) or
 // accb * (mask > 0) (input gradient), in bf16
 __global__ void k_finish(const float *accb, const float *bias, const bf16 *mask, bf16 *out, int64_t n) {
@@ -595,7 +812,7 @@ int fail(int code, const char *fmt, ...) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t wbf, wT, wf, s, rms, act, accb, z, y, dy, dyz, dz, lpart, wpart, grad, total;
+    size_t wbf, wT, wf, s, rms, act, accb, z, zt, y, dy, dyz, dz, lpart, wpart, grad, total;
     int64_t N, nblk_pix;
     int nblk_w;
 };
@@ -607,7 +824,11 @@ int64_t wgrad_tiles(const gd_grid *g) {
     return planes_of(g) * ((g->n[1] + WGY - 1) / WGY) * ((g->n[0] + WGX - 1) / WGX);
 }
 
-Layout layout(const gd_grid *g, bool training, bool own_grad) {
+// applications of G to the network's output (the struct's 0 means 1)
+int smooth_of(const gd_cnn *net) { return net->smooth > 0 ? net->smooth : 1; }
+constexpr int kMaxSmooth = 8;
+
+Layout layout(const gd_grid *g, bool training, bool own_grad, int smooth) {
     const int NT = taps_of(g->ndim), ndz = NT / 9;
     const Offsets off = offsets(NT);
     Layout L;
@@ -634,6 +855,8 @@ Layout layout(const gd_grid *g, bool training, bool own_grad) {
     if (ndz > 1) o = align_up(o + (size_t)L.N * C * 4, 256);
     L.z = o;
     o = align_up(o + (size_t)L.N * 4, 256);
+    L.zt = o;  // the second buffer of G^m z (m > 1)
+    if (smooth > 1) o = align_up(o + (size_t)L.N * 4, 256);
     if (training) {
         L.y = o;
         o = align_up(o + (size_t)L.N * 4, 256);
@@ -662,6 +885,8 @@ int check_net(const gd_cnn *net, bool training) {
     if (net->channels != C || net->layers != NL)
         return fail(GD_EINVAL, "the network has %d layers of %d channels", NL, C);
     if (!net->params) return fail(GD_EINVAL, "params is NULL");
+    if (net->smooth < 0 || net->smooth > kMaxSmooth)
+        return fail(GD_EINVAL, "smooth must be 0 .. %d (got %d)", kMaxSmooth, net->smooth);
     if (training && (!net->adam_m || !net->adam_v || !net->step))
         return fail(GD_EINVAL, "training needs adam_m, adam_v and step");
     return GD_OK;
@@ -717,6 +942,25 @@ int mid_layer(bool bwd, const gd_grid *g, const Layout &L, char *w, const bf16 *
     return GD_OK;
 }
 
+// y = G^m z: m - 1 filter passes ping-ponging between z and zt, then the last
+// one fused with u0 = ubar + s y (inference) or writing y (training)
+template <typename T>
+int finish_forward(const gd_cnn *net, const Layout &L, char *w, const T *ub, T *u0, bool train, int H, int W, int nz,
+                   hipStream_t st) {
+    const int64_t N = L.N;
+    const unsigned pblk = (unsigned)L.nblk_pix;
+    const double *s = (const double *)(w + L.s);
+    const float *zin = (const float *)(w + L.z);
+    for (int k = 1; k < smooth_of(net); ++k) {
+        float *zo = (k & 1) ? (float *)(w + L.zt) : (float *)(w + L.z);
+        GD_LAUNCH(k_gfilt, dim3(pblk), dim3(256), 0, st, zin, zo, H, W, nz, N);
+        zin = zo;
+    }
+    GD_LAUNCH(k_gfin<T>, dim3(pblk), dim3(256), 0, st, zin, ub, s, train ? (float *)(w + L.y) : (float *)nullptr,
+              train ? (T *)nullptr : u0, H, W, nz, N);
+    return GD_OK;
+}
+
 // forward (train = false: u0 out; train = true: keep every activation and y)
 template <typename T>
 int run_forward(const gd_cnn *net, const gd_grid *g, const Layout &L, char *w, const T *ub, T *u0, bool train,
@@ -738,6 +982,12 @@ int run_forward(const gd_cnn *net, const gd_grid *g, const Layout &L, char *w, c
     GD_LAUNCH(k_rms_part<T>, dim3(RMS_CHUNKS, (unsigned)g->batch), dim3(256), 0, st, ub, P, (double *)(w + L.rms));
     GD_LAUNCH(k_rms_fin, dim3((unsigned)((g->batch + 63) / 64)), dim3(64), 0, st, (const double *)(w + L.rms),
               (int)g->batch, P, s);
+    if (NT == 9 && !train) {  // 2D inference: the six layers in one kernel
+        const dim3 grid((unsigned)((W + FV - 1) / FV), (unsigned)((H + FY - 1) / FY), (unsigned)g->batch);
+        GD_LAUNCH(k_fwd2d_fused<T>, grid, dim3(FTHREADS), kFusedLds, st, ub, (const double *)s, (const bf16 *)wbf,
+                  (const float *)net->params, off, (float *)(w + L.z), H, W);
+        return finish_forward<T>(net, L, w, ub, u0, false, H, W, nz, st);
+    }
     if (NT == 9)
         GD_LAUNCH((k_conv_in<T, 9>), dim3(pblk), dim3(256), 0, st, ub, (const double *)s, (const bf16 *)(wbf + off.W[0]),
                   (const float *)(net->params + off.b[0]), act(0), H, W, nz, N);
@@ -759,9 +1009,7 @@ int run_forward(const gd_cnn *net, const gd_grid *g, const Layout &L, char *w, c
     else
         GD_LAUNCH(k_conv_out<27>, dim3(pblk), dim3(256), 0, st, (const bf16 *)last, (const bf16 *)(wbf + off.W[NL - 1]),
                   (const float *)(net->params + off.b[NL - 1]), (float *)(w + L.z), H, W, nz, N);
-    GD_LAUNCH(k_gfin<T>, dim3(pblk), dim3(256), 0, st, (const float *)(w + L.z), ub, (const double *)s,
-              train ? (float *)(w + L.y) : (float *)nullptr, train ? (T *)nullptr : u0, H, W, nz, N);
-    return GD_OK;
+    return finish_forward<T>(net, L, w, ub, u0, train, H, W, nz, st);
 }
 
 // Weight gradient of layer (CI -> CO) into grad_layer (its first weight): one
@@ -814,9 +1062,18 @@ int run_train(const gd_cnn *net, const gd_grid *g, const Layout &L, char *w, con
     GD_LAUNCH(k_loss<T>, dim3(pblk), dim3(256), 0, st, (const float *)(w + L.y), ub, u, s, dy,
               (double *)(w + L.lpart), P, N);
     GD_LAUNCH(k_loss_fin, dim3(1), dim3(256), 0, st, (const double *)(w + L.lpart), L.nblk_pix, N, loss);
-    // through the final filter: dL/dz = G dL/dy
+    // through the final filters: dL/dz = G^m dL/dy (G is symmetric), m passes
+    // ping-ponging between dyz and dy
     float *dyz = (float *)(w + L.dyz);
-    GD_LAUNCH(k_gfilt, dim3(pblk), dim3(256), 0, st, (const float *)dy, dyz, H, W, nz, N);
+    {
+        const float *gin = dy;
+        for (int k = 0; k < smooth_of(net); ++k) {
+            float *go = (k & 1) ? dy : (float *)(w + L.dyz);
+            GD_LAUNCH(k_gfilt, dim3(pblk), dim3(256), 0, st, gin, go, H, W, nz, N);
+            gin = go;
+        }
+        dyz = const_cast<float *>(gin);
+    }
     // layer 6
     if ((rc = wgrad_layer<C, 1, T>(g, L, w, act(NL - 2), ub, s, nullptr, dyz, grad + off.W[NL - 1], st))) return rc;
     if (NT == 9)
@@ -855,7 +1112,7 @@ int64_t warmstart_param_count(const gd_cnn *net) {
 
 size_t warmstart_workspace_bytes(const gd_cnn *net, const gd_grid *g, int32_t training) {
     if (check_net(net, false) || check_grid(net, g)) return 0;
-    return layout(g, training != 0, !net->grad).total;
+    return layout(g, training != 0, !net->grad, smooth_of(net)).total;
 }
 
 int warmstart_forward(const gd_cnn *net, const gd_grid *g, const void *ubar, void *u0, void *work, size_t work_bytes,
@@ -867,7 +1124,7 @@ int warmstart_forward(const gd_cnn *net, const gd_grid *g, const void *ubar, voi
     if (ubar == u0) return fail(GD_EINVAL, "ubar and u0 must differ");
     if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
     if ((uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be 256-byte aligned");
-    const Layout L = layout(g, false, false);
+    const Layout L = layout(g, false, false, smooth_of(net));
     if (work_bytes < L.total) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes", L.total);
     hipStream_t st = (hipStream_t)stream;
     if (g->dtype == GD_F32)
@@ -883,7 +1140,7 @@ int warmstart_train_step(const gd_cnn *net, const gd_grid *g, const void *ubar, 
     if (!ubar || !u || !loss) return fail(GD_EINVAL, "ubar, u and loss must be non-NULL");
     if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
     if ((uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be 256-byte aligned");
-    const Layout L = layout(g, true, !net->grad);
+    const Layout L = layout(g, true, !net->grad, smooth_of(net));
     if (work_bytes < L.total) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes", L.total);
     hipStream_t st = (hipStream_t)stream;
     if (g->dtype == GD_F32)

@@ -582,13 +582,152 @@ __global__ __launch_bounds__(256) void k_spectrum_reduce(const double *part, dou
     }
 }
 
+// blocks of 256 threads for a grid-stride loop over n items
+unsigned stride_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+// ---- band projection of a start ---------------------------------------------
+
+// Energy of each field from its unnormalized half spectrum: part[b][c] = sum
+// over chunk c of field b's stored modes of w(kx) |X|^2 (w = 1 on the kx = 0
+// and kx = nx / 2 columns, 2 elsewhere, 0 on the padding), each workgroup a
+// fixed tree over its threads, so the result does not depend on timing.
+template <typename T, bool SCALED = false>
+__global__ __launch_bounds__(256) void k_band_power(const T *X, double *part, int64_t per_field, int64_t nchunks,
+                                                    Spec s) {
+    using V = typename V2<T>::t;
+    __shared__ double red[256];
+    const int64_t b = blockIdx.y, ch = blockIdx.x;
+    const int64_t len = (per_field + nchunks - 1) / nchunks;
+    const int64_t i0 = ch * len, i1 = std::min(per_field, i0 + len);
+    const V *F = reinterpret_cast<const V *>(X) + b * per_field;
+    double acc = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const int64_t kx = i % s.nxh;
+        if (kx < s.nxc) {
+            const V z = F[i];
+            // a Parseval-scaled spectrum (SCALED) already carries w in its values
+            const double w = SCALED ? 1.0 : ((kx == 0 || 2 * kx == s.nx) ? 1.0 : 2.0);
+            acc += w * ((double)z.x * (double)z.x + (double)z.y * (double)z.y);
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[b * nchunks + ch] = red[0];
+}
+
+// X0 <- (X0 - XB) / N on the modes where |XB|^2 > tau E_b, 0 elsewhere, with
+// E_b = (1/N) sum_k w |XB|^2 the mean of |XB(k)|^2 over all N wavenumbers of
+// field b (= sum_x ubar^2, Parseval).  The 1/N makes the unnormalized
+// inverse transform the inverse.
+template <typename T>
+__global__ __launch_bounds__(256) void k_band_mask(T *X0, const T *XB, const double *part, int64_t per_field,
+                                                   int64_t nchunks, Spec s, double tau) {
+    using V = typename V2<T>::t;
+    __shared__ double thr;
+    const int64_t b = blockIdx.y;
+    const double n = (double)(s.nx * s.ny * s.nz);
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int64_t c = 0; c < nchunks; ++c) e += part[b * nchunks + c];
+        thr = tau * (e / n);
+    }
+    __syncthreads();
+    const double t = thr, inv_n = 1.0 / n;
+    V *F0 = reinterpret_cast<V *>(X0) + b * per_field;
+    const V *FB = reinterpret_cast<const V *>(XB) + b * per_field;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < per_field; i += (int64_t)gridDim.x * 256) {
+        const int64_t kx = i % s.nxh;
+        const V zb = FB[i], z0 = F0[i];
+        const double p = (double)zb.x * (double)zb.x + (double)zb.y * (double)zb.y;
+        V r;
+        r.x = r.y = T(0);
+        if (kx < s.nxc && p > t) {
+            r.x = (T)(((double)z0.x - (double)zb.x) * inv_n);
+            r.y = (T)(((double)z0.y - (double)zb.y) * inv_n);
+        }
+        F0[i] = r;
+    }
+}
+
+// The same projection on the Parseval-scaled spectra the differential-filter
+// solve holds (S = sqrt(w(kx) / N) X, and part from k_band_power<T, true>
+// sums to sum_x ubar^2 = E): U <- U where |X_B|^2 = |S_B|^2 N / w > tau E,
+// U <- S_B elsewhere (the start keeps ubar's coefficients there, so
+// start - ubar has no content outside ubar's support).
+template <typename T>
+__global__ __launch_bounds__(256) void k_band_keep(T *U, const T *UB, const double *part, int64_t per_field,
+                                                   int64_t nchunks, Spec s, double tau) {
+    using V = typename V2<T>::t;
+    __shared__ double e_sh;
+    const int64_t b = blockIdx.y;
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int64_t c = 0; c < nchunks; ++c) e += part[b * nchunks + c];
+        e_sh = e;
+    }
+    __syncthreads();
+    const double te = tau * e_sh / (double)(s.nx * s.ny * s.nz);
+    V *F = reinterpret_cast<V *>(U) + b * per_field;
+    const V *FB = reinterpret_cast<const V *>(UB) + b * per_field;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < per_field; i += (int64_t)gridDim.x * 256) {
+        const int64_t kx = i % s.nxh;
+        if (kx >= s.nxc) continue;  // padding stays zero
+        const V zb = FB[i];
+        const double w = (kx == 0 || 2 * kx == s.nx) ? 1.0 : 2.0;
+        const double p = (double)zb.x * (double)zb.x + (double)zb.y * (double)zb.y;
+        if (!(p > te * w)) F[i] = zb;
+    }
+}
+
+// u0 += ubar
+template <typename T>
+__global__ __launch_bounds__(256) void k_band_add(T *u0, const T *ubar, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) u0[i] += ubar[i];
+}
+
+// threshold of the band projection a warm start of the differential-filter
+// solve gets (relative to the mean mode power of ubar)
+constexpr double kWarmBandTau = 1e-10;
+
+// chunks per field of the band power sums: about 4096 stored modes each, at most 256
+int64_t band_chunks(const Spec &s) {
+    const int64_t per_field = s.nz * s.ny * s.nxh;
+    return std::max<int64_t>(1, std::min<int64_t>(256, per_field / 4096));
+}
+
+template <typename T>
+int band_project_run(const Spec &s, double tau, const T *ubar, T *u0, char *w, hipStream_t st) {
+    const size_t sb = align_up_256((size_t)s.elems * s.tsize);
+    T *XB = (T *)w, *X0 = (T *)(w + sb);
+    double *part = (double *)(w + 2 * sb);
+    int rc;
+    if ((rc = forward<T>(s, ubar, XB, MUL_NONE, 0.0, st))) return rc;
+    if ((rc = forward<T>(s, u0, X0, MUL_NONE, 0.0, st))) return rc;
+    const int64_t per_field = s.nz * s.ny * s.nxh, nch = band_chunks(s);
+    if (s.batch > 65535) return fail(GD_EINVAL, "batch too large for the band projection (at most 65535 fields)");
+    hipLaunchKernelGGL(k_band_power<T>, dim3((unsigned)nch, (unsigned)s.batch), dim3(256), 0, st, XB, part, per_field,
+                       nch, s);
+    const unsigned mb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((per_field + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_band_mask<T>, dim3(mb, (unsigned)s.batch), dim3(256), 0, st, X0, XB, part, per_field, nch, s,
+                       tau);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(GD_EHIP, "band projection launch: %s", hipGetErrorString(e));
+    if ((rc = inverse<T>(s, X0, u0, MUL_NONE, 0.0, st))) return rc;
+    const int64_t npts = s.batch * s.nx * s.ny * s.nz;
+    hipLaunchKernelGGL(k_band_add<T>, dim3(stride_blocks(npts)), dim3(256), 0, st, u0, ubar, npts);
+    e = hipGetLastError();
+    return e == hipSuccess ? GD_OK : fail(GD_EHIP, "band projection launch: %s", hipGetErrorString(e));
+}
+
 __global__ void k_zero_i64(int64_t *p, int64_t n) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
         p[t] = 0;
 }
 
-// blocks of 256 threads for a grid-stride loop over n items
-unsigned stride_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
 
 // PDF bin counts: LDS counters per workgroup (one field's chunk), then one
 // global integer atomic per nonzero bin.
@@ -689,6 +828,25 @@ int deconvolve_germano(int32_t solver, const gd_grid *g, double gamma, const voi
                  : forward<double>(s, (const double *)u, (double *)U, MUL_C, ik, st);
         if (rc) return rc;
     }
+    if (o->init == GD_INIT_WARM) {  // band projection of the start (the partial sums use the solve's workspace)
+        const int64_t per_field = s.nz * s.ny * s.nxh, nch = band_chunks(s);
+        if (s.batch > 65535) return fail(GD_EINVAL, "batch too large for the band projection (at most 65535 fields)");
+        double *part = (double *)(w + 2 * sb);
+        const unsigned mb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((per_field + 255) / 256, 1024));
+        if (f32) {
+            hipLaunchKernelGGL((k_band_power<float, true>), dim3((unsigned)nch, (unsigned)s.batch), dim3(256), 0, st,
+                               (const float *)UB, part, per_field, nch, s);
+            hipLaunchKernelGGL(k_band_keep<float>, dim3(mb, (unsigned)s.batch), dim3(256), 0, st, (float *)U,
+                               (const float *)UB, (const double *)part, per_field, nch, s, kWarmBandTau);
+        } else {
+            hipLaunchKernelGGL((k_band_power<double, true>), dim3((unsigned)nch, (unsigned)s.batch), dim3(256), 0, st,
+                               (const double *)UB, part, per_field, nch, s);
+            hipLaunchKernelGGL(k_band_keep<double>, dim3(mb, (unsigned)s.batch), dim3(256), 0, st, (double *)U,
+                               (const double *)UB, (const double *)part, per_field, nch, s, kWarmBandTau);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(GD_EHIP, "band projection launch: %s", hipGetErrorString(e));
+    }
     const gd_grid v = spectral_grid(g, s);
     const gd::SpecParams sp = spec_params(g, s, ik);
     rc = gd::solve_uniform(solver, &v, UB, U, o, solve_work, wb - 2 * sb, info, stream, nullptr, &sp);
@@ -777,6 +935,32 @@ int energy_spectrum(const gd_grid *g, double kpow, const void *x, double *out, v
                        nch, ns, s.batch);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? GD_OK : fail(GD_EHIP, "spectrum launch: %s", hipGetErrorString(e));
+}
+
+size_t band_project_workspace_bytes(const gd_grid *g) {
+    if (validate_spec_grid(g)) return 0;
+    const Spec s = spec_of(g);
+    return 2 * align_up_256((size_t)s.elems * s.tsize) + align_up_256((size_t)s.batch * band_chunks(s) * sizeof(double));
+}
+
+int band_project(const gd_grid *g, double tau, const void *ubar, void *u0, void *work, size_t wb, void *stream) {
+    int rc = validate_spec_grid(g);
+    if (rc) return rc;
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(GD_EINVAL, "tau must be finite and >= 0");
+    if (!ubar || !u0) return fail(GD_EINVAL, "ubar and u0 must be non-NULL");
+    if (!work) return fail(GD_EWORKSPACE, "workspace is NULL");
+    if ((uintptr_t)work % 256) return fail(GD_EALIGN, "workspace must be 256-byte aligned");
+    const size_t need = band_project_workspace_bytes(g);
+    if (wb < need) return fail(GD_EWORKSPACE, "workspace too small: need %zu bytes, got %zu", need, wb);
+    const Spec s = spec_of(g);
+    const size_t fb = (size_t)s.batch * s.nx * s.ny * s.nz * s.tsize;
+    if (gd::ranges_overlap(ubar, fb, u0, fb)) return fail(GD_EINVAL, "ubar and u0 overlap");
+    if (gd::ranges_overlap(ubar, fb, work, need) || gd::ranges_overlap(u0, fb, work, need))
+        return fail(GD_EINVAL, "a field overlaps the workspace");
+    hipStream_t st = (hipStream_t)stream;
+    if (g->dtype == GD_F32)
+        return band_project_run<float>(s, tau, (const float *)ubar, (float *)u0, (char *)work, st);
+    return band_project_run<double>(s, tau, (const double *)ubar, (double *)u0, (char *)work, st);
 }
 
 int pdf_counts(const gd_grid *g, double lo, double hi, int32_t nbins, const void *x, int64_t *counts, void *stream) {

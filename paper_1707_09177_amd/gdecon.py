@@ -69,7 +69,7 @@ class TuneInfo(ctypes.Structure):
 
 class Cnn(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("channels", ctypes.c_int32), ("layers", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("smooth", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("params", ctypes.c_void_p),
                 ("grad", ctypes.c_void_p), ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
                 ("step", ctypes.c_void_p)]
@@ -156,6 +156,10 @@ def load(path: str = LIB_PATH):
     lib.energy_spectrum.restype = ctypes.c_int
     lib.pdf_counts.argtypes = [gp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp, vp]
     lib.pdf_counts.restype = ctypes.c_int
+    lib.band_project_workspace_bytes.argtypes = [gp]
+    lib.band_project_workspace_bytes.restype = ctypes.c_size_t
+    lib.band_project.argtypes = [gp, ctypes.c_double, vp, vp, vp, ctypes.c_size_t, vp]
+    lib.band_project.restype = ctypes.c_int
     lib.closure_stress.argtypes = [gp, vp, vp, vp, vp]
     lib.closure_stress.restype = ctypes.c_int
     cp = ctypes.POINTER(Cnn)
@@ -368,6 +372,28 @@ def energy_spectrum(x: torch.Tensor, ndim: int = 2, kpow: float = 0.0, stream=No
     _check(lib.energy_spectrum(ctypes.byref(g), float(kpow), _dev_ptr(x), _dev_ptr(out), work.data_ptr(),
                                work.numel(), _stream_handle(stream)))
     return out
+
+
+BAND_TAU = 1e-10   # default threshold of band_project, relative to the mean mode power of ubar
+
+
+def band_project(ubar: torch.Tensor, u0: torch.Tensor, ndim: int = 2, tau: float = BAND_TAU,
+                 work: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """u0 <- ubar + P (u0 - ubar) in place (band_project): P keeps the Fourier
+    modes of each field where |ubar_hat|^2 > tau * mean |ubar_hat|^2.
+    Power-of-two sizes.  Returns u0."""
+    lib = load()
+    if u0.shape != ubar.shape or u0.dtype != ubar.dtype:
+        raise ValueError("ubar and u0 must match")
+    g = make_grid(ubar.shape, ndim, ubar.dtype)
+    n = int(lib.band_project_workspace_bytes(ctypes.byref(g)))
+    if n == 0:
+        raise GdError(-1, "bad grid (the band projection needs power-of-two sizes)")
+    if work is None or work.numel() < n:
+        work = torch.empty(n, dtype=torch.uint8, device=ubar.device)
+    _check(lib.band_project(ctypes.byref(g), float(tau), _dev_ptr(ubar), _dev_ptr(u0), work.data_ptr(), work.numel(),
+                            _stream_handle(stream)))
+    return u0
 
 
 def pdf_counts(x: torch.Tensor, lo: float, hi: float, nbins: int, ndim: int = 2, stream=None) -> torch.Tensor:
@@ -617,7 +643,10 @@ def deconvolve_batch(solver: str, ubars, max_iter: int, tol: float = 0.0, init: 
 class WarmStart:
     """The learned warm start (warmstart_forward / warmstart_train_step): a
     periodic CNN (3x3 taps for ndim=2, 3x3x3 for ndim=3) whose output
-    u0 = ubar + s * G f(ubar / s) starts a solve with init='given'.  Owns its
+    u0 = ubar + s * G^smooth f(ubar / s) starts a solve with init='warm' (the
+    library falls back to ubar where u0 is no better).  With ``band`` (a
+    band_project threshold, default BAND_TAU; None to skip) forward() keeps
+    the correction inside ubar's Fourier support (power-of-two sizes).  Owns its
     FP32 parameters, Adam moments and step counter on the device.  ``params``:
     initial flat FP32/FP64 vector (for example synth.cnn_init_params(seed,
     ndim=ndim)).  Fields: (ny, nx) / (batch, ny, nx) in 2D, (nz, ny, nx) /
@@ -626,12 +655,14 @@ class WarmStart:
     CHANNELS, LAYERS = 32, 6
 
     def __init__(self, params, device=None, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
-                 eps: float = 1e-8, ndim: int = 2):
+                 eps: float = 1e-8, ndim: int = 2, smooth: int = 1, band: float | None = BAND_TAU):
         self.lib = load()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.ndim = ndim
+        self.band = band
         self.net = Cnn()
         self.net.ndim, self.net.channels, self.net.layers = ndim, self.CHANNELS, self.LAYERS
+        self.net.smooth = int(smooth)
         self.net.lr, self.net.beta1, self.net.beta2, self.net.eps = lr, beta1, beta2, eps
         n = int(self.lib.warmstart_param_count(ctypes.byref(self.net)))
         p = torch.as_tensor(np.asarray(params), dtype=torch.float32).reshape(-1)
@@ -667,13 +698,24 @@ class WarmStart:
             self._work[key] = w
         return w
 
-    def forward(self, ubar: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """u0 for every field of ubar (launch only, no synchronisation)."""
+    def forward(self, ubar: torch.Tensor, out: torch.Tensor | None = None, stream=None,
+                band: bool = True) -> torch.Tensor:
+        """u0 for every field of ubar (launch only, no synchronisation); the
+        band projection follows when self.band is set and ``band``."""
         g = self._grid(ubar)
         u0 = _out(out, ubar.shape, ubar)
         w = self._workspace(g, False)
         _check(self.lib.warmstart_forward(ctypes.byref(self.net), ctypes.byref(g), _dev_ptr(ubar), _dev_ptr(u0),
                                           w.data_ptr(), w.numel(), _stream_handle(stream)))
+        if band and self.band is not None:
+            key = ("band",) + tuple(ubar.shape) + (str(ubar.dtype),)
+            bw = self._work.get(key)
+            if bw is None:
+                n = int(self.lib.band_project_workspace_bytes(ctypes.byref(g)))
+                if n == 0:
+                    raise GdError(-1, "the band projection needs power-of-two sizes (pass band=None)")
+                bw = self._work[key] = torch.empty(n, dtype=torch.uint8, device=self.device)
+            band_project(ubar, u0, self.ndim, self.band, work=bw, stream=stream)
         return u0
 
     def train_step(self, ubar: torch.Tensor, u: torch.Tensor, stream=None) -> torch.Tensor:

@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "rng_for", "field_2d", "velocity_3d", "scalar_3d",
     "spectrum_kraichnan", "spectrum_kolmogorov", "spectrum_c1",
-    "config_fields", "batch_instances",
+    "config_fields", "batch_instances", "training_fields",
 ]
 
 
@@ -243,6 +243,25 @@ def training_pairs(count: int, n: int = 512, crop: int = 128, seed0: int = 0, dt
             for cx in range(n // crop):
                 if len(out) < count:
                     out.append(f[cy * crop:(cy + 1) * crop, cx * crop:(cx + 1) * crop].astype(dtype))
+    return out
+
+
+def training_fields(count: int = 4096, n: int = 512, seed0: int = 0, dtype=np.float32, workers: int = 0):
+    """The warm-start network's training set: `count` whole periodic 2D
+    fields (n, n) with a k^-3 spectrum on 4 <= k <= n/4, returned stacked
+    (count, n, n); the filtered inputs are made by the caller (ubar = G u).
+    Field i is seeded by (5, 100000 + seed0 + i) and does not depend on
+    `workers` (threads that draw fields in parallel; 0 = one per CPU, at
+    most 16)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import os
+    out = np.empty((count, n, n), dtype=dtype)
+
+    def one(i):
+        out[i] = field_2d(n, spectrum_kraichnan, 4.0, n / 4.0, rng_for(5, 100000 + seed0 + i), dtype)
+    nw = workers if workers > 0 else max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(nw) as ex:
+        list(ex.map(one, range(count)))
     return out
 
 

@@ -211,3 +211,38 @@ def test_3d_correction_in_range_of_g_and_scale_equivariant():
         sl[ax] = n // 2
         assert np.max(np.abs(F[tuple(sl)])) <= 1e-12 * np.max(np.abs(F))
     np.testing.assert_allclose(cnn.forward(p, 3.0 * ub, ndim=3)["u0"], 3.0 * f["u0"], rtol=1e-12, atol=1e-12)
+
+
+def test_smoothed_output_transfer_function():
+    """smooth = m: the correction is G^m z, whose Fourier coefficients are
+    those of z times the closed-form transfer function to the m-th power,
+    prod_d cos^(2m)(pi k_d / n_d); checked by FFT against a run with smooth=1
+    (whose correction is G z) on the same network."""
+    p = synth.cnn_init_params(11)
+    p[cnn.param_count() - 1] = 0.1
+    ub = rng(15).standard_normal((2, 10, 12))
+    c1 = cnn.forward(p, ub, smooth=1)["u0"] - ub
+    c3 = cnn.forward(p, ub, smooth=3)["u0"] - ub
+    ky = np.arange(10)[:, None]
+    kx = np.arange(12)[None, :]
+    gh = np.cos(np.pi * ky / 10) ** 2 * np.cos(np.pi * kx / 12) ** 2
+    np.testing.assert_allclose(np.fft.fft2(c3), np.fft.fft2(c1) * gh ** 2, atol=1e-12 * np.abs(np.fft.fft2(c1)).max())
+
+
+@pytest.mark.parametrize("ndim,shape", [(2, (5, 6)), (3, (3, 4, 5))])
+def test_backprop_with_smoothing_matches_central_differences(ndim, shape):
+    params = synth.cnn_init_params(4, channels=4, ndim=ndim)
+    params[-1] = 0.05
+    ub = rng(17).standard_normal((2,) + shape)
+    u = ub + 0.3 * rng(18).standard_normal((2,) + shape)
+    loss, g = cnn.loss_and_grad(params, ub, u, channels=4, ndim=ndim, smooth=3)
+    pick = rng(19).choice(params.size, size=40, replace=False)
+    eps = 1e-6
+    for i in pick:
+        p1, p2 = params.copy(), params.copy()
+        p1[i] += eps
+        p2[i] -= eps
+        l1, _ = cnn.loss_and_grad(p1, ub, u, channels=4, ndim=ndim, smooth=3)
+        l2, _ = cnn.loss_and_grad(p2, ub, u, channels=4, ndim=ndim, smooth=3)
+        fd = (l1 - l2) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1e-3, abs(g[i])) + 1e-9, (i, fd, g[i])
