@@ -73,6 +73,9 @@ WORKLOADS = {
                     "included) vs the ubar and zero starts and Van Cittert; trapezoidal filter (value) and the "
                     "paper's differential filter at gamma = 0.1",
                cfg=5, count=64, n=1024, key="warmstart64", warm=True),
+    "c5fwd": dict(desc="the warm-start network's 2D inference (k_fwd2d_fused: six layers, 37.4 k MAC per point, bf16 "
+                       "MFMA for the 32->32 layers) on the 64 held-out 1024^2 evaluation fields",
+                  cfg=5, count=64, n=1024, key="cnn_forward_1024sq_x64", forward=True),
     "c3": dict(desc="3D periodic 256^3 x 3 velocity components, E(k)~k^-5/3 on 2<=k<=80, divergence-free, "
                     "BiCGSTAB per component to rel. residual 1e-6 (FP32 storage, FP64 dots/scalars)",
                cfg=3, ndim=3, n=256, count=3, key="256cube_x3"),
@@ -730,6 +733,40 @@ def main_warm(args, w, torch, gd, dev):
     print(json.dumps(out))
 
 
+# model flops per point of the 2D network: 2 x (9 + 4 x 9 x 32 + 9) x 32 MACs
+CNN2D_FLOP_PER_POINT = 2 * (9 * 32 + 4 * 9 * 32 * 32 + 9 * 32)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def main_forward(args, w, torch, gd, dev):
+    """The network's 2D forward pass alone (untrained weights: the cost does
+    not depend on them), without the band projection, on the c5 evaluation
+    batch.  roofline: model flops per launch / the fused kernel's duration,
+    against the dense bf16 matrix-core peak."""
+    from paper_1707_09177_amd import synth
+    ev = torch.from_numpy(np.stack([synth.field_2d(w["n"], synth.spectrum_kraichnan, 4.0, w["n"] / 4.0,
+                                                   synth.rng_for(5, 50000 + i), np.float32)
+                                    for i in range(w["count"])])).to(dev)
+    ubar = gd.filter_apply(ev, ndim=2)
+    net = gd.WarmStart(synth.cnn_init_params(0))
+    u0 = torch.empty_like(ubar)
+    for _ in range(args.warmup):
+        net.forward(ubar, out=u0, band=False)
+    ms = event_ms(torch, lambda: net.forward(ubar, out=u0, band=False), args.steps)
+    npts = int(ubar.numel())
+    tflops = CNN2D_FLOP_PER_POINT * npts / (ms * 1e-3) / 1e12
+    print(json.dumps({"metric": "warm-start network forward points/s; % bf16 MFMA peak", "value": npts / (ms * 1e-3),
+                      "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+                      "data": "synthetic", "config": {"workload": w["desc"], "fields": w["count"],
+                                                      "grid": [w["n"], w["n"]], "points": npts},
+                      "roofline": {"bound": "mfma", "achieved": tflops, "peak": MFMA_BF16_PEAK_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": tflops / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
+                                   "flop_per_point": CNN2D_FLOP_PER_POINT,
+                                   "note": "whole forward call (RMS, fused layers, G, u0 = ubar + s y); the fused "
+                                           "kernel's own share is in profiles/"}}))
+
+
 def warm_3d(gd, torch, dev, synth, args, n_train=64, n_eval=128, count_eval=8):
     """3D network: trained on 64^3 k^-5/3 fields, evaluated on held-out
     128^3 fields (k^-5/3 on 2 <= k <= 40): BiCGSTAB passes and time from the
@@ -836,8 +873,9 @@ def main():
                          "choices are saved for later --no-tune runs, e.g. under a profiler)")
     ap.add_argument("--solvers", default="bicgstab,cg,vc,vcb",
                     help="vcb: Van Cittert with several passes per sweep (same iterates, less traffic)")
-    ap.add_argument("--train-steps", type=int, default=2048,
-                    help="warm-start workload: Adam steps (batches of 8 fields: 4 passes over 4096 fields)")
+    ap.add_argument("--train-steps", type=int, default=8192,
+                    help="warm-start workload: Adam steps (batches of 8 fields: 16 passes over 4096 fields, "
+                         "about 46 s per 2D network)")
     ap.add_argument("--train-fields", type=int, default=4096, help="warm-start workload: 512^2 training fields")
     ap.add_argument("--smooth", type=int, default=1,
                     help="warm-start workload: applications of G to the network's output (1 measured best: with the "
@@ -870,6 +908,8 @@ def main():
         return main_batch(args, w, torch, gd, dev)
     if w.get("warm"):
         return main_warm(args, w, torch, gd, dev)
+    if w.get("forward"):
+        return main_forward(args, w, torch, gd, dev)
     if w.get("closure"):
         return main_closure(args, w, torch, gd, dev)
     if w.get("table1"):

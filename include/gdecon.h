@@ -305,7 +305,9 @@ void gd_tune_reset(void);
  * the network's rounding noise is damped by G_hat^m where the fields have no
  * content).  Activations are bfloat16, the 32 -> 32 layers run on the matrix
  * cores with FP32 accumulation.  The grid's ndim must equal the network's;
- * batch = number of fields.
+ * batch = number of fields.  Before the solve, band_project (below) removes
+ * the correction's content where ubar has none; the differential-filter
+ * solve does that itself for a GD_INIT_WARM start.
  *
  * Parameters: one FP32 vector, layer by layer, each W[cout][tap][cin] with
  * tap = 3*(dy+1) + (dx+1) for the offset (dy, dx) in y and x (in 3D

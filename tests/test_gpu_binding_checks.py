@@ -64,11 +64,11 @@ def test_warm_start_keeps_one_workspace_per_3d_size():
     """Fields that differ only in n_z get workspaces of their own, and the
     results do not depend on what ran before."""
     p = synth.cnn_init_params(0, ndim=3)
-    ws = gdecon.WarmStart(p, ndim=3)
+    ws = gdecon.WarmStart(p, ndim=3, band=None)   # n_z = 12: no band projection (power-of-two sizes only)
     ubs = {nz: torch.randn(nz, 8, 16, device=DEV, generator=torch.Generator(DEV).manual_seed(nz)) for nz in (4, 12)}
     got = {nz: ws.forward(ubs[nz]).clone() for nz in (4, 12, 4)}
     torch.cuda.synchronize()
     assert len(ws._work) == 2
-    fresh = gdecon.WarmStart(p, ndim=3).forward(ubs[12])
+    fresh = gdecon.WarmStart(p, ndim=3, band=None).forward(ubs[12])
     torch.cuda.synchronize()
     assert torch.equal(got[12], fresh)

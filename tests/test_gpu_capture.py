@@ -97,8 +97,8 @@ def test_warm_start_capture():
     from paper_1707_09177_amd import synth
     p = synth.cnn_init_params(0)
     g0 = torch.Generator(DEV).manual_seed(11)
-    x = torch.randn(2, 64, 96, device=DEV, generator=g0)
-    u = torch.randn(2, 64, 96, device=DEV, generator=g0)
+    x = torch.randn(2, 64, 128, device=DEV, generator=g0)   # power-of-two sizes: the band projection is captured too
+    u = torch.randn(2, 64, 128, device=DEV, generator=g0)
     eager, cap = gdecon.WarmStart(p, lr=1e-3), gdecon.WarmStart(p, lr=1e-3)
     out_e, out_c = torch.empty_like(x), torch.empty_like(x)
     for ws, out in ((eager, out_e), (cap, out_c)):     # workspaces are allocated here, outside the capture

@@ -286,9 +286,10 @@ def test_a_bad_network_start_falls_back_to_the_plain_solve():
 
 
 def test_fused_forward_spans_strips_and_row_chunks():
-    """The 2D inference kernel cuts a field into strips of 56 columns and
+    """The 2D inference kernel cuts a field into strips of 54 columns and
     chunks of 256 rows: a field of 300 x 130 spans three strips (the last
-    ragged) and two chunks; it must match the reference like any other."""
+    ragged) and two chunks (the second ragged); it must match the reference
+    like any other."""
     p = params_with_bias(4)
     ub, _ = fields((300, 130), 1, 80)
     ws = gdecon.WarmStart(p, band=None)
