@@ -617,6 +617,7 @@ def train_warm_start(gd, torch, ub, u, ndim, steps, batch, smooth, lr=1e-3, seed
             net.set_lr(lr / 10)
         if k % max(1, steps // 8) == 0 or k == steps - 1:
             losses.append(float(loss.item()))
+            print(f"train {ndim}D: step {k + 1}/{steps} loss {losses[-1]:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     return net, {"steps": steps, "batch": batch, "fields": int(count), "grid": list(ub.shape[1:]), "smooth": smooth,
                  "seconds": time.perf_counter() - t0, "loss": losses}
