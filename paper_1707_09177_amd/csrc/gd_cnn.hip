@@ -16,9 +16,10 @@
 //
 // A 3D field is a stack of nz planes and a 3D convolution is the sum of three
 // 2D convolutions of the planes shifted by dz = -1, 0, +1, each with its own
-// 3x3 slice of the weights: the 2D matrix-core kernels run once per dz, with
-// the plane shift as an argument, accumulating into an FP32 buffer that a
-// final pass turns into bf16 (bias and ReLU, or the ReLU mask).
+// 3x3 slice of the weights: the 3D matrix-core kernel stages the three
+// planes' tiles in LDS and runs the three 2D products one weight slice at a
+// time into the same registers, then writes bf16 (bias and ReLU, or the ReLU
+// mask) once.
 //
 // Data layout: activations are bfloat16, channels fastest (NHWC, 64 bytes per
 // point).  The four 32 -> 32 layers run as implicit GEMMs on the matrix cores
@@ -179,24 +180,22 @@ __global__ void k_conv_in(const T *ub, const double *s, const bf16 *w1, const fl
     for (int q = 0; q < 4; ++q) dst[q] = reinterpret_cast<const uint4 *>(o)[q];
 }
 
-// 32 -> 32 layer (one 3x3 slice) on the matrix cores; the input is the plane
-// shifted by dzo within its sample (0 in 2D).  wmat: [cout][K] with
+// 2D 32 -> 32 layer on the matrix cores.  wmat: [cout][K] with
 // K = tap * 32 + cin.  MODE 0 (forward): out = relu(conv(in) + bias);
 // MODE 1 (input gradient): out = conv'(in) * (mask > 0), with `in` the output
 // gradient, `wmat` the transposed weights and `mask` the layer's input
-// activation; MODE 2 (one dz of a 3D layer): accb (FP32) = or += conv(in).
-constexpr int kFwd = 0, kBwd = 1, kAcc = 2;
+// activation.
+constexpr int kFwd = 0, kBwd = 1;
 template <int MODE>
 __global__ __launch_bounds__(256) void k_conv_mid(const bf16 *in, const bf16 *wmat, const float *bias, const bf16 *mask,
-                                                  bf16 *out, float *accb, int first, int H, int W, int nz, int dzo,
-                                                  int tiles_x, int tiles_y) {
+                                                  bf16 *out, int H, int W, int tiles_x, int tiles_y) {
     __shared__ __attribute__((aligned(16))) bf16 tile[(TY + 2) * (TX + 2) * PSTR];
     const int blk = blockIdx.x;
     const int tx = blk % tiles_x, ty = (blk / tiles_x) % tiles_y;
     const int64_t pz = blk / (tiles_x * tiles_y);  // output plane
     const int x0 = tx * TX, y0 = ty * TY;
     const int64_t HW = (int64_t)H * W;
-    const bf16 *inb = in + plane_shift(pz, nz, dzo) * HW * C;
+    const bf16 *inb = in + pz * HW * C;
     const int tid = threadIdx.x;
     // tile with a one-point periodic halo, 16-byte chunks of 8 channels
     for (int q = tid; q < (TY + 2) * (TX + 2) * 4; q += 256) {
@@ -216,13 +215,16 @@ __global__ __launch_bounds__(256) void k_conv_mid(const bf16 *in, const bf16 *wm
     __syncthreads();
     for (int rr = wave; rr < TY; rr += 4) {
         f32x16 acc = {};
+        bf16x8 Af[K / 16];  // every operand load issued before the first product
 #pragma unroll
         for (int ks = 0; ks < K / 16; ++ks) {
             const int t = ks >> 1, dy = t / 3, dx = t % 3;
             const int pix = (rr + dy) * (TX + 2) + (j + dx);
-            const bf16x8 A = *reinterpret_cast<const bf16x8 *>(tile + pix * PSTR + (ks & 1) * 16 + kh * 8);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bf[ks], acc, 0, 0, 0);
+            Af[ks] = *reinterpret_cast<const bf16x8 *>(tile + pix * PSTR + (ks & 1) * 16 + kh * 8);
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ks = 0; ks < K / 16; ++ks) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Af[ks], Bf[ks], acc, 0, 0, 0);
         const int y = y0 + rr;
         if (y >= H) continue;
 #pragma unroll
@@ -232,13 +234,9 @@ __global__ __launch_bounds__(256) void k_conv_mid(const bf16 *in, const bf16 *wm
             if (x >= W) continue;
             const int64_t idx = ((pz * H + y) * (int64_t)W + x) * C + j;
             float val = acc[v];
-            if constexpr (MODE == kAcc) {
-                accb[idx] = first ? val : accb[idx] + val;
-            } else {
-                if constexpr (MODE == kBwd) val = (float)mask[idx] > 0.0f ? val : 0.0f;
-                else val = fmaxf(val + bj, 0.0f);
-                out[idx] = (bf16)val;
-            }
+            if constexpr (MODE == kBwd) val = (float)mask[idx] > 0.0f ? val : 0.0f;
+            else val = fmaxf(val + bj, 0.0f);
+            out[idx] = (bf16)val;
         }
     }
 }
@@ -460,13 +458,82 @@ __global__ __launch_bounds__(FTHREADS) void k_fwd2d_fused(const T *ub, const dou
     zsum_out(nstep - 1);
 }
 
-// the last step of a 3D layer: out = relu(accb + bias) (forward) or
-// accb * (mask > 0) (input gradient), in bf16
-__global__ void k_finish(const float *accb, const float *bias, const bf16 *mask, bf16 *out, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float v = accb[i];
-    out[i] = (bf16)(mask ? ((float)mask[i] > 0.0f ? v : 0.0f) : fmaxf(v + bias[i % C], 0.0f));
+// A whole 3D 32 -> 32 layer in one pass: the input tiles of planes z - 1, z,
+// z + 1 (each with its periodic x-y halo) sit in LDS, and every output row
+// accumulates its 3 x 18 MFMA steps in registers, one weight slice at a time
+// (slices: [dz][cout][K], K = tap * 32 + cin), so no FP32 partial buffer goes
+// through HBM.  MODE kFwd: out = relu(conv(in) + bias); kBwd: out =
+// conv'(in) * (mask > 0) with the transposed, mirrored slices.
+constexpr size_t kMid3Lds = (size_t)3 * (TY + 2) * (TX + 2) * PSTR * sizeof(bf16);
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv_mid3(const bf16 *in, const bf16 *slices, const float *bias,
+                                                   const bf16 *mask, bf16 *out, int H, int W, int nz, int tiles_x,
+                                                   int tiles_y) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char mid3_lds[];
+    bf16 *tiles = reinterpret_cast<bf16 *>(mid3_lds);
+    constexpr int TP = (TY + 2) * (TX + 2) * PSTR;  // one plane's tile
+    const int blk = blockIdx.x;
+    const int tx = blk % tiles_x, ty = (blk / tiles_x) % tiles_y;
+    const int64_t pz = blk / (tiles_x * tiles_y);  // output plane
+    const int x0 = tx * TX, y0 = ty * TY;
+    const int64_t HW = (int64_t)H * W;
+    const int tid = threadIdx.x;
+    for (int dzi = 0; dzi < 3; ++dzi) {
+        const bf16 *inb = in + plane_shift(pz, nz, dzi - 1) * HW * C;
+        for (int q = tid; q < (TY + 2) * (TX + 2) * 4; q += 256) {
+            const int pix = q >> 2, part = q & 3;
+            const int r = pix / (TX + 2), c = pix % (TX + 2);
+            const int gy = (int)((y0 + r - 1 + (int64_t)H) % H), gx = (int)((x0 + c - 1 + (int64_t)W) % W);
+            *reinterpret_cast<uint4 *>(tiles + dzi * TP + pix * PSTR + part * 8) =
+                *reinterpret_cast<const uint4 *>(inb + ((int64_t)gy * W + gx) * C + part * 8);
+        }
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+    const int j = lane & 31, kh = lane >> 5;
+    constexpr int RPW = TY / 4;  // output rows per wave
+    f32x16 acc[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) acc[i] = f32x16{};
+    __syncthreads();
+    for (int dzi = 0; dzi < 3; ++dzi) {
+        bf16x8 Bf[K / 16];
+        const bf16 *wm = slices + (size_t)dzi * C * K9;
+#pragma unroll
+        for (int ks = 0; ks < K / 16; ++ks) Bf[ks] = *reinterpret_cast<const bf16x8 *>(wm + j * K + ks * 16 + kh * 8);
+        const bf16 *tl = tiles + dzi * TP;
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int rr = wave + 4 * i;
+            bf16x8 Af[K / 16];  // every operand load issued before the first product
+#pragma unroll
+            for (int ks = 0; ks < K / 16; ++ks) {
+                const int t = ks >> 1, dy = t / 3, dx = t % 3;
+                const int pix = (rr + dy) * (TX + 2) + (j + dx);
+                Af[ks] = *reinterpret_cast<const bf16x8 *>(tl + pix * PSTR + (ks & 1) * 16 + kh * 8);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int ks = 0; ks < K / 16; ++ks) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Af[ks], Bf[ks], acc[i], 0, 0, 0);
+        }
+    }
+    float bj = 0.0f;
+    if constexpr (MODE == kFwd) bj = bias[j];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+        const int y = y0 + wave + 4 * i;
+        if (y >= H) continue;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int xi = 8 * (v >> 2) + 4 * kh + (v & 3);
+            const int x = x0 + xi;
+            if (x >= W) continue;
+            const int64_t idx = ((pz * H + y) * (int64_t)W + x) * C + j;
+            float val = acc[i][v];
+            if constexpr (MODE == kBwd) val = (float)mask[idx] > 0.0f ? val : 0.0f;
+            else val = fmaxf(val + bj, 0.0f);
+            out[idx] = (bf16)val;
+        }
+    }
 }
 
 // layer 6: 32 channels -> 1, no activation: z
@@ -812,7 +879,7 @@ int fail(int code, const char *fmt, ...) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    size_t wbf, wT, wf, s, rms, act, accb, z, zt, y, dy, dyz, dz, lpart, wpart, grad, total;
+    size_t wbf, wT, wf, s, rms, act, z, zt, y, dy, dyz, dz, lpart, wpart, grad, total;
     int64_t N, nblk_pix;
     int nblk_w;
 };
@@ -851,8 +918,6 @@ Layout layout(const gd_grid *g, bool training, bool own_grad, int smooth) {
     L.act = o;
     const size_t actb = align_up((size_t)L.N * C * 2, 256);
     o += (training ? NL - 1 : 2) * actb;
-    L.accb = o;
-    if (ndz > 1) o = align_up(o + (size_t)L.N * C * 4, 256);
     L.z = o;
     o = align_up(o + (size_t)L.N * 4, 256);
     L.zt = o;  // the second buffer of G^m z (m > 1)
@@ -913,9 +978,9 @@ int check_grid(const gd_cnn *net, const gd_grid *g) {
         if (e_ != hipSuccess) return fail(GD_EHIP, "launch: %s", hipGetErrorString(e_)); \
     } while (0)
 
-// One 32 -> 32 layer (forward, or its input gradient with BWD): the 2D layer
-// in one matrix-core pass; a 3D layer as three plane-shifted passes
-// accumulated in FP32, then bias and ReLU (or the mask) into bf16.
+// One 32 -> 32 layer (forward, or its input gradient with BWD) in one
+// matrix-core pass: k_conv_mid in 2D, k_conv_mid3 (three plane-shifted
+// products in registers) in 3D.
 int mid_layer(bool bwd, const gd_grid *g, const Layout &L, char *w, const bf16 *in, const bf16 *slices,
               const float *bias, const bf16 *mask, bf16 *out, hipStream_t st) {
     const int NT = taps_of(g->ndim), ndz = NT / 9;
@@ -924,21 +989,19 @@ int mid_layer(bool bwd, const gd_grid *g, const Layout &L, char *w, const bf16 *
     const unsigned cblk = (unsigned)(planes_of(g) * tiles_x * tiles_y);
     if (ndz == 1) {
         if (bwd)
-            GD_LAUNCH(k_conv_mid<kBwd>, dim3(cblk), dim3(256), 0, st, in, slices, (const float *)nullptr, mask, out,
-                      (float *)nullptr, 0, H, W, nz, 0, tiles_x, tiles_y);
+            GD_LAUNCH(k_conv_mid<kBwd>, dim3(cblk), dim3(256), 0, st, in, slices, (const float *)nullptr, mask, out, H,
+                      W, tiles_x, tiles_y);
         else
-            GD_LAUNCH(k_conv_mid<kFwd>, dim3(cblk), dim3(256), 0, st, in, slices, bias, (const bf16 *)nullptr, out,
-                      (float *)nullptr, 0, H, W, nz, 0, tiles_x, tiles_y);
+            GD_LAUNCH(k_conv_mid<kFwd>, dim3(cblk), dim3(256), 0, st, in, slices, bias, (const bf16 *)nullptr, out, H,
+                      W, tiles_x, tiles_y);
         return GD_OK;
     }
-    float *accb = (float *)(w + L.accb);
-    for (int dzi = 0; dzi < ndz; ++dzi)
-        GD_LAUNCH(k_conv_mid<kAcc>, dim3(cblk), dim3(256), 0, st, in, slices + (size_t)dzi * C * K9,
-                  (const float *)nullptr, (const bf16 *)nullptr, (bf16 *)nullptr, accb, dzi == 0 ? 1 : 0, H, W, nz,
-                  dzi - 1, tiles_x, tiles_y);
-    const int64_t n = L.N * C;
-    GD_LAUNCH(k_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const float *)accb, bwd ? nullptr : bias,
-              bwd ? mask : (const bf16 *)nullptr, out, n);
+    if (bwd)
+        GD_LAUNCH(k_conv_mid3<kBwd>, dim3(cblk), dim3(256), kMid3Lds, st, in, slices, (const float *)nullptr, mask,
+                  out, H, W, nz, tiles_x, tiles_y);
+    else
+        GD_LAUNCH(k_conv_mid3<kFwd>, dim3(cblk), dim3(256), kMid3Lds, st, in, slices, bias, (const bf16 *)nullptr,
+                  out, H, W, nz, tiles_x, tiles_y);
     return GD_OK;
 }
 
