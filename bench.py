@@ -874,9 +874,10 @@ def main():
                          "choices are saved for later --no-tune runs, e.g. under a profiler)")
     ap.add_argument("--solvers", default="bicgstab,cg,vc,vcb",
                     help="vcb: Van Cittert with several passes per sweep (same iterates, less traffic)")
-    ap.add_argument("--train-steps", type=int, default=8192,
-                    help="warm-start workload: Adam steps (batches of 8 fields: 16 passes over 4096 fields, "
-                         "about 46 s per 2D network)")
+    ap.add_argument("--train-steps", type=int, default=16384,
+                    help="warm-start workload: Adam steps (batches of 8 fields: 32 passes over 4096 fields, "
+                         "about 100 s per 2D network; 8192 steps left the differential start at the plain "
+                         "start's wall-clock, 16384 beat it)")
     ap.add_argument("--train-fields", type=int, default=4096, help="warm-start workload: 512^2 training fields")
     ap.add_argument("--smooth", type=int, default=1,
                     help="warm-start workload: applications of G to the network's output (1 measured best: with the "
