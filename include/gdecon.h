@@ -242,12 +242,12 @@ int deconvolve_batch(int32_t solver, int32_t dtype, const gd_instance *list, int
 /*
  * ---- Autotuner -------------------------------------------------------------
  *
- * Times (short fixed-length trial solves) the candidate launch configurations of a solve (tile granularity:
+ * Times the candidate launch configurations of a solve (tile granularity:
  * target tiles per resident wave; the share of short tiles claimed at the end
  * of every sweep; the tile-pool layout; per-wave or per-workgroup tile
- * claims; 3D rows per tile where the uniform kernels offer a choice) with short fixed-length trial solves on the caller's
- * buffers and remembers the fastest for this (solver, dtype, sizes)
- * signature.  Later deconvolve_* / deconvolve_batch calls with the same
+ * claims; workgroups per CU; 3D rows per tile where the uniform kernels offer
+ * a choice) with short fixed-length trial solves on the caller's buffers and
+ * remembers the fastest for this (solver, dtype, sizes) signature.  Later deconvolve_* / deconvolve_batch calls with the same
  * signature use it.  With the environment variable GD_TUNE_CACHE naming a
  * file, choices are also appended there and read back by later processes.
  * Synchronous (waits for the stream); not for use under graph capture.
@@ -264,7 +264,8 @@ typedef struct gd_tune_info {
                                 (halo reuse in L2), 1 interleaved over the XCDs */
     int32_t wave_claims;     /* 1: every wave claims its own tiles; 0: a
                                 workgroup claims tiles for its four waves */
-    int32_t reserved;
+    int32_t blocks_per_cu;   /* chosen workgroups per CU of the persistent grid
+                                (0 = as many as fit; at most 16) */
     double best_ms;          /* trial time of the chosen configuration */
     double default_ms;       /* trial time of the untuned default */
 } gd_tune_info;
@@ -277,8 +278,8 @@ int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *
 /* Pin the launch configuration of a signature without timing anything (for
  * reproducible runs): later solves with the same solver, grid and pointer
  * alignment (the alignment of ubar and u decides the lane width), or the same
- * instance list, use `choice` (its tiles_per_wave, rows, tail_pct, interleave
- * and wave_claims; the timing fields are ignored).  Also written to the
+ * instance list, use `choice` (its tiles_per_wave, rows, tail_pct,
+ * interleave, wave_claims and blocks_per_cu; the timing fields are ignored).  Also written to the
  * GD_TUNE_CACHE file when it is set.  Errors: GD_EINVAL. */
 int gd_tune_set(int32_t solver, const gd_grid *grid, const void *ubar, const void *u, const gd_tune_info *choice);
 int gd_tune_set_batch(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count,

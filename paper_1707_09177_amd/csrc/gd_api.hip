@@ -364,15 +364,17 @@ void tune_load_locked() {
     char line[1024];
     while (fgets(line, sizeof line, fp)) {
         char key[900];
-        int tpw = 0, rows = 0, tail = 0, ilv = 0, wc = 0;
-        if (sscanf(line, "%899s %d %d %d %d %d", key, &tpw, &rows, &tail, &ilv, &wc) == 6 && tpw >= 1 && tpw <= 64 &&
-            rows >= 0 && rows <= 4 && tail >= 0 && tail <= 50 && (ilv == 0 || ilv == 1) && (wc == 0 || wc == 1)) {
+        int tpw = 0, rows = 0, tail = 0, ilv = 0, wc = 0, bpc = kBlocksPerCu;
+        const int nf = sscanf(line, "%899s %d %d %d %d %d %d", key, &tpw, &rows, &tail, &ilv, &wc, &bpc);
+        if ((nf == 6 || nf == 7) && tpw >= 1 && tpw <= 64 && rows >= 0 && rows <= 4 && tail >= 0 && tail <= 50 &&
+            (ilv == 0 || ilv == 1) && (wc == 0 || wc == 1) && bpc >= 0 && bpc <= kMaxBlocksPerCu) {
             TuneCfg c;
             c.tpw = tpw;
             c.rows = rows;
             c.tail = tail;
             c.ilv = ilv;
             c.wc = wc;
+            c.bpc = bpc;
             g_tune[key] = c;
         }
     }
@@ -394,7 +396,7 @@ void tune_store(const std::string &key, const TuneCfg &c) {
     g_tune[key] = c;
     if (const char *f = tune_file()) {
         if (FILE *fp = fopen(f, "a")) {
-            fprintf(fp, "%s %d %d %d %d %d\n", key.c_str(), c.tpw, c.rows, c.tail, c.ilv, c.wc);
+            fprintf(fp, "%s %d %d %d %d %d %d\n", key.c_str(), c.tpw, c.rows, c.tail, c.ilv, c.wc, c.bpc);
             fclose(fp);
         }
     }
@@ -452,7 +454,7 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
     const int variant = (spec ? kSpecBit : 0) + var_code(g->ndim, ts.vw, ts.R);
     const void *kern = nullptr;
     int64_t blocks_cap = 0;
-    rc = solve_grid(g->dtype, solver, variant, ts.blocks_per_cu, &kern, &blocks_cap);
+    rc = solve_grid(g->dtype, solver, variant, cfg.bpc, &kern, &blocks_cap);
     if (rc) return rc;
     // march length balanced over the waves the persistent grid will hold
     ts.L = balanced_L(g->ndim == 2 ? ny : nz, g->batch * tiles_per_plane(g->ndim, nx, ny, ts.vw, ts.R),
@@ -671,12 +673,12 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
         if (I.ndim != tab[0].ndim || I.vw != tab[0].vw) same = false;
     }
     const int variant = (same && tab[0].vw == vm) ? kTableBit + var_code(tab[0].ndim, vm, 1) : VAR_ALL;
-    const void *kern = nullptr;
-    int64_t blocks_cap = 0;
-    if ((rc = solve_grid(dtype, solver, variant, 0, &kern, &blocks_cap))) return rc;
     TuneCfg cfg;
     if (force) cfg = *force;
     else tune_lookup(key_batch(solver, dtype, list, count), &cfg);
+    const void *kern = nullptr;
+    int64_t blocks_cap = 0;
+    if ((rc = solve_grid(dtype, solver, variant, cfg.bpc, &kern, &blocks_cap))) return rc;
 
     // Tiles of about equal size across instances: target points per tile from
     // the total work and the tiles the grid should hold.
@@ -843,7 +845,7 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
         out->tail_pct = cands[best].tail;
         out->interleave = cands[best].ilv;
         out->wave_claims = cands[best].wc;
-        out->reserved = 0;
+        out->blocks_per_cu = cands[best].bpc;
         out->best_ms = best_ms;
         out->default_ms = std::min(default_first, t.empty() ? 0.0 : t[0]);
     }
@@ -864,6 +866,7 @@ gd_opts trial_opts(int solver) {
 
 const int kTpwCands[] = {kTilesPerWave, 1, 3, 4, 6};
 const int kTailCands[] = {kTailPct, 0, 25};
+const int kBpcCands[] = {kBlocksPerCu, 0};
 
 // Time the launch configurations of a uniform solve (on a stored spectrum
 // when `spec` is set) and remember the fastest.
@@ -876,19 +879,21 @@ int tune_uniform(int solver, const gd_grid *g, const void *ubar, void *u, void *
     std::vector<TuneCfg> cands;
     std::vector<int> rows = {0};
     if (g->ndim == 3 && !spec) rows = {0, 1, 2, 4};
-    for (int r : rows)
-        for (int t : kTpwCands)
-            for (int tl : kTailCands)
-                for (int il = 0; il < 2; ++il)
-                    for (int wc = 0; wc < 2; ++wc) {
-                        TuneCfg c;
-                        c.tpw = t;
-                        c.rows = r;
-                        c.tail = tl;
-                        c.ilv = il;
-                        c.wc = wc;
-                        cands.push_back(c);
-                    }
+    for (int bp : kBpcCands)
+        for (int r : rows)
+            for (int t : kTpwCands)
+                for (int tl : kTailCands)
+                    for (int il = 0; il < 2; ++il)
+                        for (int wc = 0; wc < 2; ++wc) {
+                            TuneCfg c;
+                            c.tpw = t;
+                            c.rows = r;
+                            c.tail = tl;
+                            c.ilv = il;
+                            c.wc = wc;
+                            c.bpc = bp;
+                            cands.push_back(c);
+                        }
     // every candidate must launch; a shape the field cannot use falls back to
     // the default rule inside solve_uniform, so duplicates are harmless
     auto launch = [&](const TuneCfg &c) {
@@ -1034,17 +1039,19 @@ int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *
                               size_t wb, gd_info *info, void *stream, gd_tune_info *out) {
     const gd_opts o = trial_opts(solver);
     std::vector<TuneCfg> cands;
-    for (int t : kTpwCands)
-        for (int tl : kTailCands)
-            for (int il = 0; il < 2; ++il)
-                for (int wc = 0; wc < 2; ++wc) {
-                    TuneCfg c;
-                    c.tpw = t;
-                    c.tail = tl;
-                    c.ilv = il;
-                    c.wc = wc;
-                    cands.push_back(c);
-                }
+    for (int bp : kBpcCands)
+        for (int t : kTpwCands)
+            for (int tl : kTailCands)
+                for (int il = 0; il < 2; ++il)
+                    for (int wc = 0; wc < 2; ++wc) {
+                        TuneCfg c;
+                        c.tpw = t;
+                        c.tail = tl;
+                        c.ilv = il;
+                        c.wc = wc;
+                        c.bpc = bp;
+                        cands.push_back(c);
+                    }
     auto launch = [&](const TuneCfg &c) {
         return solve_batch(solver, dtype, list, count, &o, work, wb, info, stream, &c);
     };
@@ -1057,13 +1064,15 @@ int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *
 static int tune_choice(const gd_tune_info *c, TuneCfg *cfg) {
     if (!c) return fail(GD_EINVAL, "choice is NULL");
     if (c->tiles_per_wave < 1 || c->tiles_per_wave > 64 || c->rows < 0 || c->rows > 4 || c->tail_pct < 0 ||
-        c->tail_pct > 50 || (c->interleave != 0 && c->interleave != 1) || (c->wave_claims != 0 && c->wave_claims != 1))
+        c->tail_pct > 50 || (c->interleave != 0 && c->interleave != 1) || (c->wave_claims != 0 && c->wave_claims != 1) ||
+        c->blocks_per_cu < 0 || c->blocks_per_cu > kMaxBlocksPerCu)
         return fail(GD_EINVAL, "launch configuration out of range");
     cfg->tpw = c->tiles_per_wave;
     cfg->rows = c->rows;
     cfg->tail = c->tail_pct;
     cfg->ilv = c->interleave;
     cfg->wc = c->wave_claims;
+    cfg->bpc = c->blocks_per_cu;
     return GD_OK;
 }
 

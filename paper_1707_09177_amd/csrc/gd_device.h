@@ -8,9 +8,9 @@
 // G = Gx Gy (Gz), with 1D weights (1/4, 1/2, 1/4), is evaluated separably:
 //   * x: in 3D the neighbours x0-1 and x0+VW of a lane's points are the
 //     edge points of the lanes beside it, passed across by full-wave DPP
-//     shifts; only the wave's first lane and its last active lane load a
-//     point of their own (the periodic neighbour outside the wave's span).
-//     In 2D each lane loads its two neighbours itself (L1 hits);
+//     shifts; the periodic neighbours outside the wave's span are loaded by
+//     lane 0 (left) and by the lane after the last active one, or lane 63
+//     (right).  In 2D each lane loads its two neighbours itself (L1 hits);
 //   * y (3D only): a tile spans R rows; R+2 rows (one halo row each side) are
 //     x-filtered per plane and combined in registers;
 //   * the march axis: a rolling window of three x(y)-filtered planes.
@@ -18,7 +18,9 @@
 // sweeps evaluate it pointwise from several fields (for example
 // p_{n+1} = r_n + beta (p_n - omega q_n) in BiCGSTAB), so one fused pass both
 // forms p_{n+1} and applies G to it.  Loads are branch-free (inactive lanes
-// read a valid clamped address and discard the value).
+// read a valid clamped address and discard the value).  A tile's planes, rows
+// and x segment are the same in every lane (scalar registers), and a lane's
+// loads address a plane as a scalar base plus a 32-bit byte offset.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -100,9 +102,10 @@ struct Geo {
 
 template <int N> struct Arr { static constexpr int n = N > 0 ? N : 1; };
 
-// Tile position of a lane.
+// Tile position of a lane.  seg0 (the wave's first column), row0, m0 and m1
+// are the same in every lane of the wave.
 struct TilePos {
-    int64_t x0, xc, xl, xr, row0, m0, m1;
+    int64_t x0, xc, xl, xr, seg0, row0, m0, m1;
     bool act;
 };
 
@@ -125,13 +128,21 @@ __device__ __forceinline__ TilePos tile_pos(const Geo &g, int64_t lt, int lane) 
     p.m1 = mend < g.nmarch ? mend : g.nmarch;
     const int64_t xs = c % g.nxs;
     const int64_t rs = c / g.nxs;
-    p.x0 = xs * (WAVE * VW) + (int64_t)lane * VW;
+    p.seg0 = xs * (WAVE * VW);
+    p.x0 = p.seg0 + (int64_t)lane * VW;
     p.act = p.x0 < g.nx;
     p.xc = p.act ? p.x0 : g.nx - VW;  // a valid column for inactive lanes
     p.xl = p.xc == 0 ? g.nx - 1 : p.xc - 1;
     p.xr = (p.xc + VW >= g.nx) ? p.xc + VW - g.nx : p.xc + VW;
     p.row0 = rs * R;
     return p;
+}
+
+// base + byte_off: a wave-uniform base (scalar registers) plus a 32-bit
+// per-lane byte offset, the form of a global load with a scalar base address
+template <typename T>
+__device__ __forceinline__ const T *at_off(const T *base, uint32_t byte_off) {
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
 // Full-wave DPP shifts by one lane (GFX9 wave_shr:1 / wave_shl:1): lane i
@@ -168,40 +179,49 @@ __device__ __forceinline__ void march_row(const Geo &g, int64_t lt, const Op &op
     const TilePos p = tile_pos<VW, 1>(g, lt, lane);
     auto wrapm = [&](int64_t m) -> int64_t { return m < 0 ? m + g.nmarch : (m >= g.nmarch ? m - g.nmarch : m); };
 
+    // a plane is one row: loads address it as a uniform base plus 32-bit byte offsets
+    const uint32_t oc = (uint32_t)(p.xc * (int64_t)sizeof(T));
+    const uint32_t ol = (uint32_t)(p.xl * (int64_t)sizeof(T));
+    const uint32_t orr = (uint32_t)(p.xr * (int64_t)sizeof(T));
     // raw stencil inputs of one plane: the lane's vector and its two x neighbours
-    T cv[NI][VW], cl[NI], cr[NI];
     auto load_in = [&](int64_t mw, T (&v)[NI][VW], T (&l)[NI], T (&r)[NI]) {
-        const int64_t base = mw * g.plane;
 #pragma unroll
         for (int f = 0; f < Op::NI; ++f) {
-            vld<T, VW>(op.in[f] + base + p.xc, v[f]);
-            l[f] = op.in[f][base + p.xl];
-            r[f] = op.in[f][base + p.xr];
+            const T *pb = op.in[f] + mw * g.plane;
+            vld<T, VW>(at_off(pb, oc), v[f]);
+            l[f] = *at_off(pb, ol);
+            r[f] = *at_off(pb, orr);
         }
     };
-    T co[NO][VW];
     auto load_out = [&](int64_t m, T (&o)[NO][VW]) {
 #pragma unroll
-        for (int f = 0; f < Op::NO; ++f) vld_nt<T, VW>(op.oin[f] + m * g.plane + p.xc, o[f]);
+        for (int f = 0; f < Op::NO; ++f) vld_nt<T, VW>(at_off(op.oin[f] + m * g.plane, oc), o[f]);
     };
 
-    C W0[VW], W1[VW], W2[VW], S1[VW], S2[VW];
+    // the x-filtered rows of planes m-2, m-1, m (G_y combines them)
+    C W0[VW], W1[VW], W2[VW], SA[VW], SB[VW];
 #pragma unroll
-    for (int k = 0; k < VW; ++k) W0[k] = W1[k] = W2[k] = S1[k] = S2[k] = C(0);
+    for (int k = 0; k < VW; ++k) W0[k] = W1[k] = W2[k] = SA[k] = SB[k] = C(0);
+    // ping-pong buffers (the march is unrolled by two, so no buffer is copied
+    // from one step to the next): plane loads and centre fields
+    T vA[NI][VW], lA[NI], rA[NI], vB[NI][VW], lB[NI], rB[NI], oA[NO][VW], oB[NO][VW];
 #pragma unroll
     for (int f = 0; f < NO; ++f)
 #pragma unroll
-        for (int k = 0; k < VW; ++k) co[f][k] = T(0);
+        for (int k = 0; k < VW; ++k) oA[f][k] = oB[f][k] = T(0);
 
-    load_in(wrapm(p.m0 - 1), cv, cl, cr);
-    for (int64_t m = p.m0 - 1; m <= p.m1; ++m) {
-        // prefetch: inputs of plane m+1, centre fields of plane m
-        T nv[NI][VW], nl[NI], nr[NI], no[NO][VW];
-        if (m < p.m1) load_in(wrapm(m + 1), nv, nl, nr);
-        if (m >= p.m0 && m < p.m1) load_out(m, no);
+    // step m: plane m is in (cv, cl, cr); plane m + 1's loads go to (nv, nl,
+    // nr), plane m's centre fields to no; co holds plane m - 1's, sprev S(m-1).
+    // The loads are unconditional (the last step reloads its own plane and the
+    // first and last load unused centre fields, from cache), so no register
+    // array needs a copy for a path that skips them.
+    auto step = [&](int64_t m, T (&cv)[NI][VW], T (&cl)[NI], T (&cr)[NI], T (&nv)[NI][VW], T (&nl)[NI],
+                    T (&nr)[NI], T (&co)[NO][VW], T (&no)[NO][VW], C (&sprev)[VW], C (&scur)[VW]) {
+        load_in(wrapm(m < p.m1 ? m + 1 : m), nv, nl, nr);
+        load_out(m < p.m0 ? p.m0 : (m < p.m1 ? m : p.m1 - 1), no);
 
         // x-filter plane m
-        C sc[VW], hx[VW], left, right;
+        C hx[VW], left, right;
         {
             T a[NI], b[NI];
 #pragma unroll
@@ -217,50 +237,37 @@ __device__ __forceinline__ void march_row(const Geo &g, int64_t lt, const Op &op
             T a[NI];
 #pragma unroll
             for (int f = 0; f < NI; ++f) a[f] = cv[f][k];
-            sc[k] = op.mix(a);
+            scur[k] = op.mix(a);
         }
 #pragma unroll
         for (int k = 0; k < VW; ++k) {
-            const C l = k == 0 ? left : sc[k - 1];
-            const C rr = k == VW - 1 ? right : sc[k + 1];
-            hx[k] = C(0.5) * sc[k] + C(0.25) * (l + rr);
+            const C l = k == 0 ? left : scur[k - 1];
+            const C rr = k == VW - 1 ? right : scur[k + 1];
+            hx[k] = C(0.5) * scur[k] + C(0.25) * (l + rr);
         }
+        C gv[VW];
 #pragma unroll
         for (int k = 0; k < VW; ++k) {
             W0[k] = W1[k];
             W1[k] = W2[k];
             W2[k] = hx[k];
-            S1[k] = S2[k];
-            S2[k] = sc[k];
+            gv[k] = C(0.5) * W1[k] + C(0.25) * (W0[k] + W2[k]);
         }
         // output plane m-1 (its centre fields were loaded one step ago)
-        if (m > p.m0 && p.act) {
-            C gv[VW];
-#pragma unroll
-            for (int k = 0; k < VW; ++k) gv[k] = C(0.5) * W1[k] + C(0.25) * (W0[k] + W2[k]);
-            op.out((m - 1) * g.plane + p.x0, S1, gv, co, acc);
-        }
-        // rotate the prefetch buffers
-#pragma unroll
-        for (int f = 0; f < NI; ++f) {
-            cl[f] = nl[f];
-            cr[f] = nr[f];
-#pragma unroll
-            for (int k = 0; k < VW; ++k) cv[f][k] = nv[f][k];
-        }
-#pragma unroll
-        for (int f = 0; f < NO; ++f)
-#pragma unroll
-            for (int k = 0; k < VW; ++k) co[f][k] = no[f][k];
+        if (m > p.m0 && p.act) op.out((m - 1) * g.plane + p.x0, sprev, gv, co, acc);
+    };
+
+    load_in(wrapm(p.m0 - 1), vA, lA, rA);
+    for (int64_t m = p.m0 - 1; m <= p.m1; m += 2) {
+        step(m, vA, lA, rA, vB, lB, rB, oB, oA, SB, SA);
+        if (m + 1 <= p.m1) step(m + 1, vB, lB, rB, vA, lA, rA, oA, oB, SA, SB);
     }
 }
 
 // 3D march: a tile spans R rows of a plane, and R + 2 rows (one halo row
 // each side) are x-filtered per plane and combined in y in registers.  The x
-// neighbours cross lanes by DPP; S is formed as soon as a plane's loads have
-// arrived, and the registers of the raw loads then take the next plane's,
-// which are in flight while the plane is filtered (one raw plane of R + 2
-// rows per wave, not two).  Must be called by the whole wave.
+// neighbours cross lanes by DPP; the next plane's loads are in flight while a
+// plane is filtered.  Must be called by the whole wave.
 template <int VW, int R, typename T, typename C, class Op>
 __device__ __forceinline__ void march_slab(const Geo &g, int64_t lt, const Op &op, double (&acc)[NACC], int lane) {
     constexpr int HR = R + 2;
@@ -284,16 +291,18 @@ __device__ __forceinline__ void march_slab(const Geo &g, int64_t lt, const Op &o
     }
 
     // the wave's x span: lanes 0 .. last hold field points (a field's last
-    // segment may be partial; nx is a multiple of VW)
-    const int64_t seg0 = p.x0 - (int64_t)lane * VW;
+    // segment may be partial; nx is a multiple of VW); the same in every lane
+    const int64_t seg0 = p.seg0;
     const int64_t nseg = nx - seg0 < (int64_t)WAVE * VW ? nx - seg0 : (int64_t)WAVE * VW;
     const int last = (int)(nseg / VW) - 1;
-    // the periodic neighbours outside the span: lane 0 loads the left one,
-    // lane `last` the right one (when last == 0, lane 0 needs both: the right
-    // one is then loaded when the plane is formed)
+    // the periodic neighbours outside the span: lane 0 loads the left one; the
+    // right one is loaded by lane last + 1 (a lane without points of its own)
+    // when the span is partial, else by lane last = 63
+    const bool full = last == WAVE - 1;
+    const int redge = full ? last : last + 1;
     const int64_t xleft = seg0 == 0 ? nx - 1 : seg0 - 1;
     const int64_t xright = seg0 + nseg >= nx ? seg0 + nseg - nx : seg0 + nseg;
-    const int64_t xe = lane == 0 ? xleft : (lane == last ? xright : p.xc);
+    const int64_t xe = lane == 0 ? xleft : (lane == redge ? xright : p.xc);
 
     auto wrapm = [&](int64_t m) -> int64_t { return m < 0 ? m + g.nmarch : (m >= g.nmarch ? m - g.nmarch : m); };
 
@@ -309,11 +318,9 @@ __device__ __forceinline__ void march_slab(const Geo &g, int64_t lt, const Op &o
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) oo[r] = (uint32_t)((orow[r] + p.xc) * (int64_t)sizeof(T));
-    auto at = [](const T *base, uint32_t byte_off) {
-        return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
-    };
+    auto at = [](const T *base, uint32_t byte_off) { return at_off(base, byte_off); };
 
-    // raw stencil inputs of the plane in flight: the lane's vector and its edge point
+    // raw stencil inputs of the plane in flight: the lane's vectors and edge points
     T raw[HR][NI][VW], rawe[HR][NI];
     auto load_in = [&](int64_t mw) {
 #pragma unroll
@@ -338,11 +345,13 @@ __device__ __forceinline__ void march_slab(const Geo &g, int64_t lt, const Op &o
         }
     };
 
-    C W0[R][VW], W1[R][VW], W2[R][VW], S1[R][VW], S2[R][VW];
+    // the in-plane filtered planes m-2, m-1, m (G_z combines them); S1 holds
+    // S(m-1) until its output
+    C W0[R][VW], W1[R][VW], W2[R][VW], S1[R][VW];
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int k = 0; k < VW; ++k) W0[r][k] = W1[r][k] = W2[r][k] = S1[r][k] = S2[r][k] = C(0);
+        for (int k = 0; k < VW; ++k) W0[r][k] = W1[r][k] = W2[r][k] = S1[r][k] = C(0);
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -364,22 +373,19 @@ __device__ __forceinline__ void march_slab(const Geo &g, int64_t lt, const Op &o
                 sm[h][k] = op.mix(a);
             }
             se[h] = op.mix(rawe[h]);
-            sr[h] = se[h];
+            // lane last's right neighbour: its own edge point on a full span,
+            // else lane last + 1's
+            sr[h] = full ? se[h] : dpp_shift<kDppWaveShl1>(se[h]);
         }
-        if (last == 0) {  // a one-lane span: lane 0's right neighbour, loaded now
-            const int64_t mw = wrapm(m);
-#pragma unroll
-            for (int h = 0; h < HR; ++h) {
-                T e[NI];
-#pragma unroll
-                for (int f = 0; f < NI; ++f) e[f] = op.in[f][mw * g.plane + rowoff[h] + xright];
-                sr[h] = op.mix(e);
-            }
-        }
-        // prefetch plane m+1 into the registers just freed
-        if (m < p.m1) load_in(wrapm(m + 1));
+        // plane m + 1 into the registers just freed.  The scheduler may not
+        // hoist these loads above the use of plane m's values, and they are
+        // unconditional (the last step reloads its own plane, from cache): the
+        // loads then reuse the same registers, with no copy at the end of the
+        // step.
+        __builtin_amdgcn_sched_barrier(0);
+        load_in(wrapm(m < p.m1 ? m + 1 : m));
 
-        // x-filter the R + 2 rows of plane m
+        // x-filter the R + 2 rows of plane m, then y and z
         C hx[HR][VW];
 #pragma unroll
         for (int h = 0; h < HR; ++h) {
@@ -394,6 +400,7 @@ __device__ __forceinline__ void march_slab(const Geo &g, int64_t lt, const Op &o
                 hx[h][k] = C(0.5) * sm[h][k] + C(0.25) * (l + rr);
             }
         }
+        C gv[R][VW];
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -401,24 +408,26 @@ __device__ __forceinline__ void march_slab(const Geo &g, int64_t lt, const Op &o
                 W0[r][k] = W1[r][k];
                 W1[r][k] = W2[r][k];
                 W2[r][k] = C(0.5) * hx[r + 1][k] + C(0.25) * (hx[r][k] + hx[r + 2][k]);
-                S1[r][k] = S2[r][k];
-                S2[r][k] = sm[r + 1][k];
+                gv[r][k] = C(0.5) * W1[r][k] + C(0.25) * (W0[r][k] + W2[r][k]);
             }
-        // output plane m-1 (its centre fields were loaded one step ago)
+        // output plane m - 1 (its centre fields were loaded one step ago)
         if (m > p.m0) {
             const int64_t mo = m - 1;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (p.act && p.row0 + r < g.nrows) {
-                    C gv[VW];
-#pragma unroll
-                    for (int k = 0; k < VW; ++k) gv[k] = C(0.5) * W1[r][k] + C(0.25) * (W0[r][k] + W2[r][k]);
-                    op.out(mo * g.plane + (p.row0 + r) * nx + p.x0, S1[r], gv, co[r], acc);
-                }
+                if (p.act && p.row0 + r < g.nrows)
+                    op.out(mo * g.plane + (p.row0 + r) * nx + p.x0, S1[r], gv[r], co[r], acc);
             }
         }
-        // centre fields of plane m, for the next step's output
-        if (m >= p.m0 && m < p.m1) load_out(m);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < VW; ++k) S1[r][k] = sm[r + 1][k];
+        // centre fields of plane m, for the next step's output (unconditional
+        // too: the first and the last step load a neighbouring plane of the
+        // tile, unused)
+        __builtin_amdgcn_sched_barrier(0);
+        load_out(m < p.m0 ? p.m0 : (m < p.m1 ? m : p.m1 - 1));
     }
 }
 

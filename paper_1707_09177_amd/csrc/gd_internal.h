@@ -135,6 +135,12 @@ constexpr int kSteal = NGRP;
 constexpr int kTilesPerWave = 2;
 // Percent of every column's planes cut into short tiles (claimed last).
 constexpr int kTailPct = 15;
+// Workgroups per CU of the persistent grid (0: as many as fit).  Two waves
+// per SIMD measured faster than three for the 2D kernels, which fit three
+// (16 x 2048^2 FP32: BiCGSTAB 4.47 against 4.89 ms, CG 3.72 against 4.66 ms);
+// most 3D and uneven-batch kernels fit two anyway.
+constexpr int kBlocksPerCu = 2;
+constexpr int kMaxBlocksPerCu = 16;
 
 struct Params {
     Inst tmpl;            // uniform batch: instance 0 (others offset by stride)
@@ -172,6 +178,7 @@ struct TuneCfg {
     int tail = kTailPct;
     int ilv = 0;  // interleaved tile pools
     int wc = 0;   // per-wave tile claims
+    int bpc = kBlocksPerCu;  // workgroups per CU (0: as many as fit)
 };
 
 // A solve on a stored Fourier spectrum (the differential filter); hw is the

@@ -33,6 +33,13 @@ __device__ __forceinline__ int ld_i32(const int32_t *p) {
 __device__ __forceinline__ double ld_f64(const double *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// v, which is the same in every lane, as a value the compiler knows to be
+// wave-uniform (kept in scalar registers, with scalar branches on it)
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 template <bool TABLE>
 static __device__ __forceinline__ Inst get_inst(const Params &P, int i) {
@@ -562,6 +569,9 @@ __device__ __forceinline__ bool skip_instance(const Params &P, const State *S) {
 template <typename T, int VS, int PH>
 __device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch, int64_t t, int lane) {
     constexpr int nacc = PhaseNacc<PH>::v;
+    // the tile, and with it the instance, the tile's planes and rows and the
+    // plane addresses of the march, are the same in every lane
+    t = wave_uniform(t);
     int64_t lt = 0;
     const int i = locate<var_table(VS)>(P, t, lt);
     State *S = &P.st[i];
@@ -602,7 +612,7 @@ __device__ __forceinline__ void run_tile(const Params &P, int it, uint32_t epoch
 template <typename T, int VS, int PH>
 __device__ __forceinline__ void run_phase(const Params &P, int it, uint32_t epoch) {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t ntot = P.total_tiles;
     __shared__ int64_t s_base;
     __shared__ uint32_t s_left[NGRP];
@@ -831,11 +841,11 @@ static __device__ __forceinline__ int grid_sync(const Params &P, uint32_t &epoch
     return sn.active;
 }
 
-// Waves per SIMD the kernels of a variant must reach: the FP32 table-driven
-// kernels (uneven batches) sit just above the 256 registers that two waves
-// allow, so they are held to two (a few bytes spill); the others keep the
-// count their registers give.
-template <typename T, int VS> constexpr int kMinWavesPerEU = (var_table(VS) && sizeof(T) == 4) ? 2 : 1;
+// Waves per SIMD the kernels of a variant must reach: two for FP32, whose
+// kernels all fit the 256 registers of two waves without spilling (the
+// two-row 3D BiCGSTAB kernel only just); FP64 keeps the count its registers
+// give (its two-row and four-row 3D kernels would spill).
+template <typename T, int VS> constexpr int kMinWavesPerEU = sizeof(T) == 4 ? 2 : 1;
 
 template <typename T, int SOLVER, int VS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kMinWavesPerEU<T, VS>))) void solve_kernel(
@@ -914,7 +924,7 @@ template <typename T, int VS>
 __global__ __launch_bounds__(BLOCK) void filter_kernel(Inst tmpl, int64_t stride_elems, int64_t tiles_per_inst,
                                                        int64_t total_tiles) {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t t = (int64_t)blockIdx.x * WPB + (threadIdx.x >> 6);
+    const int64_t t = (int64_t)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= total_tiles) return;
     const int64_t b = t / tiles_per_inst;
     const T *x = static_cast<const T *>(tmpl.ubar) + b * stride_elems;

@@ -63,7 +63,7 @@ class Instance(ctypes.Structure):
 class TuneInfo(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int32), ("best", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32),
                 ("rows", ctypes.c_int32), ("tail_pct", ctypes.c_int32), ("interleave", ctypes.c_int32),
-                ("wave_claims", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("wave_claims", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
@@ -503,10 +503,11 @@ def autotune(solver: str, ubar: torch.Tensor, ndim: int = 2, out: torch.Tensor |
     return _tune_dict(t)
 
 
-def _choice(tiles_per_wave=2, rows=0, tail_pct=0, interleave=0, wave_claims=0) -> TuneInfo:
+def _choice(tiles_per_wave=2, rows=0, tail_pct=0, interleave=0, wave_claims=0, blocks_per_cu=2) -> TuneInfo:
     t = TuneInfo()
     t.tiles_per_wave, t.rows, t.tail_pct, t.interleave, t.wave_claims = (int(tiles_per_wave), int(rows), int(tail_pct),
                                                                          int(interleave), int(wave_claims))
+    t.blocks_per_cu = int(blocks_per_cu)
     return t
 
 
@@ -514,7 +515,7 @@ def tune_set(solver: str, ubar: torch.Tensor, out: torch.Tensor, ndim: int = 2, 
     """Pin the launch configuration for solves of `solver` on fields shaped
     like ubar whose input and output are aligned like ubar and out
     (gd_tune_set).  choice: tiles_per_wave, rows, tail_pct, interleave,
-    wave_claims."""
+    wave_claims, blocks_per_cu (0: as many workgroups per CU as fit)."""
     g = make_grid(ubar.shape, ndim, ubar.dtype)
     t = _choice(**choice)
     _check(load().gd_tune_set(SOLVERS[solver], ctypes.byref(g), _dev_ptr(ubar), _dev_ptr(out), ctypes.byref(t)))

@@ -131,6 +131,9 @@ def test_tune_set_validates_choices():
     assert lib.gd_tune_set(2, ctypes.byref(g), 256, 512, ctypes.byref(bad)) == -1
     bad = gdecon._choice(wave_claims=2)
     assert lib.gd_tune_set(2, ctypes.byref(g), 256, 512, ctypes.byref(bad)) == -1
+    for bpc in (-1, 17):
+        bad = gdecon._choice(blocks_per_cu=bpc)
+        assert lib.gd_tune_set(2, ctypes.byref(g), 256, 512, ctypes.byref(bad)) == -1
     assert lib.gd_tune_set(7, ctypes.byref(g), 256, 512, ctypes.byref(gdecon._choice())) == -1
 
 

@@ -1,7 +1,8 @@
 """Every launch configuration the autotuner can choose gives the same answer.
 
 Each case pins one configuration (gd_tune_set / gd_tune_set_batch): tile
-granularity, short tail tiles, interleaved pools and per-wave claims.  It then
+granularity, short tail tiles, interleaved pools, per-wave claims and
+workgroups per CU (two, or as many as fit).  It then
 checks the solve against the CPU FP64 oracle: relative L2 <= 1e-10 in FP64
 and equal pass counts.  Configurations only change which wave handles which
 tile and how the partial sums are split, never what is computed.
@@ -16,7 +17,7 @@ from paper_1707_09177_amd import gdecon
 
 pytestmark = pytest.mark.gpu
 
-MODES = [dict(tiles_per_wave=tpw, tail_pct=tail, interleave=ilv, wave_claims=wc)
+MODES = [dict(tiles_per_wave=tpw, tail_pct=tail, interleave=ilv, wave_claims=wc, blocks_per_cu=0 if ilv == wc else 2)
          for tpw in (1, 3) for tail in (0, 25) for ilv in (0, 1) for wc in (0, 1)]
 
 
@@ -27,7 +28,8 @@ def _forget_choices():
 
 
 def mode_id(m):
-    return f"tpw{m['tiles_per_wave']}-tail{m['tail_pct']}-ilv{m['interleave']}-wc{m['wave_claims']}"
+    return (f"tpw{m['tiles_per_wave']}-tail{m['tail_pct']}-ilv{m['interleave']}-wc{m['wave_claims']}"
+            f"-bpc{m['blocks_per_cu']}")
 
 
 @pytest.mark.parametrize("mode", MODES, ids=mode_id)
