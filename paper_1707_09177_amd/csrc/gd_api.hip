@@ -669,10 +669,10 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
         std::memset(&I, 0, sizeof I);
         I.ndim = d.ndim;
         I.vw = (al && d.n[0] % vm == 0 && d.n[0] >= vm) ? vm : 1;
-        I.R = 1;
-        if (I.ndim != tab[0].ndim || I.vw != tab[0].vw) same = false;
+        I.R = (I.ndim == 3 && mixed_variant_ok(tsize, 3, I.vw, 2) && d.n[1] >= 2) ? 2 : 1;
+        if (I.ndim != tab[0].ndim || I.vw != tab[0].vw || I.R != tab[0].R) same = false;
     }
-    const int variant = (same && tab[0].vw == vm) ? kTableBit + var_code(tab[0].ndim, vm, 1) : VAR_ALL;
+    const int variant = (same && tab[0].vw == vm) ? kTableBit + var_code(tab[0].ndim, vm, tab[0].R) : VAR_ALL;
     TuneCfg cfg;
     if (force) cfg = *force;
     else tune_lookup(key_batch(solver, dtype, list, count), &cfg);
@@ -764,7 +764,7 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
     if (rc == GD_OK) {
         g_last_launch.variant = variant;
         g_last_launch.vw = same ? tab[0].vw : 0;
-        g_last_launch.R = 1;
+        g_last_launch.R = same ? tab[0].R : 0;
         g_last_launch.L = count == 1 ? tab[0].geo.L : 0;
     }
     return rc;

@@ -215,10 +215,13 @@ __host__ __device__ constexpr bool variant_ok(int tsize, int ndim, int vw, int R
     if (vw == vm) return R == 1 || R == 2;
     return vw == 1 && (R == 4 || R == 1);
 }
-// Shapes the VAR_ALL kernel (uneven batches) can run.
+// Shapes the VAR_ALL kernel (uneven batches) can run: one-row tiles, and in
+// FP32 two-row 3D tiles of 16-byte lanes (their registers fit the two waves
+// per SIMD the batch kernels run at; in FP64 they would not).
 __host__ __device__ constexpr bool mixed_variant_ok(int tsize, int ndim, int vw, int R) {
     const int vm = 16 / tsize;
     if (ndim == 2) return R == 1 && (vw == vm || vw == 1);
+    if (tsize == 4 && vw == vm && R == 2) return true;
     return (vw == vm || vw == 1) && R == 1;
 }
 

@@ -101,7 +101,12 @@ __device__ __forceinline__ void with_variant(const Inst &I, F &&f) {
             if (I.vw == VM) f.template operator()<2, VM, 1>();
             else f.template operator()<2, 1, 1>();
         } else if (I.vw == VM) {
-            f.template operator()<3, VM, 1>();
+            if constexpr (mixed_variant_ok((int)sizeof(T), 3, VM, 2)) {
+                if (I.R == 2) f.template operator()<3, VM, 2>();
+                else f.template operator()<3, VM, 1>();
+            } else {
+                f.template operator()<3, VM, 1>();
+            }
         } else {
             f.template operator()<3, 1, 1>();
         }
