@@ -236,7 +236,8 @@ Geo make_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int vw, int R, int64_
         g.plane = nx * ny;
         g.nrs = (ny + R - 1) / R;
     }
-    g.nxs = (nx + (int64_t)WAVE * vw - 1) / ((int64_t)WAVE * vw);
+    const int64_t tc = ndim == 3 ? tile_cols(vw, R) : (int64_t)WAVE * vw;  // x columns per tile
+    g.nxs = (nx + tc - 1) / tc;
     g.L = L;
     const int64_t cols = g.nxs * g.nrs;
     const int64_t L2 = std::max<int64_t>(kMinL, L / 4);

@@ -102,8 +102,17 @@ struct Geo {
 
 template <int N> struct Arr { static constexpr int n = N > 0 ? N : 1; };
 
-// Tile position of a lane.  seg0 (the wave's first column), row0, m0 and m1
-// are the same in every lane of the wave.
+// Lane rows of a tile: a 3D tile of 16-byte lanes and R = 4 rows is two
+// half-waves of 32 lanes stacked in y, each lane holding two rows (the rows
+// between the halves are passed across instead of loaded twice); every other
+// tile is one row of 64 lanes, each lane holding R rows.
+__host__ __device__ constexpr int tile_lane_rows(int vw, int R) { return (vw > 1 && R == 4) ? 2 : 1; }
+// x columns a tile spans
+__host__ __device__ constexpr int tile_cols(int vw, int R) { return WAVE / tile_lane_rows(vw, R) * vw; }
+
+// Tile position of a lane.  seg0 (the tile's first column), m0 and m1 are
+// the same in every lane of the wave; so is row0 (the lane's first row) in a
+// one-lane-row tile.
 struct TilePos {
     int64_t x0, xc, xl, xr, seg0, row0, m0, m1;
     bool act;
@@ -128,13 +137,15 @@ __device__ __forceinline__ TilePos tile_pos(const Geo &g, int64_t lt, int lane) 
     p.m1 = mend < g.nmarch ? mend : g.nmarch;
     const int64_t xs = c % g.nxs;
     const int64_t rs = c / g.nxs;
-    p.seg0 = xs * (WAVE * VW);
-    p.x0 = p.seg0 + (int64_t)lane * VW;
+    constexpr int LY = tile_lane_rows(VW, R), LX = WAVE / LY;
+    const int lx = lane & (LX - 1), ly = lane / LX;
+    p.seg0 = xs * (LX * VW);
+    p.x0 = p.seg0 + (int64_t)lx * VW;
     p.act = p.x0 < g.nx;
     p.xc = p.act ? p.x0 : g.nx - VW;  // a valid column for inactive lanes
     p.xl = p.xc == 0 ? g.nx - 1 : p.xc - 1;
     p.xr = (p.xc + VW >= g.nx) ? p.xc + VW - g.nx : p.xc + VW;
-    p.row0 = rs * R;
+    p.row0 = rs * R + ly * (R / LY);
     return p;
 }
 
@@ -431,6 +442,160 @@ __device__ __forceinline__ void march_slab(const Geo &g, int64_t lt, const Op &o
     }
 }
 
+// 3D march of a two-lane-row tile (16-byte lanes, R = 4): lanes 0-31 hold
+// rows row0, row0 + 1 of 32 x-segments and lanes 32-63 the next two rows.
+// Each lane loads its two rows and one more: the row above the tile (lower
+// half) or the row below it (upper half); the rows between the halves cross
+// by a lane exchange (lane i <-> i ^ 32) of x-filtered values.  So a lane
+// loads 3 rows per 2 output rows (the one-lane-row tile of R = 2: 4).
+// x neighbours cross lanes by DPP within each half.  Must be called by the
+// whole wave.
+template <int VW, typename T, typename C, class Op>
+__device__ __forceinline__ void march_pair(const Geo &g, int64_t lt, const Op &op, double (&acc)[NACC], int lane) {
+    constexpr int R = 4, RY = 2, LX = WAVE / 2;
+    constexpr int NI = Arr<Op::NI>::n;
+    constexpr int NO = Arr<Op::NO>::n;
+    const TilePos p = tile_pos<VW, R>(g, lt, lane);
+    const int lx = lane & (LX - 1);
+    const bool upper = lane >= LX;
+    const int64_t nx = g.nx;
+    auto wrow = [&](int64_t row) -> int64_t {
+        row %= g.nrows;
+        return row < 0 ? row + g.nrows : row;
+    };
+    // rows a lane loads: its own two (periodically wrapped: a row past the
+    // field's end is a neighbour's halo, not an output) and the extra one
+    int64_t rowoff[3];
+    rowoff[0] = wrow(p.row0) * nx;
+    rowoff[1] = wrow(p.row0 + 1) * nx;
+    rowoff[2] = wrow(upper ? p.row0 + 2 : p.row0 - 1) * nx;
+
+    // a half's x span: lanes 0 .. last of the half hold field points; the
+    // periodic neighbours outside it are loaded by the half's lane 0 (left)
+    // and by its lane last + 1, or last = 31 on a full span (right)
+    const int64_t seg0 = p.seg0;
+    const int64_t nseg = nx - seg0 < (int64_t)LX * VW ? nx - seg0 : (int64_t)LX * VW;
+    const int last = (int)(nseg / VW) - 1;
+    const bool full = last == LX - 1;
+    const int redge = full ? last : last + 1;
+    const int64_t xleft = seg0 == 0 ? nx - 1 : seg0 - 1;
+    const int64_t xright = seg0 + nseg >= nx ? seg0 + nseg - nx : seg0 + nseg;
+    const int64_t xe = lx == 0 ? xleft : (lx == redge ? xright : p.xc);
+
+    auto wrapm = [&](int64_t m) -> int64_t { return m < 0 ? m + g.nmarch : (m >= g.nmarch ? m - g.nmarch : m); };
+    uint32_t vo[3], eo[3];
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+        vo[h] = (uint32_t)((rowoff[h] + p.xc) * (int64_t)sizeof(T));
+        eo[h] = (uint32_t)((rowoff[h] + xe) * (int64_t)sizeof(T));
+    }
+
+    T raw[3][NI][VW], rawe[3][NI];
+    auto load_in = [&](int64_t mw) {
+#pragma unroll
+        for (int f = 0; f < Op::NI; ++f) {
+            const T *pb = op.in[f] + mw * g.plane;
+#pragma unroll
+            for (int h = 0; h < 3; ++h) {
+                vld<T, VW>(at_off(pb, vo[h]), raw[h][f]);
+                rawe[h][f] = *at_off(pb, eo[h]);
+            }
+        }
+    };
+    T co[RY][NO][VW];
+    auto load_out = [&](int64_t m) {
+#pragma unroll
+        for (int f = 0; f < Op::NO; ++f) {
+            const T *pb = op.oin[f] + m * g.plane;
+#pragma unroll
+            for (int r = 0; r < RY; ++r) vld_nt<T, VW>(at_off(pb, vo[r]), co[r][f]);
+        }
+    };
+
+    C W0[RY][VW], W1[RY][VW], W2[RY][VW], S1[RY][VW];
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int k = 0; k < VW; ++k) W0[r][k] = W1[r][k] = W2[r][k] = S1[r][k] = C(0);
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int f = 0; f < NO; ++f)
+#pragma unroll
+            for (int k = 0; k < VW; ++k) co[r][f][k] = T(0);
+
+    load_in(wrapm(p.m0 - 1));
+    for (int64_t m = p.m0 - 1; m <= p.m1; ++m) {
+        C sm[3][VW], se[3], sr[3];
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+#pragma unroll
+            for (int k = 0; k < VW; ++k) {
+                T a[NI];
+#pragma unroll
+                for (int f = 0; f < NI; ++f) a[f] = raw[h][f][k];
+                sm[h][k] = op.mix(a);
+            }
+            se[h] = op.mix(rawe[h]);
+            sr[h] = full ? se[h] : dpp_shift<kDppWaveShl1>(se[h]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        load_in(wrapm(m < p.m1 ? m + 1 : m));
+
+        // x-filter the three rows (DPP across the whole wave; the halves'
+        // edge lanes take their own loads instead)
+        C hx[3][VW];
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+            C left = dpp_shift<kDppWaveShr1>(sm[h][VW - 1]);
+            C right = dpp_shift<kDppWaveShl1>(sm[h][0]);
+            if (lx == 0) left = se[h];
+            if (lx == last) right = sr[h];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) {
+                const C l = k == 0 ? left : sm[h][k - 1];
+                const C rr = k == VW - 1 ? right : sm[h][k + 1];
+                hx[h][k] = C(0.5) * sm[h][k] + C(0.25) * (l + rr);
+            }
+        }
+        // the row below own row 1 (lower half) is the upper half's own row 0;
+        // the row above own row 0 (upper half) is the lower half's own row 1
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+            const C send = upper ? hx[0][k] : hx[1][k];
+            const C recv = __shfl_xor(send, LX, WAVE);
+            const C above0 = upper ? recv : hx[2][k];
+            const C below1 = upper ? hx[2][k] : recv;
+            W0[0][k] = W1[0][k];
+            W1[0][k] = W2[0][k];
+            W2[0][k] = C(0.5) * hx[0][k] + C(0.25) * (above0 + hx[1][k]);
+            W0[1][k] = W1[1][k];
+            W1[1][k] = W2[1][k];
+            W2[1][k] = C(0.5) * hx[1][k] + C(0.25) * (hx[0][k] + below1);
+        }
+        C gv[RY][VW];
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int k = 0; k < VW; ++k) gv[r][k] = C(0.5) * W1[r][k] + C(0.25) * (W0[r][k] + W2[r][k]);
+        // output plane m - 1 (its centre fields were loaded one step ago)
+        if (m > p.m0) {
+            const int64_t mo = m - 1;
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                if (p.act && p.row0 + r < g.nrows)
+                    op.out(mo * g.plane + (p.row0 + r) * nx + p.x0, S1[r], gv[r], co[r], acc);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+            for (int k = 0; k < VW; ++k) S1[r][k] = sm[r][k];
+        __builtin_amdgcn_sched_barrier(0);
+        load_out(m < p.m0 ? p.m0 : (m < p.m1 ? m : p.m1 - 1));
+    }
+}
+
 // March one tile with the separable stencil.
 //   Op::NI stencil-input fields op.in[f]; op.mix(v[NI]) forms S at a point
 //   Op::NO centre-only fields op.oin[f], loaded for every output point
@@ -442,6 +607,8 @@ __device__ __forceinline__ void march_tile(const Geo &g, int64_t lt, const Op &o
     static_assert(NDIM == 3 || R == 1, "2D tiles are one row wide");
     if constexpr (NDIM == 2)
         march_row<VW, T, C>(g, lt, op, acc, lane);
+    else if constexpr (tile_lane_rows(VW, R) == 2)
+        march_pair<VW, T, C>(g, lt, op, acc, lane);
     else
         march_slab<VW, R, T, C>(g, lt, op, acc, lane);
 }
@@ -455,9 +622,10 @@ __device__ __forceinline__ void point_tile(const Geo &g, int64_t lt, const Op &o
     C zero[VW];
 #pragma unroll
     for (int k = 0; k < VW; ++k) zero[k] = C(0);
+    constexpr int RY = R / tile_lane_rows(VW, R);  // rows per lane
     for (int64_t m = p.m0; m < p.m1; ++m)
 #pragma unroll
-        for (int r = 0; r < R; ++r)
+        for (int r = 0; r < RY; ++r)
             if (NDIM == 2 || p.row0 + r < g.nrows) {
                 const int64_t i = m * g.plane + (p.row0 + r) * g.nx + p.x0;
                 T o[NO][VW];

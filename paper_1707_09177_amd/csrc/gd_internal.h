@@ -207,12 +207,13 @@ int64_t balanced_L(int64_t nmarch, int64_t cols, int64_t waves);
 TileShape choose_tiles(int ndim, int64_t nx, int64_t ny, int64_t nz, int64_t batch, int tsize, bool aligned,
                        int solver, bool mixed);
 // Tile shapes compiled into the single-shape kernels: 2D lanes of 16 bytes or
-// of one element; 3D lanes of 16 bytes with 1 or 2 rows per tile, or of one
-// element with 4 or 1 rows (fewer registers per row).
+// of one element; 3D lanes of 16 bytes with 1, 2 or 4 rows per tile (4: two
+// half-wave lane rows of two rows each), or of one element with 4 or 1 rows
+// (fewer registers per row).
 __host__ __device__ constexpr bool variant_ok(int tsize, int ndim, int vw, int R) {
     const int vm = 16 / tsize;
     if (ndim == 2) return R == 1 && (vw == vm || vw == 1);
-    if (vw == vm) return R == 1 || R == 2;
+    if (vw == vm) return R == 1 || R == 2 || R == 4;
     return vw == 1 && (R == 4 || R == 1);
 }
 // Shapes the VAR_ALL kernel (uneven batches) can run: one-row tiles, and in

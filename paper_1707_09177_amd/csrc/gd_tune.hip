@@ -36,7 +36,8 @@ TileShape choose_tiles(int ndim, int64_t nx, int64_t ny, int64_t nz, int64_t bat
 }
 
 int64_t tiles_per_plane(int ndim, int64_t nx, int64_t ny, int vw, int R) {
-    const int64_t nxs = (nx + 64 * vw - 1) / (64 * vw);
+    const int64_t tc = ndim == 3 ? tile_cols(vw, R) : 64 * vw;  // x columns per tile
+    const int64_t nxs = (nx + tc - 1) / tc;
     return ndim == 2 ? nxs : nxs * ((ny + R - 1) / R);
 }
 
