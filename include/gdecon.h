@@ -266,6 +266,12 @@ typedef struct gd_tune_info {
                                 workgroup claims tiles for its four waves */
     int32_t blocks_per_cu;   /* chosen workgroups per CU of the persistent grid
                                 (0 = as many as fit; at most 16) */
+    int32_t segments;        /* chosen long tiles per column along the march
+                                axis (1 .. 64), whatever the wave count; 0 =
+                                as many as keep every resident wave busy.
+                                Uniform solves only (uneven batches ignore
+                                it); the tuner tries it for 3D fields. */
+    int32_t pad;
     double best_ms;          /* trial time of the chosen configuration */
     double default_ms;       /* trial time of the untuned default */
 } gd_tune_info;
@@ -279,7 +285,7 @@ int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *
  * reproducible runs): later solves with the same solver, grid and pointer
  * alignment (the alignment of ubar and u decides the lane width), or the same
  * instance list, use `choice` (its tiles_per_wave, rows, tail_pct,
- * interleave, wave_claims and blocks_per_cu; the timing fields are ignored).  Also written to the
+ * interleave, wave_claims, blocks_per_cu and segments; the timing fields are ignored).  Also written to the
  * GD_TUNE_CACHE file when it is set.  Errors: GD_EINVAL. */
 int gd_tune_set(int32_t solver, const gd_grid *grid, const void *ubar, const void *u, const gd_tune_info *choice);
 int gd_tune_set_batch(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count,

@@ -365,10 +365,11 @@ void tune_load_locked() {
     char line[1024];
     while (fgets(line, sizeof line, fp)) {
         char key[900];
-        int tpw = 0, rows = 0, tail = 0, ilv = 0, wc = 0, bpc = kBlocksPerCu;
-        const int nf = sscanf(line, "%899s %d %d %d %d %d %d", key, &tpw, &rows, &tail, &ilv, &wc, &bpc);
-        if ((nf == 6 || nf == 7) && tpw >= 1 && tpw <= 64 && rows >= 0 && rows <= 4 && tail >= 0 && tail <= 50 &&
-            (ilv == 0 || ilv == 1) && (wc == 0 || wc == 1) && bpc >= 0 && bpc <= kMaxBlocksPerCu) {
+        int tpw = 0, rows = 0, tail = 0, ilv = 0, wc = 0, bpc = kBlocksPerCu, segs = 0;
+        const int nf = sscanf(line, "%899s %d %d %d %d %d %d %d", key, &tpw, &rows, &tail, &ilv, &wc, &bpc, &segs);
+        if (nf >= 6 && tpw >= 1 && tpw <= 64 && rows >= 0 && rows <= 4 && tail >= 0 && tail <= 50 &&
+            (ilv == 0 || ilv == 1) && (wc == 0 || wc == 1) && bpc >= 0 && bpc <= kMaxBlocksPerCu && segs >= 0 &&
+            segs <= kMaxSegs) {
             TuneCfg c;
             c.tpw = tpw;
             c.rows = rows;
@@ -376,6 +377,7 @@ void tune_load_locked() {
             c.ilv = ilv;
             c.wc = wc;
             c.bpc = bpc;
+            c.segs = segs;
             g_tune[key] = c;
         }
     }
@@ -397,7 +399,7 @@ void tune_store(const std::string &key, const TuneCfg &c) {
     g_tune[key] = c;
     if (const char *f = tune_file()) {
         if (FILE *fp = fopen(f, "a")) {
-            fprintf(fp, "%s %d %d %d %d %d %d\n", key.c_str(), c.tpw, c.rows, c.tail, c.ilv, c.wc, c.bpc);
+            fprintf(fp, "%s %d %d %d %d %d %d %d\n", key.c_str(), c.tpw, c.rows, c.tail, c.ilv, c.wc, c.bpc, c.segs);
             fclose(fp);
         }
     }
@@ -460,6 +462,10 @@ int solve_uniform(int solver, const gd_grid *g, const void *ubar, void *u, const
     // march length balanced over the waves the persistent grid will hold
     ts.L = balanced_L(g->ndim == 2 ? ny : nz, g->batch * tiles_per_plane(g->ndim, nx, ny, ts.vw, ts.R),
                       blocks_cap * WPB * std::max(1, cfg.tpw));
+    if (cfg.segs > 0) {  // a fixed number of long tiles per column
+        const int64_t nm = g->ndim == 2 ? ny : nz;
+        ts.L = std::min<int64_t>(kMaxL, std::max<int64_t>(kMinL, (nm + cfg.segs - 1) / cfg.segs));
+    }
 
     Params P;
     std::memset(&P, 0, sizeof P);
@@ -847,6 +853,7 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
         out->interleave = cands[best].ilv;
         out->wave_claims = cands[best].wc;
         out->blocks_per_cu = cands[best].bpc;
+        out->segments = cands[best].segs;
         out->best_ms = best_ms;
         out->default_ms = std::min(default_first, t.empty() ? 0.0 : t[0]);
     }
@@ -895,6 +902,22 @@ int tune_uniform(int solver, const gd_grid *g, const void *ubar, void *u, void *
                             c.bpc = bp;
                             cands.push_back(c);
                         }
+    // 3D stencil sweeps: a few long tiles per column, all marching the same
+    // plane ranges, even where that leaves CUs idle (3 x 256^3 FP32
+    // BiCGSTAB: two tiles per column on 192 workgroups, 5.19 ms, against
+    // 5.30 ms for the wave-count rule's 52-plane tiles on 480)
+    if (g->ndim == 3 && !spec)
+        for (int bp : {kBlocksPerCu, 1})
+            for (int r : rows)
+                for (int sg = 1; sg <= 4; ++sg) {
+                    TuneCfg c;
+                    c.tpw = 1;
+                    c.rows = r;
+                    c.tail = 0;
+                    c.bpc = bp;
+                    c.segs = sg;
+                    cands.push_back(c);
+                }
     // every candidate must launch; a shape the field cannot use falls back to
     // the default rule inside solve_uniform, so duplicates are harmless
     auto launch = [&](const TuneCfg &c) {
@@ -1066,7 +1089,7 @@ static int tune_choice(const gd_tune_info *c, TuneCfg *cfg) {
     if (!c) return fail(GD_EINVAL, "choice is NULL");
     if (c->tiles_per_wave < 1 || c->tiles_per_wave > 64 || c->rows < 0 || c->rows > 4 || c->tail_pct < 0 ||
         c->tail_pct > 50 || (c->interleave != 0 && c->interleave != 1) || (c->wave_claims != 0 && c->wave_claims != 1) ||
-        c->blocks_per_cu < 0 || c->blocks_per_cu > kMaxBlocksPerCu)
+        c->blocks_per_cu < 0 || c->blocks_per_cu > kMaxBlocksPerCu || c->segments < 0 || c->segments > kMaxSegs)
         return fail(GD_EINVAL, "launch configuration out of range");
     cfg->tpw = c->tiles_per_wave;
     cfg->rows = c->rows;
@@ -1074,6 +1097,7 @@ static int tune_choice(const gd_tune_info *c, TuneCfg *cfg) {
     cfg->ilv = c->interleave;
     cfg->wc = c->wave_claims;
     cfg->bpc = c->blocks_per_cu;
+    cfg->segs = c->segments;
     return GD_OK;
 }
 

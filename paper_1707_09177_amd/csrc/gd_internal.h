@@ -141,6 +141,8 @@ constexpr int kTailPct = 15;
 // most 3D and uneven-batch kernels fit two anyway.
 constexpr int kBlocksPerCu = 2;
 constexpr int kMaxBlocksPerCu = 16;
+// Largest tiles-per-column choice a launch configuration may pin.
+constexpr int kMaxSegs = 64;
 
 struct Params {
     Inst tmpl;            // uniform batch: instance 0 (others offset by stride)
@@ -171,7 +173,8 @@ struct Params {
 
 // Launch configuration the autotuner chooses between: target tiles per
 // resident wave (tile granularity) and, for 3D fields in the uniform kernels,
-// rows per tile (0 = the default rule).
+// rows per tile (0 = the default rule) and tiles per column along the march
+// axis (0 = the wave-count rule).
 struct TuneCfg {
     int tpw = kTilesPerWave;
     int rows = 0;
@@ -179,6 +182,7 @@ struct TuneCfg {
     int ilv = 0;  // interleaved tile pools
     int wc = 0;   // per-wave tile claims
     int bpc = kBlocksPerCu;  // workgroups per CU (0: as many as fit)
+    int segs = 0;  // > 0: every column is cut into this many long tiles, whatever the wave count
 };
 
 // A solve on a stored Fourier spectrum (the differential filter); hw is the

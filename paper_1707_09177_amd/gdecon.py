@@ -64,6 +64,7 @@ class TuneInfo(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int32), ("best", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32),
                 ("rows", ctypes.c_int32), ("tail_pct", ctypes.c_int32), ("interleave", ctypes.c_int32),
                 ("wave_claims", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("segments", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
@@ -487,7 +488,8 @@ def _make_opts(max_iter, tol, init, norm_ref, history, wait_limit_us, max_replac
 
 
 def _tune_dict(t: TuneInfo) -> dict:
-    return {k: (float(getattr(t, k)) if k.endswith("_ms") else int(getattr(t, k))) for k, _ in TuneInfo._fields_}
+    return {k: (float(getattr(t, k)) if k.endswith("_ms") else int(getattr(t, k))) for k, _ in TuneInfo._fields_
+            if k != "pad"}
 
 
 def autotune(solver: str, ubar: torch.Tensor, ndim: int = 2, out: torch.Tensor | None = None, stream=None) -> dict:
@@ -503,11 +505,13 @@ def autotune(solver: str, ubar: torch.Tensor, ndim: int = 2, out: torch.Tensor |
     return _tune_dict(t)
 
 
-def _choice(tiles_per_wave=2, rows=0, tail_pct=0, interleave=0, wave_claims=0, blocks_per_cu=2) -> TuneInfo:
+def _choice(tiles_per_wave=2, rows=0, tail_pct=0, interleave=0, wave_claims=0, blocks_per_cu=2,
+            segments=0) -> TuneInfo:
     t = TuneInfo()
     t.tiles_per_wave, t.rows, t.tail_pct, t.interleave, t.wave_claims = (int(tiles_per_wave), int(rows), int(tail_pct),
                                                                          int(interleave), int(wave_claims))
     t.blocks_per_cu = int(blocks_per_cu)
+    t.segments = int(segments)
     return t
 
 
@@ -515,7 +519,8 @@ def tune_set(solver: str, ubar: torch.Tensor, out: torch.Tensor, ndim: int = 2, 
     """Pin the launch configuration for solves of `solver` on fields shaped
     like ubar whose input and output are aligned like ubar and out
     (gd_tune_set).  choice: tiles_per_wave, rows, tail_pct, interleave,
-    wave_claims, blocks_per_cu (0: as many workgroups per CU as fit)."""
+    wave_claims, blocks_per_cu (0: as many workgroups per CU as fit),
+    segments (> 0: that many long tiles per column along the march axis)."""
     g = make_grid(ubar.shape, ndim, ubar.dtype)
     t = _choice(**choice)
     _check(load().gd_tune_set(SOLVERS[solver], ctypes.byref(g), _dev_ptr(ubar), _dev_ptr(out), ctypes.byref(t)))

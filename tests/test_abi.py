@@ -134,6 +134,11 @@ def test_tune_set_validates_choices():
     for bpc in (-1, 17):
         bad = gdecon._choice(blocks_per_cu=bpc)
         assert lib.gd_tune_set(2, ctypes.byref(g), 256, 512, ctypes.byref(bad)) == -1
+    for segs in (-1, 65):
+        bad = gdecon._choice(segments=segs)
+        assert lib.gd_tune_set(2, ctypes.byref(g), 256, 512, ctypes.byref(bad)) == -1
+    assert lib.gd_tune_set(2, ctypes.byref(g), 256, 512, ctypes.byref(gdecon._choice(segments=64))) == 0
+    lib.gd_tune_reset()
     assert lib.gd_tune_set(7, ctypes.byref(g), 256, 512, ctypes.byref(gdecon._choice())) == -1
 
 

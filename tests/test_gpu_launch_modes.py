@@ -1,8 +1,9 @@
 """Every launch configuration the autotuner can choose gives the same answer.
 
 Each case pins one configuration (gd_tune_set / gd_tune_set_batch): tile
-granularity, short tail tiles, interleaved pools, per-wave claims and
-workgroups per CU (two, or as many as fit).  It then
+granularity, short tail tiles, interleaved pools, per-wave claims,
+workgroups per CU (one, two, or as many as fit), and in 3D a fixed number
+of long tiles per column (whatever the wave count).  It then
 checks the solve against the CPU FP64 oracle: relative L2 <= 1e-10 in FP64
 and equal pass counts.  Configurations only change which wave handles which
 tile and how the partial sums are split, never what is computed.
@@ -66,3 +67,27 @@ def test_batch_modes_match_oracle(mode):
         want, winfo, _ = oracle.solve("bicgstab", ub, ub.ndim, 5)
         assert infos[i]["iters"] == winfo[0]["iters"]
         assert rel_l2(outs[i].cpu().numpy(), want) <= 1e-10, (i, shapes[i])
+
+
+@pytest.mark.parametrize("segments", [1, 2, 3, 5])
+@pytest.mark.parametrize("rows", [0, 1, 2, 4])
+@pytest.mark.parametrize("shape", [(2, 20, 24, 36), (3, 9, 8, 132), (1, 41, 13, 260)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_tiles_per_column_match_oracle(segments, rows, shape):
+    """3D columns cut into a fixed number of long tiles (the last one
+    ragged, or below the minimum tile length) with one or two workgroups
+    per CU."""
+    u = np.random.default_rng(segments + 7 * rows + sum(shape)).standard_normal(shape)
+    ub = oracle.filter(u, 3)
+    N = 4
+    want, winfo, _ = oracle.solve("bicgstab", ub, 3, N)
+    ubt = to_dev(ub, torch.float64)
+    out = torch.empty_like(ubt)
+    gdecon.tune_set("bicgstab", ubt, out, ndim=3, tiles_per_wave=1, rows=rows, tail_pct=0,
+                    blocks_per_cu=1 + segments % 2, segments=segments)
+    res = gdecon.Deconvolver(ubt.shape, 3, ubt.dtype, "bicgstab").solve(ubt, N, 0.0, out=out)
+    nz = shape[1]
+    assert gdecon.last_launch()["L"] == max(8, -(-nz // segments))
+    for gi, wi in zip(res.info(), winfo):
+        assert gi["iters"] == wi["iters"]
+    assert rel_l2(out.cpu().numpy(), want) <= 1e-10
