@@ -412,16 +412,61 @@ def main_closure(args, w, torch, gd, dev):
     print(json.dumps(out))
 
 
+def germano_inputs(w, torch, gd, dev):
+    """The workload's fields (FP32, host) and their differential-filter images (device)."""
+    from paper_1707_09177_amd import synth
+    u = synth.config_fields(w["cfg"], n=w["n"], count=w["count"], dtype=np.float32)
+    ut = torch.from_numpy(u).to(dev)
+    ubar = gd.germano_filter(ut, w["gamma"], ndim=w["ndim"])
+    torch.cuda.synchronize()
+    del ut
+    return u, ubar
+
+
+def germano_result(gd, torch, ubar, w, s, steps, warmup, tune, dev):
+    """One solver with the differential filter, whole call (forward FFT, solve
+    on the coefficients, inverse FFT) to the workload's tolerance: time,
+    passes, and the call's algorithmic bytes per second."""
+    nd, gamma, tol = w["ndim"], w["gamma"], w["tol"]
+    npts = int(ubar.numel())
+    stream = torch.cuda.current_stream()
+    d = gd.GermanoDeconvolver(ubar.shape, nd, ubar.dtype, s, gamma, device=dev)
+    out = torch.empty_like(ubar)
+    tuned = d.autotune(ubar, out) if tune else None   # untimed
+    reps = steps if s == "bicgstab" else max(2, steps // (10 if s in ("vc", "sd") else 2))
+    for _ in range(warmup):
+        d.solve(ubar, 5000, tol, out=out)
+    torch.cuda.synchronize()
+    info = d.solve(ubar, 5000, tol, out=out).info()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record(stream)
+        d.solve(ubar, 5000, tol, out=out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    iters = [i["iters"] for i in info]
+    # the stored half spectrum the solve kernel sweeps: 2 (n_x/2 + 1) reals per row, padded to 16 bytes
+    nxs = (2 * (w["n"] // 2 + 1) + 3) // 4 * 4
+    spec_pts = npts // w["n"] * nxs
+    algo = spec_pts * 4 * accesses(s, max(iters))
+    # whole call: forward FFT (real rows in, spectrum out, then each column axis
+    # read and written), the solve on the spectrum, and the inverse FFT in reverse
+    call_bytes = algo + 2 * npts * 4 + (6 if nd == 2 else 10) * spec_pts * 4
+    launch = gd.last_launch()
+    return dict(ms=ms, iters=sorted(set(iters)), status=sorted({i["status_name"] for i in info}),
+                worst_true_rel_residual=max(i["r_true"] / i["r_ref"] for i in info),
+                points_per_s=npts / (ms * 1e-3), solve_kernel_bytes=algo, call_bytes=call_bytes,
+                call_GBs=call_bytes / (ms * 1e-3) / 1e9, call_hbm_frac=call_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                launch=launch, tune=tuned)
+
+
 def main_germano(args, w, torch, gd, dev):
     """Time Algorithms 1-4 with the paper's differential filter to 99 % residual
     reduction (whole call: forward FFT, solve on the coefficients, inverse FFT)."""
     nd, gamma, tol = w["ndim"], w["gamma"], w["tol"]
-    from paper_1707_09177_amd import synth
-    u = synth.config_fields(w["cfg"], n=w["n"], count=w["count"], dtype=np.float32)
-    ut = torch.from_numpy(u).to(dev)
-    ubar = gd.germano_filter(ut, gamma, ndim=nd)
-    torch.cuda.synchronize()
-    del ut
+    u, ubar = germano_inputs(w, torch, gd, dev)
     npts = int(ubar.numel())
     stream = torch.cuda.current_stream()
     if args.tune_only:
@@ -429,38 +474,8 @@ def main_germano(args, w, torch, gd, dev):
             d = gd.GermanoDeconvolver(ubar.shape, nd, ubar.dtype, s, gamma, device=dev)
             print(json.dumps({"solver": s, "tune": d.autotune(ubar)}))
         return
-    results = {}
-    for s in args.solvers.split(","):
-        d = gd.GermanoDeconvolver(ubar.shape, nd, ubar.dtype, s, gamma, device=dev)
-        out = torch.empty_like(ubar)
-        tuned = d.autotune(ubar, out) if not args.no_tune else None   # untimed
-        reps = args.steps if s == "bicgstab" else max(2, args.steps // (10 if s in ("vc", "sd") else 2))
-        for _ in range(args.warmup):
-            d.solve(ubar, 5000, tol, out=out)
-        torch.cuda.synchronize()
-        info = d.solve(ubar, 5000, tol, out=out).info()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-        torch.cuda.synchronize()
-        for a, b in evs:
-            a.record(stream)
-            d.solve(ubar, 5000, tol, out=out)
-            b.record(stream)
-        torch.cuda.synchronize()
-        ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-        iters = [i["iters"] for i in info]
-        # the stored half spectrum the solve kernel sweeps: 2 (n_x/2 + 1) reals per row, padded to 16 bytes
-        nxs = (2 * (w["n"] // 2 + 1) + 3) // 4 * 4
-        spec_pts = npts // w["n"] * nxs
-        algo = spec_pts * 4 * accesses(s, max(iters))
-        # whole call: forward FFT (real rows in, spectrum out, then each column axis
-        # read and written), the solve on the spectrum, and the inverse FFT in reverse
-        call_bytes = algo + 2 * npts * 4 + (6 if nd == 2 else 10) * spec_pts * 4
-        launch = gd.last_launch()
-        results[s] = dict(ms=ms, iters=sorted(set(iters)), status=sorted({i["status_name"] for i in info}),
-                          worst_true_rel_residual=max(i["r_true"] / i["r_ref"] for i in info),
-                          points_per_s=npts / (ms * 1e-3), solve_kernel_bytes=algo, call_bytes=call_bytes,
-                          call_GBs=call_bytes / (ms * 1e-3) / 1e9, launch=launch, tune=tuned)
-        del d, out
+    results = {s: germano_result(gd, torch, ubar, w, s, args.steps, args.warmup, not args.no_tune, dev)
+               for s in args.solvers.split(",")}
     # the paper's spectral assessment (its N = 5 comparison): the highest shell up to
     # which the recovered energy spectrum keeps at least half of the true one
     kpow = -2.0 if nd == 2 else 0.0          # 2D fields are vorticities: kinetic energy is |w_hat|^2 / k^2
@@ -739,23 +754,30 @@ CNN2D_FLOP_PER_POINT = 2 * (9 * 32 + 4 * 9 * 32 * 32 + 9 * 32)
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
-def main_forward(args, w, torch, gd, dev):
-    """The network's 2D forward pass alone (untrained weights: the cost does
-    not depend on them), without the band projection, on the c5 evaluation
-    batch.  roofline: model flops per launch / the fused kernel's duration,
-    against the dense bf16 matrix-core peak."""
+def forward_result(w, torch, gd, dev, steps, warmup):
+    """Time the network's 2D forward call on the c5 evaluation batch: ms,
+    points and model TFLOP/s."""
     from paper_1707_09177_amd import synth
     ev = torch.from_numpy(np.stack([synth.field_2d(w["n"], synth.spectrum_kraichnan, 4.0, w["n"] / 4.0,
                                                    synth.rng_for(5, 50000 + i), np.float32)
                                     for i in range(w["count"])])).to(dev)
     ubar = gd.filter_apply(ev, ndim=2)
+    del ev
     net = gd.WarmStart(synth.cnn_init_params(0))
     u0 = torch.empty_like(ubar)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         net.forward(ubar, out=u0, band=False)
-    ms = event_ms(torch, lambda: net.forward(ubar, out=u0, band=False), args.steps)
+    ms = event_ms(torch, lambda: net.forward(ubar, out=u0, band=False), steps)
     npts = int(ubar.numel())
-    tflops = CNN2D_FLOP_PER_POINT * npts / (ms * 1e-3) / 1e12
+    return ms, npts, CNN2D_FLOP_PER_POINT * npts / (ms * 1e-3) / 1e12
+
+
+def main_forward(args, w, torch, gd, dev):
+    """The network's 2D forward pass alone (untrained weights: the cost does
+    not depend on them), without the band projection, on the c5 evaluation
+    batch.  roofline: model flops per launch / the fused kernel's duration,
+    against the dense bf16 matrix-core peak."""
+    ms, npts, tflops = forward_result(w, torch, gd, dev, args.steps, args.warmup)
     print(json.dumps({"metric": "warm-start network forward points/s; % bf16 MFMA peak", "value": npts / (ms * 1e-3),
                       "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
@@ -978,6 +1000,10 @@ def main():
         out["c3"] = extra_uniform(args, WORKLOADS["c3"], torch, gd, dev)
         torch.cuda.empty_cache()
         out["c4"] = extra_batch(args, WORKLOADS["c4"], torch, gd, dev)
+        torch.cuda.empty_cache()
+        out["germano2d"] = extra_germano(args, WORKLOADS["germano2d"], torch, gd, dev)
+        torch.cuda.empty_cache()
+        out["c5fwd"] = extra_forward(args, WORKLOADS["c5fwd"], torch, gd, dev)
     print(json.dumps(out))
 
 
@@ -1024,6 +1050,24 @@ def extra_batch(args, w, torch, gd, dev):
     return {"workload": w["desc"], "instances": len(shapes), "instances_2d": sum(1 for s in sizes if s[0] == 2),
             "points": npts, "solver": "bicgstab", "points_per_s": r["points_per_s"], "ms": r["ms"],
             "hbm_frac": r["hbm_frac"], "traffic": measured_traffic(w["key"]), **r}
+
+
+def extra_germano(args, w, torch, gd, dev):
+    """BiCGSTAB and Van Cittert with the paper's differential filter (whole
+    call), reported as an extra key."""
+    _, ubar = germano_inputs(w, torch, gd, dev)
+    r = {s: germano_result(gd, torch, ubar, w, s, max(5, args.steps // 2), args.warmup, not args.no_tune, dev)
+         for s in ("bicgstab", "vc")}
+    del ubar
+    return {"workload": w["desc"], "solvers": r, "ms": r["bicgstab"]["ms"],
+            "call_hbm_frac": r["bicgstab"]["call_hbm_frac"], "vs_vancittert": r["vc"]["ms"] / r["bicgstab"]["ms"]}
+
+
+def extra_forward(args, w, torch, gd, dev):
+    """The warm-start network's 2D forward call, reported as an extra key."""
+    ms, npts, tflops = forward_result(w, torch, gd, dev, max(10, args.steps), args.warmup)
+    return {"workload": w["desc"], "points": npts, "ms": ms, "tflops": tflops,
+            "mfma_frac": tflops / MFMA_BF16_PEAK_TFLOPS, "peak_tflops": MFMA_BF16_PEAK_TFLOPS}
 
 
 if __name__ == "__main__":
