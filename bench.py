@@ -160,6 +160,22 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5) -> float:
     return gbs
 
 
+def traffic_rate(traffic, ms):
+    """The measured-traffic roofline figure: HBM bytes per launch (rocprofv3
+    FETCH_SIZE + WRITE_SIZE, committed under profiles/) over the launch's
+    time, and its fraction of the HBM peak; None where no traffic figure
+    matches the current sources."""
+    if not traffic or not ms:
+        return None, None
+    gbs = traffic / (ms * 1e-3) / 1e9
+    return gbs, gbs / HBM_PEAK_GBS
+
+
+def add_traffic_rate(roof: dict, ms) -> dict:
+    roof["traffic_GBs"], roof["traffic_frac"] = traffic_rate(roof.get("traffic"), ms)
+    return roof
+
+
 def add_copy_ceiling(roof: dict, torch) -> dict:
     """Measured copy bandwidth and the kernel's fraction of it, next to the
     vendor-peak fraction (measured after the timed region)."""
@@ -324,13 +340,13 @@ def main_batch(args, w, torch, gd, dev):
         "config": {"workload": w["desc"], "instances": len(shapes),
                    "instances_2d": sum(1 for s in sizes if s[0] == 2), "points": npts, "solver": main_s,
                    "tol": 1e-6},
-        "roofline": add_copy_ceiling({"bound": "hbm", "achieved": m["algorithmic_GBs"], "peak": HBM_PEAK_GBS,
-                                      "unit": "GB/s",
+        "roofline": add_copy_ceiling(add_traffic_rate({"bound": "hbm", "achieved": m["algorithmic_GBs"],
+                                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": m["hbm_frac"],
                      "traffic": measured_traffic(w["key"]) if main_s == "bicgstab" else None,
                      "kernel": f"solve_kernel<float,{main_s}> (one persistent launch per batch solve, "
                                f"captured with its table and prep kernels in one graph)",
-                     "bytes_per_launch": m["algorithmic_bytes"]}, torch),
+                     "bytes_per_launch": m["algorithmic_bytes"]}, m["ms"]), torch),
         "solvers": results,
     }
     if "vc" in results and main_s != "vc":
@@ -387,10 +403,10 @@ def main_closure(args, w, torch, gd, dev):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w["desc"], "velocity_fields": vel.shape[0], "grid": [w["n"]] * nd, "points": npts,
                    "pairs": nd * (nd + 1) // 2},
-        "roofline": add_copy_ceiling({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                      "frac": gbs / HBM_PEAK_GBS,
+        "roofline": add_copy_ceiling(add_traffic_rate({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                                                       "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                      "traffic": measured_traffic(w["key"], CLOSURE_TRAFFIC_FILE, CLOSURE_SOURCES), "kernel": f"k_closure<float,{nd}>",
-                     "bytes_per_launch": algo}, torch),
+                     "bytes_per_launch": algo}, ms_cl), torch),
         "closure_ms_min": ms_cl_min,
         "chain": {"ms": ms_chain, "points_per_s": npts / (ms_chain * 1e-3),
                   "solve_iters": sorted({i["iters"] for i in info}),
@@ -974,15 +990,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["desc"], "fields": w["count"], "grid": [w["n"]] * w["ndim"],
                    "points": npts, "solver": main_s, "tol": 1e-6},
-        "roofline": add_copy_ceiling({"bound": "hbm", "achieved": m["algorithmic_GBs"], "peak": HBM_PEAK_GBS,
-                                      "unit": "GB/s",
+        "roofline": add_copy_ceiling(add_traffic_rate({"bound": "hbm", "achieved": m["algorithmic_GBs"],
+                                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": m["hbm_frac"],
                      "traffic": measured_traffic(w["key"]) if main_s == "bicgstab" else None,
                      "kernel": f"solve_kernel<float,{main_s}> (one persistent launch per solve)",
                      "bytes_per_launch": npts * itemsize * m["accesses_per_point"],
                      "accesses_per_point": m["accesses_per_point"],
                      "kernel_accesses_per_point": m["kernel_accesses_per_point"],
-                     "kernel_frac": m["kernel_hbm_frac"]}, torch),
+                     "kernel_frac": m["kernel_hbm_frac"]}, m["ms"]), torch),
         "iterations": m["iters"][0] if len(set(m["iters"])) == 1 else m["iters"],
         "solvers": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
     }
@@ -1035,8 +1051,10 @@ def extra_uniform(args, w, torch, gd, dev):
     npts, itemsize = int(ubar.numel()), ubar.element_size()
     r = uniform_result(gd, torch, ubar, w, "bicgstab", args.steps, args.warmup, not args.no_tune, npts, itemsize)
     del ubar, u32
+    traffic = measured_traffic(w["key"])
     return {"workload": w["desc"], "points": npts, "solver": "bicgstab", "points_per_s": r["points_per_s"],
-            "ms": r["ms"], "hbm_frac": r["hbm_frac"], "traffic": measured_traffic(w["key"]), **r}
+            "ms": r["ms"], "hbm_frac": r["hbm_frac"], "traffic": traffic,
+            "traffic_frac": traffic_rate(traffic, r["ms"])[1], **r}
 
 
 def extra_batch(args, w, torch, gd, dev):
@@ -1047,9 +1065,10 @@ def extra_batch(args, w, torch, gd, dev):
     r = batch_result(gd, torch, shapes, ubars, "bicgstab", max(5, args.steps // 2), args.warmup, not args.no_tune,
                      npts, ubars[0].element_size(), graph=not args.no_graph)
     del ubars, us
+    traffic = measured_traffic(w["key"])
     return {"workload": w["desc"], "instances": len(shapes), "instances_2d": sum(1 for s in sizes if s[0] == 2),
             "points": npts, "solver": "bicgstab", "points_per_s": r["points_per_s"], "ms": r["ms"],
-            "hbm_frac": r["hbm_frac"], "traffic": measured_traffic(w["key"]), **r}
+            "hbm_frac": r["hbm_frac"], "traffic": traffic, "traffic_frac": traffic_rate(traffic, r["ms"])[1], **r}
 
 
 def extra_germano(args, w, torch, gd, dev):
