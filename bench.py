@@ -1045,16 +1045,26 @@ def uniform_result(gd, torch, ubar, w, s, steps, warmup, tune, npts, itemsize):
                 tune=r["tune"], launch=r["launch"])
 
 
-def extra_uniform(args, w, torch, gd, dev):
-    """BiCGSTAB on a second uniform workload, reported as an extra key."""
+def extra_uniform(args, w, torch, gd, dev, others=("cg", "vc")):
+    """BiCGSTAB on a second uniform workload, reported as an extra key, with
+    CG and Van Cittert on the same fields for the "vs Van Cittert" ratio."""
     u32, ubar = make_inputs(w, torch, gd, dev)
     npts, itemsize = int(ubar.numel()), ubar.element_size()
     r = uniform_result(gd, torch, ubar, w, "bicgstab", args.steps, args.warmup, not args.no_tune, npts, itemsize)
+    rest = {s: uniform_result(gd, torch, ubar, w, s, max(5, args.steps // 2), args.warmup, not args.no_tune, npts,
+                              itemsize) for s in others}
     del ubar, u32
     traffic = measured_traffic(w["key"])
-    return {"workload": w["desc"], "points": npts, "solver": "bicgstab", "points_per_s": r["points_per_s"],
-            "ms": r["ms"], "hbm_frac": r["hbm_frac"], "traffic": traffic,
-            "traffic_frac": traffic_rate(traffic, r["ms"])[1], **r}
+    out = {"workload": w["desc"], "points": npts, "solver": "bicgstab", "points_per_s": r["points_per_s"],
+           "ms": r["ms"], "hbm_frac": r["hbm_frac"], "traffic": traffic,
+           "traffic_frac": traffic_rate(traffic, r["ms"])[1], **r}
+    out["others"] = {s: {k: v[k] for k in ("ms", "iters", "status", "worst_true_rel_residual", "hbm_frac", "tune",
+                                            "launch")} for s, v in rest.items()}
+    if "vc" in rest:
+        out["vs_vancittert"] = rest["vc"]["ms"] / r["ms"]
+        if "cg" in rest:
+            out["cg_vs_vancittert"] = rest["vc"]["ms"] / rest["cg"]["ms"]
+    return out
 
 
 def extra_batch(args, w, torch, gd, dev):

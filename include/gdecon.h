@@ -272,8 +272,10 @@ typedef struct gd_tune_info {
                                 Uniform solves only (uneven batches ignore
                                 it); the tuner tries it for 3D fields. */
     int32_t pad;
-    double best_ms;          /* trial time of the chosen configuration */
-    double default_ms;       /* trial time of the untuned default */
+    double best_ms;          /* trial time of the chosen configuration (the
+                                leaders' round: solves of 8 Krylov or 20 Van
+                                Cittert / steepest-descent passes) */
+    double default_ms;       /* the same trial's time for the untuned default */
 } gd_tune_info;
 
 int deconvolve_autotune(int32_t solver, const gd_grid *grid, const void *ubar, void *u, void *work, size_t work_bytes,

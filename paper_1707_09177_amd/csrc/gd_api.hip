@@ -780,16 +780,19 @@ int solve_batch(int solver, int dtype, const gd_instance *list, int32_t count, c
 // ---- autotuner ---------------------------------------------------------------
 
 // A later candidate must beat the best so far by this fraction: the leaders'
-// times are minima of eight runs, which repeat to about 0.3 %, so 0.5 %
+// times are minima of five runs, which repeat to about 0.3 %, so 0.5 %
 // separates them (a 2 % margin had kept a configuration 1.6 % slower).
 constexpr double kTuneMargin = 0.005;
 
 // Time each candidate with short fixed-length solves (4 Krylov or 10 Van
 // Cittert / steepest-descent passes; one warm-up, then the best of three),
-// then time the four fastest again, round-robin, best of five more each (the
-// first round's noise is of the order of the differences between the leading
-// candidates), and return the index of the fastest; candidate 0 is the
-// untuned default.
+// then time the four fastest again on solves twice as long, round-robin,
+// best of five each, and return the index of the fastest; candidate 0 (the
+// untuned default) is always among them.  The first round's noise is of the
+// order of the differences between the leaders, and the longer solves rank
+// them as full solves do, where init and exit weigh less: 3 x 256^3 BiCGSTAB
+// with two tiles per column trails 52-plane tiles in some 4-pass trials but
+// leads by 2 % in full solves.  launch(cfg, long_trial) runs one trial.
 template <typename Launch>
 int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStream_t stream, gd_tune_info *out) {
     hipEvent_t e0, e1;
@@ -799,9 +802,9 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
         return fail(GD_EHIP, "hipEventCreate failed");
     }
     int rc = GD_OK;
-    auto time_once = [&](size_t c, double &ms_out) -> int {
+    auto time_once = [&](size_t c, bool long_trial, double &ms_out) -> int {
         (void)hipEventRecord(e0, stream);
-        int r = launch(cands[c]);
+        int r = launch(cands[c], long_trial);
         if (r) return r;
         (void)hipEventRecord(e1, stream);
         if (hipEventSynchronize(e1) != hipSuccess) return fail(GD_EHIP, "hipEventSynchronize failed");
@@ -812,13 +815,12 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
     };
     std::vector<double> t(cands.size(), 1e30);
     for (size_t c = 0; c < cands.size() && rc == GD_OK; ++c) {
-        if ((rc = launch(cands[c]))) break;
+        if ((rc = launch(cands[c], false))) break;
         for (int rep = 0; rep < 3 && rc == GD_OK; ++rep) {
             double ms = 0;
-            if ((rc = time_once(c, ms)) == GD_OK) t[c] = std::min(t[c], ms);
+            if ((rc = time_once(c, false, ms)) == GD_OK) t[c] = std::min(t[c], ms);
         }
     }
-    const double default_first = t.empty() ? 0.0 : t[0];
     // second round over the leaders (the default always among them)
     std::vector<size_t> order(cands.size());
     for (size_t c = 0; c < order.size(); ++c) order[c] = c;
@@ -826,11 +828,12 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
     std::vector<size_t> lead(order.begin(), order.begin() + std::min<size_t>(4, order.size()));
     if (std::find(lead.begin(), lead.end(), (size_t)0) == lead.end() && !cands.empty()) lead.push_back(0);
     std::sort(lead.begin(), lead.end());
+    std::vector<double> t2(cands.size(), 1e30);
     for (int rep = 0; rep < 5 && rc == GD_OK; ++rep)
         for (size_t c : lead) {
             double ms = 0;
-            if ((rc = time_once(c, ms))) break;
-            t[c] = std::min(t[c], ms);
+            if ((rc = time_once(c, true, ms))) break;
+            t2[c] = std::min(t2[c], ms);
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -840,9 +843,9 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
     int best = -1;
     double best_ms = 0;
     for (size_t c : lead)
-        if (best < 0 || t[c] < best_ms * (1.0 - kTuneMargin)) {
+        if (best < 0 || t2[c] < best_ms * (1.0 - kTuneMargin)) {
             best = (int)c;
-            best_ms = t[c];
+            best_ms = t2[c];
         }
     if (out) {
         out->candidates = (int32_t)cands.size();
@@ -855,17 +858,18 @@ int time_candidates(const std::vector<TuneCfg> &cands, Launch &&launch, hipStrea
         out->blocks_per_cu = cands[best].bpc;
         out->segments = cands[best].segs;
         out->best_ms = best_ms;
-        out->default_ms = std::min(default_first, t.empty() ? 0.0 : t[0]);
+        out->default_ms = t2.empty() ? 0.0 : t2[0];
     }
     return best;
 }
 
-gd_opts trial_opts(int solver) {
+gd_opts trial_opts(int solver, bool long_trial = false) {
     gd_opts o;
     std::memset(&o, 0, sizeof o);
     // enough passes that the sweeps, not init and exit, decide (Van Cittert
     // and steepest descent passes move a third to a half of a Krylov pass)
     o.max_iter = (solver == GD_VANCITTERT || solver == GD_STEEPEST_DESCENT) ? 10 : 4;
+    if (long_trial) o.max_iter *= 2;
     o.init = GD_INIT_UBAR;
     o.norm_ref = GD_REF_R0UBAR;
     o.tol = 0.0;
@@ -883,7 +887,7 @@ int tune_uniform(int solver, const gd_grid *g, const void *ubar, void *u, void *
     int rc = validate_grid(g);
     if (rc) return rc;
     if (solver < GD_VANCITTERT || solver > GD_STEEPEST_DESCENT) return fail(GD_EINVAL, "bad solver %d", solver);
-    const gd_opts o = trial_opts(solver);
+    const gd_opts o = trial_opts(solver), o2 = trial_opts(solver, true);
     std::vector<TuneCfg> cands;
     std::vector<int> rows = {0};
     if (g->ndim == 3 && !spec) rows = {0, 1, 2, 4};
@@ -920,8 +924,8 @@ int tune_uniform(int solver, const gd_grid *g, const void *ubar, void *u, void *
                 }
     // every candidate must launch; a shape the field cannot use falls back to
     // the default rule inside solve_uniform, so duplicates are harmless
-    auto launch = [&](const TuneCfg &c) {
-        return solve_uniform(solver, g, ubar, u, &o, work, wb, info, stream, &c, spec);
+    auto launch = [&](const TuneCfg &c, bool long_trial) {
+        return solve_uniform(solver, g, ubar, u, long_trial ? &o2 : &o, work, wb, info, stream, &c, spec);
     };
     const int best = time_candidates(cands, launch, (hipStream_t)stream, out);
     if (best < 0) return best;
@@ -1061,7 +1065,7 @@ int deconvolve_autotune(int32_t solver, const gd_grid *g, const void *ubar, void
 
 int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *list, int32_t count, void *work,
                               size_t wb, gd_info *info, void *stream, gd_tune_info *out) {
-    const gd_opts o = trial_opts(solver);
+    const gd_opts o = trial_opts(solver), o2 = trial_opts(solver, true);
     std::vector<TuneCfg> cands;
     for (int bp : kBpcCands)
         for (int t : kTpwCands)
@@ -1076,8 +1080,8 @@ int deconvolve_batch_autotune(int32_t solver, int32_t dtype, const gd_instance *
                         c.bpc = bp;
                         cands.push_back(c);
                     }
-    auto launch = [&](const TuneCfg &c) {
-        return solve_batch(solver, dtype, list, count, &o, work, wb, info, stream, &c);
+    auto launch = [&](const TuneCfg &c, bool long_trial) {
+        return solve_batch(solver, dtype, list, count, long_trial ? &o2 : &o, work, wb, info, stream, &c);
     };
     const int best = time_candidates(cands, launch, (hipStream_t)stream, out);
     if (best < 0) return best;
