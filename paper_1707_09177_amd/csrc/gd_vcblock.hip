@@ -55,8 +55,13 @@ struct alignas(128) VState {
     double r_ref, r0, r_last;
     int32_t iters, status, done, redo;  // redo: passes of the sweep to recompute
     int32_t parity;                     // buffer set holding the current u, r
-    uint32_t pad;
+    int32_t next;                       // passes of the field's next sweep
+    int32_t nshort;                     // sweeps shortened to a predicted stop so far
 };
+
+// Sweeps a field may shorten to the passes its residual's decay rate predicts
+// to the tolerance (the host launches this many sweeps beyond max_iter / K).
+constexpr int kShortSweeps = 2;
 
 // fields still iterating (the sweeps' fast exit) and fields with a sweep to recompute
 struct alignas(128) Global {
@@ -251,6 +256,8 @@ __global__ __launch_bounds__(256) void k_vcb_init_reduce(Args A) {
     st->r0 = r0;
     st->r_ref = r_ref;
     st->r_last = r0;
+    st->next = A.steps;
+    st->nshort = 0;
     int status = GD_MAXITER, done;
     if (!isfinite(r_ref)) {
         status = GD_NONFINITE;
@@ -293,7 +300,7 @@ __global__ __launch_bounds__(256) void k_vcb_sweep(Args A) {
             __syncthreads();
             if (threadIdx.x == 0) {
                 skip = REDO ? st->redo == 0 : st->done != 0;
-                passes = REDO ? st->redo : A.steps;
+                passes = REDO ? st->redo : st->next;
                 par = st->parity;
             }
             __syncthreads();
@@ -414,7 +421,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_vcb_march(Args A) {
             __syncthreads();
             if (tid == 0) {
                 skip = REDO ? st->redo == 0 : st->done != 0;
-                passes = REDO ? st->redo : A.steps;
+                passes = REDO ? st->redo : st->next;
                 par = st->parity;
             }
             __syncthreads();
@@ -559,7 +566,7 @@ __global__ __launch_bounds__(256) void k_vcb_sweep_reduce(Args A) {
     const int64_t f = blockIdx.x;
     VState *st = A.st + f;
     if (REDO ? st->redo == 0 : st->done != 0) return;  // uniform across the workgroup
-    const int steps = REDO ? st->redo : A.steps;
+    const int steps = REDO ? st->redo : st->next;
     double tot[kMaxK];
     for (int j = 0; j < steps; ++j) tot[j] = field_sum(A.part + f * A.pslots * (kMaxK + 1), A.stiles, j, red);
     if (threadIdx.x != 0) return;
@@ -593,8 +600,25 @@ __global__ __launch_bounds__(256) void k_vcb_sweep_reduce(Args A) {
         }
     }
     st->iters = n0 + steps;
-    st->r_last = sqrt(tot[steps - 1]);
+    const double r_now = sqrt(tot[steps - 1]);
+    const double r_prev = steps >= 2 ? sqrt(tot[steps - 2]) : st->r_last;
+    st->r_last = r_now;
     st->parity = 1 - p;
+    // The next sweep runs all A.steps passes or, at most kShortSweeps times
+    // per field, the passes the last decay rate predicts to the tolerance
+    // (Algorithm 1's residual shrinks by a nearly constant factor per pass
+    // once its slowest mode dominates), so that the stop falls on a sweep's
+    // last pass and nothing is recomputed.  A wrong prediction costs a short
+    // sweep or a recomputation; the stopping rule itself is unchanged.
+    int nx = A.steps;
+    if (A.tol > 0.0 && st->nshort < kShortSweeps && r_now > 0.0 && r_now < r_prev) {
+        const double need = log(A.tol * st->r_ref / r_now) / log(r_now / r_prev);
+        if (need >= 0.0 && need < (double)A.steps) {
+            nx = max(1, (int)ceil(need));
+            ++st->nshort;
+        }
+    }
+    st->next = min(nx, A.max_iter - st->iters);
 }
 
 // Exit: the true residual ||ubar - G u|| of the final u, the info record, and
@@ -782,16 +806,20 @@ int run(const gd_grid *g, const void *ubar, void *u, const gd_opts *o, void *wor
             else hipLaunchKernelGGL((k_vcb_sweep<T, NDIM, false>), dim3(sweep_blocks), dim3(256), 0, st, A);
         }
     };
+    // passes per sweep (a field's own count, at most this, is set by the
+    // reduce kernels)
+    A.steps = std::min(S::K, o->max_iter);
     hipLaunchKernelGGL(k_vcb_prep, dim3((unsigned)((g->batch + 255) / 256)), dim3(256), 0, st, A.st, A.glob, g->batch);
     const dim3 per_field((unsigned)g->batch);
     hipLaunchKernelGGL((k_vcb_init<T, NDIM>), dim3((unsigned)nblk), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_vcb_init_reduce, per_field, dim3(256), 0, st, A);
-    for (int done = 0; done < o->max_iter; done += S::K) {
-        A.steps = std::min(S::K, o->max_iter - done);
+    // enough sweeps for max_iter passes, also for a field that shortened
+    // kShortSweeps of them (each runs at least one pass)
+    const int nsweeps = o->max_iter > 0 ? (o->max_iter + S::K - 1) / S::K + kShortSweeps : 0;
+    for (int k = 0; k < nsweeps; ++k) {
         launch_sweep(false);
         hipLaunchKernelGGL(k_vcb_sweep_reduce<false>, per_field, dim3(256), 0, st, A);
     }
-    A.steps = 0;
     launch_sweep(true);
     hipLaunchKernelGGL(k_vcb_sweep_reduce<true>, per_field, dim3(256), 0, st, A);
     // norms above are plain sums; the inner product carries the spacing weight h^d

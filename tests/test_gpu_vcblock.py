@@ -129,3 +129,25 @@ def test_bench_size_converges_like_the_oracle():
     for gi, oi in zip(info, oinf):
         assert gi["status_name"] == "CONVERGED" and abs(gi["iters"] - oi["iters"]) <= 1 + oi["replaced"]
         assert gi["r_true"] <= 2e-6 * gi["r_ref"]
+
+
+@pytest.mark.parametrize("max_iter", [9, 10, 12, 17, 300])
+@pytest.mark.parametrize("shape", [(130, 300), (20, 24, 36)])
+def test_predicted_sweep_lengths_match_oracle(shape, max_iter):
+    """A sweep is shortened to the passes the residual's last decay rate
+    predicts to the tolerance.  On random fields the decay slows down, so
+    predictions fall short and a field takes short sweeps, or runs into
+    max_iter within one: pass counts, statuses, histories and u match the
+    oracle."""
+    nd = len(shape)
+    ub = oracle.filter(rand((3,) + shape, 80), nd)
+    tol = 2e-2
+    want, winf, whist = oracle.solve("vc", ub, nd, max_iter, tol=tol)
+    got, ginf, ghist = run(ub, nd, max_iter, torch.float64, tol=tol)
+    for gi, wi in zip(ginf, winf):
+        assert gi["iters"] == wi["iters"] and gi["status_name"] == wi["status_name"], (gi, wi)
+    for e in rel_l2_per_field(got, want, nd):
+        assert e <= 1e-11, e
+    for b in range(ub.shape[0]):
+        n = winf[b]["iters"]
+        np.testing.assert_allclose(ghist[b][:n + 1], whist[b][:n + 1], rtol=1e-11, atol=1e-300)
