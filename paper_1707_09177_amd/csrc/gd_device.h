@@ -490,8 +490,10 @@ __device__ __forceinline__ void march_pair(const Geo &g, int64_t lt, const Op &o
         eo[h] = (uint32_t)((rowoff[h] + xe) * (int64_t)sizeof(T));
     }
 
-    T raw[3][NI][VW], rawe[3][NI];
-    auto load_in = [&](int64_t mw) {
+    // raw stencil inputs of two planes in flight (double-buffered: plane m + 2
+    // is loaded while plane m is filtered)
+    T rawA[3][NI][VW], raweA[3][NI], rawB[3][NI][VW], raweB[3][NI];
+    auto load_in = [&](int64_t mw, T (&raw)[3][NI][VW], T (&rawe)[3][NI]) {
 #pragma unroll
         for (int f = 0; f < Op::NI; ++f) {
             const T *pb = op.in[f] + mw * g.plane;
@@ -524,8 +526,9 @@ __device__ __forceinline__ void march_pair(const Geo &g, int64_t lt, const Op &o
 #pragma unroll
             for (int k = 0; k < VW; ++k) co[r][f][k] = T(0);
 
-    load_in(wrapm(p.m0 - 1));
-    for (int64_t m = p.m0 - 1; m <= p.m1; ++m) {
+    // one step: filter plane m from `raw` (loaded two steps ago), then reuse
+    // its registers for plane m + 2 (the last steps reload plane m1, from cache)
+    auto step = [&](int64_t m, T (&raw)[3][NI][VW], T (&rawe)[3][NI]) {
         C sm[3][VW], se[3], sr[3];
 #pragma unroll
         for (int h = 0; h < 3; ++h) {
@@ -540,7 +543,7 @@ __device__ __forceinline__ void march_pair(const Geo &g, int64_t lt, const Op &o
             sr[h] = full ? se[h] : dpp_shift<kDppWaveShl1>(se[h]);
         }
         __builtin_amdgcn_sched_barrier(0);
-        load_in(wrapm(m < p.m1 ? m + 1 : m));
+        load_in(wrapm(m + 2 <= p.m1 ? m + 2 : p.m1), raw, rawe);
 
         // x-filter the three rows (DPP across the whole wave; the halves'
         // edge lanes take their own loads instead)
@@ -593,6 +596,14 @@ __device__ __forceinline__ void march_pair(const Geo &g, int64_t lt, const Op &o
             for (int k = 0; k < VW; ++k) S1[r][k] = sm[r][k];
         __builtin_amdgcn_sched_barrier(0);
         load_out(m < p.m0 ? p.m0 : (m < p.m1 ? m : p.m1 - 1));
+    };
+
+    // planes m0 - 1 .. m1 (the two halo planes included), two in flight
+    load_in(wrapm(p.m0 - 1), rawA, raweA);
+    load_in(wrapm(p.m0 <= p.m1 ? p.m0 : p.m1), rawB, raweB);
+    for (int64_t m = p.m0 - 1; m <= p.m1; m += 2) {
+        step(m, rawA, raweA);
+        if (m + 1 <= p.m1) step(m + 1, rawB, raweB);
     }
 }
 
