@@ -362,15 +362,17 @@ def closure_accesses(ndim: int) -> int:
     return 2 * ndim + ndim * (ndim + 1) // 2
 
 
-def main_closure(args, w, torch, gd, dev):
-    """Deconvolve the filtered velocity, then time the closure stress kernel
-    (and the whole chain: solve of every component + closure)."""
+def closure_measure(w, torch, gd, dev, steps, warmup, tune):
+    """Deconvolve the filtered velocity (BiCGSTAB to 1e-6), then time the
+    closure stress kernel and the whole chain (solve of every component +
+    closure).  Returns the timings, the algorithmic bytes and the tensors."""
     nd = w["ndim"]
     u32, ubar = make_inputs(w, torch, gd, dev)
+    del u32
     vel = ubar.view(-1, nd, *ubar.shape[1:])                 # (fields, components, grid)
     d = gd.Deconvolver(ubar.shape, nd, ubar.dtype, "bicgstab")
     ustar = torch.empty_like(ubar)
-    if not args.no_tune:
+    if tune:
         gd.autotune("bicgstab", ubar, ndim=nd, out=ustar)
     info = d.solve(ubar, 500, 1e-6, out=ustar).info()
     us = ustar.view_as(vel)
@@ -378,7 +380,7 @@ def main_closure(args, w, torch, gd, dev):
     stream = torch.cuda.current_stream()
 
     def timed(fn, reps):
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
@@ -390,13 +392,23 @@ def main_closure(args, w, torch, gd, dev):
         ms = [a.elapsed_time(b) for a, b in evs]
         return float(np.mean(ms)), float(np.min(ms))
 
-    ms_cl, ms_cl_min = timed(lambda: gd.closure_stress(vel, us, nd, out=tau), args.steps)
+    ms_cl, ms_cl_min = timed(lambda: gd.closure_stress(vel, us, nd, out=tau), steps)
     ms_chain, _ = timed(lambda: (d.solve(ubar, 500, 1e-6, out=ustar), gd.closure_stress(vel, us, nd, out=tau)),
-                        max(3, args.steps // 4))
+                        max(3, steps // 4))
     npts = int(np.prod(vel.shape[2:])) * vel.shape[0]             # grid points of the velocity batch
-    itemsize = ubar.element_size()
-    algo = npts * itemsize * closure_accesses(nd)
+    algo = npts * ubar.element_size() * closure_accesses(nd)
     gbs = algo / (ms_cl * 1e-3) / 1e9
+    return dict(ms_cl=ms_cl, ms_cl_min=ms_cl_min, ms_chain=ms_chain, npts=npts, algo=algo, gbs=gbs, info=info,
+                vel=vel, us=us)
+
+
+def main_closure(args, w, torch, gd, dev):
+    """Deconvolve the filtered velocity, then time the closure stress kernel
+    (and the whole chain: solve of every component + closure)."""
+    nd = w["ndim"]
+    r = closure_measure(w, torch, gd, dev, args.steps, args.warmup, not args.no_tune)
+    ms_cl, ms_cl_min, ms_chain, npts, algo, gbs, info, vel, us = (
+        r[k] for k in ("ms_cl", "ms_cl_min", "ms_chain", "npts", "algo", "gbs", "info", "vel", "us"))
     out = {
         "metric": "closure-stress grid points/s (all tau_ij pairs); % HBM roofline", "value": npts / (ms_cl * 1e-3),
         "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_cl,
@@ -1020,6 +1032,8 @@ def main():
         out["germano2d"] = extra_germano(args, WORKLOADS["germano2d"], torch, gd, dev)
         torch.cuda.empty_cache()
         out["c5fwd"] = extra_forward(args, WORKLOADS["c5fwd"], torch, gd, dev)
+        torch.cuda.empty_cache()
+        out["closure3d"] = extra_closure(args, WORKLOADS["closure3d"], torch, gd, dev)
     print(json.dumps(out))
 
 
@@ -1090,6 +1104,19 @@ def extra_germano(args, w, torch, gd, dev):
     del ubar
     return {"workload": w["desc"], "solvers": r, "ms": r["bicgstab"]["ms"],
             "call_hbm_frac": r["bicgstab"]["call_hbm_frac"], "vs_vancittert": r["vc"]["ms"] / r["bicgstab"]["ms"]}
+
+
+def extra_closure(args, w, torch, gd, dev):
+    """The closure stress kernel after the velocity's deconvolution, reported
+    as an extra key."""
+    r = closure_measure(w, torch, gd, dev, args.steps, args.warmup, not args.no_tune)
+    traffic = measured_traffic(w["key"], CLOSURE_TRAFFIC_FILE, CLOSURE_SOURCES)
+    out = {"workload": w["desc"], "points": r["npts"], "ms": r["ms_cl"], "algorithmic_GBs": r["gbs"],
+           "hbm_frac": r["gbs"] / HBM_PEAK_GBS, "traffic": traffic, "traffic_frac": traffic_rate(traffic, r["ms_cl"])[1],
+           "chain_ms": r["ms_chain"], "closure_share": r["ms_cl"] / r["ms_chain"],
+           "solve_iters": sorted({i["iters"] for i in r["info"]})}
+    del r
+    return out
 
 
 def extra_forward(args, w, torch, gd, dev):
